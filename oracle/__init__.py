@@ -1,0 +1,236 @@
+"""CPU oracle for collision-affording point trees.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports or
+links this package, and this package never imports the product.
+
+The arithmetic lives in `capt_oracle.c` (plain C, float64 where the paper does
+not fix the precision, float32 for the collision predicate the GPU must match
+bit for bit); this module compiles it with gcc and marshals numpy arrays.
+
+Functions and what they follow:
+  brute_f32        plain definition of the collision answer (Alg. 3's test
+                   against every point of the cloud; Lemma 1's right-hand side)
+  brute_f64        the same test in float64, with the relative margin
+                   |d^2 - r^2| / r^2 of the closest-to-boundary point
+  clearance_f64    nearest-point distance clamped at r_max, minus r, and its
+                   gradient (not in the paper; defined for the differentiable
+                   query)
+  build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning
+  query            CollisionCheck (Alg. 3, Sec. IV-D) on a tree given as arrays
+  morton_key       Z-order key (Sec. II-B, Sec. IV-C)
+  filter           Filter (Alg. 2, Sec. IV-C)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "capt_oracle.c")
+_LIB = os.path.join(_HERE, "libcapt_oracle.so")
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+          "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+_lib = None
+
+
+def compile_library(force: bool = True) -> str:
+    """Compile the oracle with gcc (contraction off, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            compile_library(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, f32 = C.c_int64, C.c_int32, C.c_float
+        sig = {
+            "orc_sqdist_f32": (f32, [P, P]),
+            "orc_brute_f32": (None, [P, i64, P, i64, i32, P]),
+            "orc_brute_f64": (None, [P, i64, P, i64, P, P]),
+            "orc_clearance_f64": (None, [P, i64, P, i64, f32, P, P, P]),
+            "orc_build": (P, [P, i64, f32, f32, C.c_int]),
+            "orc_tree_dims": (None, [P, P, P, P, P]),
+            "orc_tree_copy": (None, [P, P, P, P, P, P, P, P]),
+            "orc_tree_free": (None, [P]),
+            "orc_query": (None, [i64, i32, P, P, P, P, P, i64, P, P, P, P]),
+            "orc_query_serial": (None, [i64, i32, P, P, P, P, P, i64, i32, P]),
+            "orc_morton_key": (C.c_uint64, [P, C.c_int]),
+            "orc_morton_grid": (None, [P, i64, P, P]),
+            "orc_morton_cell": (None, [P, P, C.c_double, P]),
+            "orc_filter": (i64, [P, i64, f32, C.c_int, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a, cols):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    assert a.ndim == 2 and a.shape[1] == cols, a.shape
+    return a
+
+
+def sqdist_f32(a, b) -> np.float32:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    return np.float32(_load().orc_sqdist_f32(_p(a), _p(b)))
+
+
+def brute_f32(points, spheres, group: int = 1) -> np.ndarray:
+    pts, sph = _f32(points, 3), _f32(spheres, 4)
+    assert len(sph) % group == 0
+    out = np.zeros(len(sph) // group, dtype=np.uint8)
+    _load().orc_brute_f32(_p(pts), len(pts), _p(sph), len(sph), group, _p(out))
+    return out
+
+
+def brute_f64(points, spheres):
+    pts, sph = _f32(points, 3), _f32(spheres, 4)
+    out = np.zeros(len(sph), dtype=np.uint8)
+    margin = np.zeros(len(sph), dtype=np.float64)
+    _load().orc_brute_f64(_p(pts), len(pts), _p(sph), len(sph), _p(out), _p(margin))
+    return out, margin
+
+
+def clearance_f64(points, spheres, r_max: float):
+    pts, sph = _f32(points, 3), _f32(spheres, 4)
+    m = len(sph)
+    clr = np.zeros(m, dtype=np.float64)
+    wit = np.zeros(m, dtype=np.int32)
+    grad = np.zeros((m, 3), dtype=np.float64)
+    _load().orc_clearance_f64(_p(pts), len(pts), _p(sph), m, np.float32(r_max),
+                              _p(clr), _p(wit), _p(grad))
+    return clr, wit, grad
+
+
+@dataclass
+class Tree:
+    """A CAPT as plain arrays (Sec. IV-A): n real points padded to N = 2^D."""
+    n: int
+    N: int
+    D: int
+    r_min: float
+    r_max: float
+    T: np.ndarray        # float32 [N-1], Eytzinger order
+    rep: np.ndarray      # int32 [N], representative per leaf (>= n: padding)
+    cell: np.ndarray     # float32 [N, 6] lo xyz, hi xyz
+    aabb: np.ndarray     # float32 [N, 6] lo xyz, hi xyz of the stored set
+    pruned: np.ndarray   # uint8 [N]
+    off: np.ndarray      # int64 [N+1]
+    idx: np.ndarray      # int32 [off[N]], each set sorted by original index
+
+    def set_of(self, leaf: int) -> np.ndarray:
+        return self.idx[self.off[leaf]:self.off[leaf + 1]]
+
+
+def build_tree(points, r_min: float, r_max: float, prune: bool = True) -> Tree:
+    pts = _f32(points, 3)
+    lib = _load()
+    h = lib.orc_build(_p(pts), len(pts), np.float32(r_min), np.float32(r_max), int(prune))
+    try:
+        n, N, D, tot = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        lib.orc_tree_dims(h, C.byref(n), C.byref(N), C.byref(D), C.byref(tot))
+        N_ = N.value
+        T = np.zeros(max(N_ - 1, 0), dtype=np.float32)
+        rep = np.zeros(N_, dtype=np.int32)
+        cell = np.zeros((N_, 6), dtype=np.float32)
+        aabb = np.zeros((N_, 6), dtype=np.float32)
+        pruned = np.zeros(N_, dtype=np.uint8)
+        off = np.zeros(N_ + 1, dtype=np.int64)
+        idx = np.zeros(max(tot.value, 1), dtype=np.int32)
+        lib.orc_tree_copy(h, _p(T) if N_ > 1 else None, _p(rep), _p(cell), _p(aabb),
+                          _p(pruned), _p(off), _p(idx))
+    finally:
+        lib.orc_tree_free(h)
+    return Tree(n.value, N_, D.value, float(np.float32(r_min)), float(np.float32(r_max)),
+                T, rep, cell, aabb, pruned, off, idx[:tot.value])
+
+
+def query(N: int, D: int, T, aabb, off, setxyz, spheres):
+    """CollisionCheck (Alg. 3) per sphere on a tree given as arrays.  Returns
+    (hit u8 [m], leaf i32 [m], aabb_rejected u8 [m], scanned i32 [m])."""
+    sph = _f32(spheres, 4)
+    m = len(sph)
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    aabb = np.ascontiguousarray(aabb, dtype=np.float32).reshape(-1, 6)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    setxyz = np.ascontiguousarray(setxyz, dtype=np.float32).reshape(-1, 3)
+    hit = np.zeros(m, dtype=np.uint8)
+    leaf = np.zeros(m, dtype=np.int32)
+    rej = np.zeros(m, dtype=np.uint8)
+    scanned = np.zeros(m, dtype=np.int32)
+    _load().orc_query(N, D, _p(T) if len(T) else None, _p(aabb), _p(off),
+                      _p(setxyz) if len(setxyz) else None, _p(sph), m,
+                      _p(hit), _p(leaf), _p(rej), _p(scanned))
+    return hit, leaf, rej, scanned
+
+
+def query_tree(tree: Tree, points, spheres):
+    """Alg. 3 on an oracle tree; set points are stored in sorted-index order."""
+    pts = _f32(points, 3)
+    return query(tree.N, tree.D, tree.T, tree.aabb, tree.off, pts[tree.idx], spheres)
+
+
+def query_serial(N: int, D: int, T, aabb, off, setxyz, spheres, group: int) -> np.ndarray:
+    """Single-threaded Alg. 3 with per-configuration early exit."""
+    sph = _f32(spheres, 4)
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    aabb = np.ascontiguousarray(aabb, dtype=np.float32).reshape(-1, 6)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    setxyz = np.ascontiguousarray(setxyz, dtype=np.float32).reshape(-1, 3)
+    out = np.zeros(len(sph) // group, dtype=np.uint8)
+    _load().orc_query_serial(N, D, _p(T) if len(T) else None, _p(aabb), _p(off),
+                             _p(setxyz) if len(setxyz) else None, _p(sph), len(sph),
+                             group, _p(out))
+    return out
+
+
+def morton_key(q, perm: int) -> int:
+    q = np.ascontiguousarray(q, dtype=np.uint32)
+    return int(_load().orc_morton_key(_p(q), perm))
+
+
+def morton_grid(points):
+    pts = _f32(points, 3)
+    lo = np.zeros(3, dtype=np.float32)
+    scale = C.c_double()
+    _load().orc_morton_grid(_p(pts), len(pts), _p(lo), C.byref(scale))
+    return lo, scale.value
+
+
+def morton_cell(p, lo, scale: float) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    q = np.zeros(3, dtype=np.uint32)
+    _load().orc_morton_cell(_p(p), _p(lo), scale, _p(q))
+    return q
+
+
+def filter(points, r_filter: float, npass: int = 6):  # noqa: A001
+    """Filter (Alg. 2).  Returns (kept original indices in final order,
+    counts after each pass)."""
+    pts = _f32(points, 3)
+    out = np.zeros(max(len(pts), 1), dtype=np.int32)
+    counts = np.zeros(npass, dtype=np.int64)
+    k = _load().orc_filter(_p(pts), len(pts), np.float32(r_filter), npass, _p(out), _p(counts))
+    return out[:k].copy(), counts
