@@ -1,0 +1,241 @@
+/*
+ * capt.h - C ABI of the MI355X collision-affording point tree (CAPT) library.
+ *
+ * A CAPT (Ramsey, Kingston, Thomason, Kavraki, "Collision-Affording Point
+ * Trees", arXiv 2406.02807) answers "does a sphere of radius r in
+ * [r_min, r_max] touch any point of a 3-D point cloud?" exactly, by descending
+ * an implicit k-d tree to one leaf cell and scanning that leaf's affordance
+ * set: every cloud point that a sphere of radius <= r_max centred anywhere in
+ * the cell could touch (Sec. IV-A, Lemma 1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers (HIP global memory of the current device)
+ *    unless the comment says "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is ordered on it; entry points return without waiting for it
+ *    unless the comment says "synchronises".
+ *  - Points are float32 [n][3] (x, y, z) row-major.  Spheres are float32
+ *    [m][4] (x, y, z, r) row-major.
+ *  - The caller owns every input and output buffer.  A forest owns its own
+ *    device memory until capt_destroy.
+ *  - Nothing throws across the ABI.  On failure an entry point returns a
+ *    non-zero capt_status, writes no output, and capt_last_error() describes
+ *    the failure (thread-local).  Host-side argument checks run before any
+ *    device work is queued.
+ *  - The collision predicate is float32 and fixed: a sphere (x, r) touches p
+ *    iff ((dx*dx + dy*dy) + dz*dz) <= r*r with dx = x_x - p_x etc., each
+ *    operation rounded to nearest-even, no fused multiply-add.  Answers equal
+ *    a brute-force evaluation of that predicate over the whole cloud bit for
+ *    bit, for every radius in [r_min, r_max] (Lemma 1).
+ */
+#ifndef CAPT_H
+#define CAPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct capt_forest_s *capt_forest;   /* immutable after build or import */
+typedef int32_t capt_status;
+
+#define CAPT_OK           0
+#define CAPT_EINVAL       1   /* bad argument, non-finite cloud point, bad blob */
+#define CAPT_ENOMEM       2   /* device or host allocation failed */
+#define CAPT_EHIP         3   /* a HIP runtime call or kernel failed */
+#define CAPT_ERADIUS      4   /* a query radius lies outside [r_min, r_max] (checked mode) */
+#define CAPT_EPRUNED      5   /* clearance on a forest with r_min-pruned leaves */
+#define CAPT_EUNSUPPORTED 6   /* size beyond the library's limits */
+
+/* Build flags */
+#define CAPT_NO_PRUNE     0x1u  /* never apply r_min pruning (Sec. IV-B) */
+/* Query flags */
+#define CAPT_CHECK_RADII  0x2u  /* validate radii first (one device-to-host sync) */
+#define CAPT_PER_CLOUD    0x4u  /* forests: one launch per cloud, not one batched launch */
+#define CAPT_NO_GRAPH     0x8u  /* forests: launch the batched kernel directly, no hipGraph */
+
+/*
+ * Filter (Alg. 2, Sec. IV-C).  For each of the six axis permutations, in the
+ * order xyz, xzy, yxz, yzx, zxy, zyx: stable-sort the current points along the
+ * Z-order (Morton) curve of that permutation, then keep a point iff its
+ * float32 squared distance to the last kept point exceeds r_filter^2.  The
+ * Morton grid is 2^21 cells per axis over the cubic bounding box of the input
+ * (lower corner = float32 minimum, cell = largest extent / 2^21).  Key bit
+ * 3b + (2 - j) holds bit b of the cell coordinate on the permutation's j-th
+ * axis.
+ *   xyz        [n][3] input points (finite)
+ *   r_filter   >= 0, finite
+ *   out_xyz    [n][3] capacity; receives the kept points, in final curve
+ *              order, bitwise equal to the input coordinates
+ *   out_index  [n] capacity or NULL; original index of each kept point
+ *   n_out      host; number of kept points
+ * Synchronises on `stream` once at the end to read n_out.  Scratch memory is
+ * taken from the allocator (capt_set_allocator) and released before return.
+ */
+capt_status capt_filter(const float *xyz, int64_t n, float r_filter,
+                        float *out_xyz, int32_t *out_index, int64_t *n_out,
+                        void *stream);
+
+/*
+ * Construct (Alg. 1, Sec. IV-A/B) for `ncloud` independent clouds.
+ *   xyz        [sum n_c][3] points of all clouds back to back (finite)
+ *   cloud_off  host [ncloud + 1]; cloud c is xyz[cloud_off[c] .. cloud_off[c+1])
+ *              (non-decreasing, cloud_off[0] = 0; empty clouds allowed)
+ *   r_min      0 <= r_min <= r_max, finite; r_min = 0 disables pruning
+ *   r_max      > 0, finite
+ *   flags      CAPT_NO_PRUNE or 0
+ *   out        host; receives the forest
+ * Each cloud of n points is padded with points at +inf to N = 2^D >= n
+ * (Sec. IV-A).  Node i at depth d splits on axis d mod 3 at the coordinate of
+ * the lower median under the order (coordinate, original index); points at or
+ * below the value go left, children are 2i+1 and 2i+2 (Eytzinger order).  A
+ * leaf's affordance set holds every real point whose float64 distance to the
+ * leaf's closed cell is <= r_max (1 + 2^-20); when r_min > 0, the cell is
+ * bounded and the float64 squared distance from the leaf's representative to
+ * the cell's farthest corner is <= r_min^2 (1 - 2^-18), the set is just the
+ * representative (Sec. IV-B).  Each leaf also stores the float32 bounding box of its set.
+ * Synchronises on `stream` once (to size the affordance sets).  Non-finite
+ * points give CAPT_EINVAL and no forest.
+ */
+capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                       float r_min, float r_max, uint32_t flags, void *stream,
+                       capt_forest *out);
+
+/*
+ * CollisionCheck (Alg. 3, Sec. IV-D) with configuration-level early exit.
+ *   f          forest from capt_build / capt_import
+ *   spheres    [M][4]; the spheres of cloud c are
+ *              spheres[query_off[c] .. query_off[c+1])
+ *   query_off  host [ncloud + 1], non-decreasing, each range a multiple of
+ *              `group`
+ *   group      1 .. 1024 spheres per configuration
+ *   out        [M / group] bytes; out[k] = 1 iff some sphere of configuration
+ *              k touches its cloud, else 0
+ *   flags      CAPT_CHECK_RADII, CAPT_PER_CLOUD, CAPT_NO_GRAPH
+ * Radii must lie in [r_min, r_max] of the forest (Lemma 1); outside it the
+ * answer is unspecified, or CAPT_ERADIUS with CAPT_CHECK_RADII.  Non-finite
+ * centres give 0.  A forest with more than one cloud is queried with one
+ * persistent launch over a cost-sorted tile queue, replayed from a cached
+ * hipGraph when `spheres`, `out`, `query_off` and `group` repeat.
+ */
+capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *query_off,
+                          int32_t group, uint8_t *out, uint32_t flags, void *stream);
+
+/*
+ * Clearance of each sphere: c = min(d, r_max) - r, with d the float32
+ * distance from the centre to the nearest point of the sphere's leaf
+ * affordance set (equal to the nearest point of the whole cloud whenever
+ * d < r_max, by Lemma 1 case 1).  witness = original index of that point
+ * (smallest index on ties), or -1 when d >= r_max.  The forest must have no
+ * pruned leaf (build it with CAPT_NO_PRUNE or r_min = 0), else CAPT_EPRUNED.
+ *   spheres    [M][4];  query_off  host [ncloud + 1]
+ *   clearance  [M] float32;  witness  [M] int32
+ */
+capt_status capt_clearance(capt_forest f, const float *spheres, const int64_t *query_off,
+                           float *clearance, int32_t *witness, void *stream);
+
+/*
+ * Backward of capt_clearance: for each sphere,
+ *   grad_spheres[s] = (g * (x - p*) / |x - p*|, -g)   if witness >= 0 and x != p*
+ *                     (0, 0, 0, -g)                    otherwise
+ * with g = grad_clearance[s] and p* the witness point of its cloud.
+ *   witness       [M] from capt_clearance
+ *   grad_clearance [M] float32
+ *   grad_spheres  [M][4] float32 (d/dx, d/dy, d/dz, d/dr)
+ */
+capt_status capt_clearance_backward(capt_forest f, const float *spheres,
+                                    const int64_t *query_off, const int32_t *witness,
+                                    const float *grad_clearance, float *grad_spheres,
+                                    void *stream);
+
+/* Release a forest's device memory (waits for the device first).  NULL is a no-op. */
+void capt_destroy(capt_forest f);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *capt_last_error(void);
+
+/*
+ * Per-cloud sizes of a forest (host outputs, any may be NULL).
+ *   n: real points; D: depth (N = 2^D leaves); set_total: stored set entries
+ *   (without alignment padding); pruned: pruned leaves; bytes: device bytes
+ */
+capt_status capt_forest_info(capt_forest f, int32_t cloud, int64_t *n, int32_t *D,
+                             int64_t *set_total, int64_t *pruned, int64_t *bytes);
+
+/*
+ * Export cloud `cloud` of a forest to a host blob, or import a one-cloud
+ * forest from one.  With host_blob == NULL, capt_export only writes the
+ * required size to *bytes.  Export synchronises.  Blob layout (little endian,
+ * every section starts at a multiple of 8 bytes):
+ *   header   uint32 magic 0x54504143 ("CAPT"), uint32 version 1,
+ *            int64 n, int64 N, int32 D, uint32 flags, float r_min, float r_max,
+ *            int64 set_total (S)
+ *   float    points [n][3]       the cloud as given to capt_build
+ *   float    T [N-1]             test sequence (Eytzinger order)
+ *   int32    rep [N]             representative index per leaf (>= n: padding)
+ *   float    aabb [N][6]         lo xyz, hi xyz of each stored set
+ *   uint8    pruned [N]
+ *   int64    set_off [N+1]       set of leaf l is entries set_off[l] .. set_off[l+1]
+ *   int32    set_idx [S]         original point indices in stored (scan) order
+ * capt_import checks sizes, ranges and that every AABB is the bounding box of
+ * its set (CAPT_EINVAL otherwise); it does not re-derive the sets.
+ */
+capt_status capt_export(capt_forest f, int32_t cloud, void *host_blob, size_t *bytes);
+capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_forest *out);
+
+/*
+ * Device memory hooks for forests and scratch.  alloc returns NULL on failure.
+ * Passing NULL for both restores hipMalloc / hipFree.  Not thread-safe with
+ * respect to concurrent entry points.
+ */
+capt_status capt_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                               void (*release)(void *ptr, void *stream, void *ctx),
+                               void *ctx);
+
+/*
+ * GPU brute force (the baseline of the benchmark): every sphere against every
+ * point of its cloud with the same predicate, one launch per cloud, one
+ * wavefront per configuration, exiting at the first hit.
+ *   xyz, cloud_off, ncloud as in capt_build; spheres, query_off, group, out
+ *   as in capt_collides.
+ */
+capt_status capt_bruteforce_collides(const float *xyz, const int64_t *cloud_off,
+                                     int32_t ncloud, const float *spheres,
+                                     const int64_t *query_off, int32_t group,
+                                     uint8_t *out, void *stream);
+
+/*
+ * Work accounting for one collision query (not on the hot path): per sphere,
+ * the leaf reached, whether the leaf AABB rejected it, and how many set
+ * entries a scan in stored order tests before its first hit (the whole set
+ * if none).  Any output may be NULL.
+ *   leaf [M] int32, rejected [M] uint8, scanned [M] int32
+ */
+capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t *query_off,
+                             int32_t *leaf, uint8_t *rejected, int32_t *scanned, void *stream);
+
+/*
+ * Launch shape of the batched collision kernel (chosen by the autotuner).
+ *   waves_per_group  wavefronts per workgroup (1 .. 16)
+ *   groups_per_cu    persistent workgroups per compute unit (1 .. 16)
+ *   tile_cfgs        configurations a workgroup takes per queue pop (1 .. 4096)
+ *   lds_levels       tree levels kept in LDS (0 .. 14)
+ * Zero fields keep their current value.  Applies to later calls.
+ */
+typedef struct {
+    int32_t waves_per_group;
+    int32_t groups_per_cu;
+    int32_t tile_cfgs;
+    int32_t lds_levels;
+} capt_tuning;
+
+capt_status capt_set_tuning(const capt_tuning *t);
+capt_status capt_get_tuning(capt_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAPT_H */

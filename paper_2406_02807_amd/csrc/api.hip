@@ -1,0 +1,597 @@
+// C ABI of the CAPT library: argument checks, error state, allocator hooks,
+// forest lifetime, import/export, and dispatch to the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "capt_internal.h"
+
+namespace capt {
+
+namespace {
+thread_local char g_err[512] = "";
+
+struct Allocator {
+    void *(*alloc)(size_t, void *, void *) = nullptr;
+    void (*release)(void *, void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_alloc;
+
+struct ApiGuard {
+    ApiGuard() { g_err[0] = 0; }
+};
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+capt_status hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return e == hipErrorOutOfMemory ? CAPT_ENOMEM : CAPT_EHIP;
+}
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    if (g_alloc.alloc) return g_alloc.alloc(bytes, s, g_alloc.ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (!p) return;
+    if (g_alloc.release) {
+        g_alloc.release(p, s, g_alloc.ctx);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+const DeviceInfo &device_info() {
+    static DeviceInfo info;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return;
+        info.cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+        info.lds_per_block = p.sharedMemPerBlock > 0 ? (int)p.sharedMemPerBlock : 65536;
+        if (info.lds_per_block > 65536) info.lds_per_block = 65536;
+    });
+    return info;
+}
+
+}  // namespace capt
+
+using namespace capt;
+
+namespace {
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+capt_status check_offsets(const int64_t *off, int32_t count, const char *name) {
+    if (!off) {
+        set_error("%s is NULL", name);
+        return CAPT_EINVAL;
+    }
+    if (off[0] != 0) {
+        set_error("%s[0] = %lld, expected 0", name, (long long)off[0]);
+        return CAPT_EINVAL;
+    }
+    for (int32_t c = 0; c < count; ++c)
+        if (off[c + 1] < off[c]) {
+            set_error("%s decreases at %d", name, c);
+            return CAPT_EINVAL;
+        }
+    return CAPT_OK;
+}
+
+capt_status check_queries(capt_forest f, const float *spheres, const int64_t *qoff, int32_t group) {
+    if (!f) {
+        set_error("forest is NULL");
+        return CAPT_EINVAL;
+    }
+    const int32_t nc = (int32_t)f->clouds.size();
+    capt_status st = check_offsets(qoff, nc, "query_off");
+    if (st) return st;
+    if (group < 1 || group > 1024) {
+        set_error("group = %d outside 1 .. 1024", group);
+        return CAPT_EINVAL;
+    }
+    for (int32_t c = 0; c < nc; ++c)
+        if ((qoff[c + 1] - qoff[c]) % group) {
+            set_error("query range of cloud %d (%lld spheres) is not a multiple of group %d", c,
+                      (long long)(qoff[c + 1] - qoff[c]), group);
+            return CAPT_EINVAL;
+        }
+    if (qoff[nc] > 0 && !spheres) {
+        set_error("spheres is NULL");
+        return CAPT_EINVAL;
+    }
+    if (qoff[nc] >= ((int64_t)1 << 40)) {
+        set_error("too many spheres");
+        return CAPT_EUNSUPPORTED;
+    }
+    return CAPT_OK;
+}
+
+void destroy_forest(capt_forest_s *f) {
+    if (!f) return;
+    (void)hipDeviceSynchronize();
+    free_plan(f->plan);
+    for (auto &c : f->clouds) free_cloud(c);
+    if (f->d_clouds) dev_free(f->d_clouds, nullptr);
+    delete f;
+}
+
+// ---- blob layout --------------------------------------------------------
+constexpr uint32_t BLOB_MAGIC = 0x54504143u;   // "CAPT"
+constexpr uint32_t BLOB_VERSION = 1;
+
+struct BlobHeader {
+    uint32_t magic;
+    uint32_t version;
+    int64_t n;
+    int64_t N;
+    int32_t D;
+    uint32_t flags;
+    float r_min;
+    float r_max;
+    int64_t set_total;
+};
+static_assert(sizeof(BlobHeader) == 48, "blob header is 48 bytes");
+
+inline size_t a8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+struct BlobLayout {
+    size_t pts, T, rep, aabb, pruned, off, idx, total;
+    BlobLayout(int64_t n, int64_t N, int64_t S) {
+        size_t o = a8(sizeof(BlobHeader));
+        pts = o;    o = a8(o + sizeof(float) * 3 * (size_t)n);
+        T = o;      o = a8(o + sizeof(float) * (size_t)(N - 1));
+        rep = o;    o = a8(o + sizeof(int32_t) * (size_t)N);
+        aabb = o;   o = a8(o + sizeof(float) * 6 * (size_t)N);
+        pruned = o; o = a8(o + (size_t)N);
+        off = o;    o = a8(o + sizeof(int64_t) * (size_t)(N + 1));
+        idx = o;    o = a8(o + sizeof(int32_t) * (size_t)S);
+        total = o;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *capt_last_error(void) { return g_err; }
+
+capt_status capt_set_allocator(void *(*alloc)(size_t, void *, void *), void (*release)(void *, void *, void *),
+                               void *ctx) {
+    ApiGuard g;
+    if ((alloc == nullptr) != (release == nullptr)) {
+        set_error("alloc and release must both be set or both be NULL");
+        return CAPT_EINVAL;
+    }
+    g_alloc.alloc = alloc;
+    g_alloc.release = release;
+    g_alloc.ctx = ctx;
+    return CAPT_OK;
+}
+
+capt_status capt_set_tuning(const capt_tuning *t) {
+    ApiGuard g;
+    if (!t) {
+        set_error("tuning is NULL");
+        return CAPT_EINVAL;
+    }
+    if (t->waves_per_group < 0 || t->waves_per_group > 16 || t->groups_per_cu < 0 || t->groups_per_cu > 16 ||
+        t->tile_cfgs < 0 || t->tile_cfgs > 4096 || t->lds_levels < 0 || t->lds_levels > 14) {
+        set_error("tuning value out of range");
+        return CAPT_EINVAL;
+    }
+    capt_tuning &cur = tuning();
+    if (t->waves_per_group) cur.waves_per_group = t->waves_per_group;
+    if (t->groups_per_cu) cur.groups_per_cu = t->groups_per_cu;
+    if (t->tile_cfgs) cur.tile_cfgs = t->tile_cfgs;
+    if (t->lds_levels) cur.lds_levels = t->lds_levels;
+    return CAPT_OK;
+}
+
+capt_status capt_get_tuning(capt_tuning *t) {
+    ApiGuard g;
+    if (!t) {
+        set_error("tuning is NULL");
+        return CAPT_EINVAL;
+    }
+    *t = tuning();
+    return CAPT_OK;
+}
+
+capt_status capt_filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, int32_t *out_index,
+                        int64_t *n_out, void *stream) {
+    ApiGuard g;
+    if (!n_out) {
+        set_error("n_out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (n < 0 || (n > 0 && (!xyz || !out_xyz))) {
+        set_error("bad cloud arguments (n = %lld)", (long long)n);
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(r_filter) || !(r_filter >= 0.0f)) {
+        set_error("r_filter = %g must be finite and >= 0", (double)r_filter);
+        return CAPT_EINVAL;
+    }
+    if (n >= ((int64_t)1 << 31)) {
+        set_error("cloud of %lld points exceeds 2^31", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    return filter(xyz, n, r_filter, out_xyz, out_index, n_out, (hipStream_t)stream);
+}
+
+capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
+                       uint32_t flags, void *stream, capt_forest *out) {
+    ApiGuard g;
+    if (!out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    *out = nullptr;
+    if (ncloud < 1) {
+        set_error("ncloud = %d must be >= 1", ncloud);
+        return CAPT_EINVAL;
+    }
+    capt_status st = check_offsets(cloud_off, ncloud, "cloud_off");
+    if (st) return st;
+    if (cloud_off[ncloud] > 0 && !xyz) {
+        set_error("xyz is NULL");
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(r_min) || !finite_f(r_max) || !(r_min >= 0.0f) || !(r_max > 0.0f) || r_min > r_max) {
+        set_error("radii r_min = %g, r_max = %g must satisfy 0 <= r_min <= r_max, r_max > 0", (double)r_min,
+                  (double)r_max);
+        return CAPT_EINVAL;
+    }
+    if (flags & ~CAPT_NO_PRUNE) {
+        set_error("unknown build flags 0x%x", flags);
+        return CAPT_EINVAL;
+    }
+    capt_forest_s *f = new (std::nothrow) capt_forest_s();
+    if (!f) {
+        set_error("host allocation failed");
+        return CAPT_ENOMEM;
+    }
+    st = build_forest(xyz, cloud_off, ncloud, r_min, r_max, flags, (hipStream_t)stream, f);
+    if (st) {
+        destroy_forest(f);
+        return st;
+    }
+    *out = f;
+    return CAPT_OK;
+}
+
+capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
+                          uint8_t *out, uint32_t flags, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, group);
+    if (st) return st;
+    if (flags & ~(CAPT_CHECK_RADII | CAPT_PER_CLOUD | CAPT_NO_GRAPH)) {
+        set_error("unknown query flags 0x%x", flags);
+        return CAPT_EINVAL;
+    }
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && !out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (M == 0) return CAPT_OK;
+    return collides(f, spheres, query_off, group, out, flags, (hipStream_t)stream);
+}
+
+capt_status capt_clearance(capt_forest f, const float *spheres, const int64_t *query_off, float *clearance,
+                           int32_t *witness, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, 1);
+    if (st) return st;
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && (!clearance || !witness)) {
+        set_error("clearance or witness is NULL");
+        return CAPT_EINVAL;
+    }
+    if (f->pruned_total > 0) {
+        set_error("forest has %lld pruned leaves; build with CAPT_NO_PRUNE or r_min = 0 for clearance",
+                  (long long)f->pruned_total);
+        return CAPT_EPRUNED;
+    }
+    if (M == 0) return CAPT_OK;
+    return clearance_fwd(f, spheres, query_off, clearance, witness, (hipStream_t)stream);
+}
+
+capt_status capt_clearance_backward(capt_forest f, const float *spheres, const int64_t *query_off,
+                                    const int32_t *witness, const float *grad_clearance, float *grad_spheres,
+                                    void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, 1);
+    if (st) return st;
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && (!witness || !grad_clearance || !grad_spheres)) {
+        set_error("witness, grad_clearance or grad_spheres is NULL");
+        return CAPT_EINVAL;
+    }
+    if (f->pruned_total > 0) {
+        set_error("forest has pruned leaves");
+        return CAPT_EPRUNED;
+    }
+    if (M == 0) return CAPT_OK;
+    return clearance_bwd(f, spheres, query_off, witness, grad_clearance, grad_spheres, (hipStream_t)stream);
+}
+
+void capt_destroy(capt_forest f) { destroy_forest(f); }
+
+capt_status capt_forest_info(capt_forest f, int32_t cloud, int64_t *n, int32_t *D, int64_t *set_total,
+                             int64_t *pruned, int64_t *bytes) {
+    ApiGuard g;
+    if (!f || cloud < 0 || cloud >= (int32_t)f->clouds.size()) {
+        set_error("bad forest or cloud index");
+        return CAPT_EINVAL;
+    }
+    const CloudHost &c = f->clouds[cloud];
+    if (n) *n = c.n;
+    if (D) *D = c.D;
+    if (set_total) *set_total = c.set_total;
+    if (pruned) *pruned = c.pruned;
+    if (bytes) *bytes = (int64_t)(c.fixed_bytes + c.sets_bytes);
+    return CAPT_OK;
+}
+
+capt_status capt_export(capt_forest f, int32_t cloud, void *host_blob, size_t *bytes) {
+    ApiGuard g;
+    if (!f || !bytes || cloud < 0 || cloud >= (int32_t)f->clouds.size()) {
+        set_error("bad forest, cloud index or bytes pointer");
+        return CAPT_EINVAL;
+    }
+    const CloudHost &c = f->clouds[cloud];
+    const BlobLayout L(c.n, c.N, c.set_total);
+    if (!host_blob) {
+        *bytes = L.total;
+        return CAPT_OK;
+    }
+    if (*bytes < L.total) {
+        set_error("blob buffer of %zu bytes is smaller than %zu", *bytes, L.total);
+        return CAPT_EINVAL;
+    }
+    char *B = static_cast<char *>(host_blob);
+    memset(B, 0, L.total);
+    BlobHeader h{BLOB_MAGIC, BLOB_VERSION, c.n, c.N, c.D, c.dev.flags, f->r_min, f->r_max, c.set_total};
+    memcpy(B, &h, sizeof h);
+    std::vector<Leaf> leaves((size_t)c.N);
+    std::vector<float> px((size_t)std::max<int64_t>(c.set_padded, 1)), py(px.size()), pz(px.size());
+    std::vector<int32_t> pidx(px.size());
+    if (c.n > 0) CAPT_HIP(hipMemcpy(B + L.pts, c.dev.pts, sizeof(float) * 3 * (size_t)c.n, hipMemcpyDeviceToHost));
+    if (c.N > 1) CAPT_HIP(hipMemcpy(B + L.T, c.dev.T, sizeof(float) * (size_t)(c.N - 1), hipMemcpyDeviceToHost));
+    CAPT_HIP(hipMemcpy(B + L.rep, c.rep, sizeof(int32_t) * (size_t)c.N, hipMemcpyDeviceToHost));
+    CAPT_HIP(hipMemcpy(B + L.pruned, c.pruned_flag, (size_t)c.N, hipMemcpyDeviceToHost));
+    CAPT_HIP(hipMemcpy(leaves.data(), c.dev.leaf, sizeof(Leaf) * (size_t)c.N, hipMemcpyDeviceToHost));
+    if (c.set_padded > 0)
+        CAPT_HIP(hipMemcpy(pidx.data(), c.dev.pidx, sizeof(int32_t) * (size_t)c.set_padded, hipMemcpyDeviceToHost));
+    float *aabb = reinterpret_cast<float *>(B + L.aabb);
+    int64_t *off = reinterpret_cast<int64_t *>(B + L.off);
+    int32_t *idx = reinterpret_cast<int32_t *>(B + L.idx);
+    int64_t o = 0;
+    for (int64_t l = 0; l < c.N; ++l) {
+        const Leaf &lf = leaves[(size_t)l];
+        for (int a = 0; a < 3; ++a) {
+            aabb[6 * l + a] = lf.lo[a];
+            aabb[6 * l + 3 + a] = lf.hi[a];
+        }
+        off[l] = o;
+        for (uint32_t k = 0; k < lf.count; ++k) idx[o++] = pidx[lf.start + k];
+    }
+    off[c.N] = o;
+    return CAPT_OK;
+}
+
+capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_forest *out) {
+    ApiGuard g;
+    if (!host_blob || !out || bytes < sizeof(BlobHeader)) {
+        set_error("bad blob arguments");
+        return CAPT_EINVAL;
+    }
+    *out = nullptr;
+    const char *B = static_cast<const char *>(host_blob);
+    BlobHeader h;
+    memcpy(&h, B, sizeof h);
+    if (h.magic != BLOB_MAGIC || h.version != BLOB_VERSION || h.n < 0 || h.D < 0 || h.D > 30 ||
+        h.N != ((int64_t)1 << h.D) || h.n > h.N || (h.n > 0 && h.N >= 2 * h.n) || h.set_total < 0 ||
+        !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max) {
+        set_error("blob header is invalid");
+        return CAPT_EINVAL;
+    }
+    const BlobLayout L(h.n, h.N, h.set_total);
+    if (bytes < L.total) {
+        set_error("blob holds %zu bytes, layout needs %zu", bytes, L.total);
+        return CAPT_EINVAL;
+    }
+    const float *pts = reinterpret_cast<const float *>(B + L.pts);
+    const float *aabb = reinterpret_cast<const float *>(B + L.aabb);
+    const int64_t *off = reinterpret_cast<const int64_t *>(B + L.off);
+    const int32_t *idx = reinterpret_cast<const int32_t *>(B + L.idx);
+    const uint8_t *pr = reinterpret_cast<const uint8_t *>(B + L.pruned);
+    if (off[0] != 0 || off[h.N] != h.set_total) {
+        set_error("blob set offsets are invalid");
+        return CAPT_EINVAL;
+    }
+    for (int64_t j = 0; j < 3 * h.n; ++j)
+        if (!std::isfinite(pts[j])) {
+            set_error("blob point %lld is not finite", (long long)(j / 3));
+            return CAPT_EINVAL;
+        }
+    // place the sets (aligned as the builder does) and check every AABB
+    const int32_t *rep = reinterpret_cast<const int32_t *>(B + L.rep);
+    std::vector<Leaf> leaves((size_t)h.N);
+    int64_t padded = 0, pruned = 0;
+    for (int64_t l = 0; l < h.N; ++l) {
+        if (off[l + 1] < off[l] || rep[l] < 0 || rep[l] >= h.N) {
+            set_error("blob leaf %lld is invalid", (long long)l);
+            return CAPT_EINVAL;
+        }
+        const int64_t cnt = off[l + 1] - off[l];
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t k = off[l]; k < off[l + 1]; ++k) {
+            if (idx[k] < 0 || idx[k] >= h.n) {
+                set_error("blob set entry %lld is out of range", (long long)k);
+                return CAPT_EINVAL;
+            }
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], pts[3 * (int64_t)idx[k] + a]);
+                hi[a] = std::max(hi[a], pts[3 * (int64_t)idx[k] + a]);
+            }
+        }
+        for (int a = 0; a < 3; ++a)
+            if (memcmp(&lo[a], &aabb[6 * l + a], 4) != 0 || memcmp(&hi[a], &aabb[6 * l + 3 + a], 4) != 0) {
+                set_error("blob AABB of leaf %lld is not the bounding box of its set", (long long)l);
+                return CAPT_EINVAL;
+            }
+        Leaf &lf = leaves[(size_t)l];
+        for (int a = 0; a < 3; ++a) {
+            lf.lo[a] = lo[a];
+            lf.hi[a] = hi[a];
+        }
+        lf.start = (uint32_t)padded;
+        lf.count = (uint32_t)cnt;
+        padded += cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
+        pruned += pr[l] ? 1 : 0;
+        if (padded >= ((int64_t)1 << 32)) {
+            set_error("blob sets too large");
+            return CAPT_EUNSUPPORTED;
+        }
+    }
+    const size_t E = (size_t)std::max<int64_t>(padded, 1);
+    std::vector<float> px(E, INFINITY), py(E, INFINITY), pz(E, INFINITY);
+    std::vector<int32_t> pidx(E, -1);
+    for (int64_t l = 0; l < h.N; ++l)
+        for (int64_t k = off[l]; k < off[l + 1]; ++k) {
+            const size_t e = leaves[(size_t)l].start + (size_t)(k - off[l]);
+            const int64_t id = idx[k];
+            px[e] = pts[3 * id];
+            py[e] = pts[3 * id + 1];
+            pz[e] = pts[3 * id + 2];
+            pidx[e] = (int32_t)id;
+        }
+
+    capt_forest_s *f = new (std::nothrow) capt_forest_s();
+    if (!f) {
+        set_error("host allocation failed");
+        return CAPT_ENOMEM;
+    }
+    f->clouds.resize(1);
+    f->r_min = h.r_min;
+    f->r_max = h.r_max;
+    f->flags = h.flags;
+    f->pruned_total = pruned;
+    CloudHost &c = f->clouds[0];
+    c.n = h.n;
+    c.N = h.N;
+    c.D = h.D;
+    c.set_total = h.set_total;
+    c.set_padded = padded;
+    c.pruned = pruned;
+    hipStream_t s = (hipStream_t)stream;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t oT = 0;
+    const size_t oLeaf = al(sizeof(float) * (size_t)std::max<int64_t>(h.N - 1, 1));
+    const size_t oPts = al(oLeaf + sizeof(Leaf) * (size_t)h.N);
+    const size_t oRep = al(oPts + sizeof(float) * 3 * (size_t)std::max<int64_t>(h.n, 1));
+    const size_t oPr = al(oRep + sizeof(int32_t) * (size_t)h.N);
+    c.fixed_bytes = al(oPr + (size_t)h.N);
+    c.fixed = dev_alloc(c.fixed_bytes, s);
+    c.sets_bytes = al(sizeof(float) * E) * 3 + al(sizeof(int32_t) * E);
+    c.sets = dev_alloc(c.sets_bytes, s);
+    if (!c.fixed || !c.sets) {
+        destroy_forest(f);
+        set_error("device allocation failed");
+        return CAPT_ENOMEM;
+    }
+    char *F = static_cast<char *>(c.fixed);
+    char *P = static_cast<char *>(c.sets);
+    c.dev.T = reinterpret_cast<float *>(F + oT);
+    c.dev.leaf = reinterpret_cast<Leaf *>(F + oLeaf);
+    c.dev.pts = reinterpret_cast<float *>(F + oPts);
+    c.rep = reinterpret_cast<int32_t *>(F + oRep);
+    c.pruned_flag = reinterpret_cast<uint8_t *>(F + oPr);
+    c.dev.px = reinterpret_cast<float *>(P);
+    c.dev.py = reinterpret_cast<float *>(P + al(sizeof(float) * E));
+    c.dev.pz = reinterpret_cast<float *>(P + 2 * al(sizeof(float) * E));
+    c.dev.pidx = reinterpret_cast<int32_t *>(P + 3 * al(sizeof(float) * E));
+    c.dev.n = h.n;
+    c.dev.D = h.D;
+    c.dev.flags = h.flags;
+    auto cp = [&](void *dst, const void *src, size_t nb) -> capt_status {
+        if (nb) CAPT_HIP(hipMemcpy(dst, src, nb, hipMemcpyHostToDevice));
+        return CAPT_OK;
+    };
+    capt_status st = CAPT_OK;
+    if (!st) st = cp(const_cast<float *>(c.dev.T), B + L.T, sizeof(float) * (size_t)(h.N - 1));
+    if (!st) st = cp(const_cast<Leaf *>(c.dev.leaf), leaves.data(), sizeof(Leaf) * (size_t)h.N);
+    if (!st) st = cp(const_cast<float *>(c.dev.pts), pts, sizeof(float) * 3 * (size_t)h.n);
+    if (!st) st = cp(c.rep, rep, sizeof(int32_t) * (size_t)h.N);
+    if (!st) st = cp(c.pruned_flag, pr, (size_t)h.N);
+    if (!st) st = cp(const_cast<float *>(c.dev.px), px.data(), sizeof(float) * E);
+    if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);
+    if (!st) st = cp(const_cast<float *>(c.dev.pz), pz.data(), sizeof(float) * E);
+    if (!st) st = cp(const_cast<int32_t *>(c.dev.pidx), pidx.data(), sizeof(int32_t) * E);
+    if (!st) st = upload_views(f, s);
+    if (st) {
+        destroy_forest(f);
+        return st;
+    }
+    *out = f;
+    return CAPT_OK;
+}
+
+capt_status capt_bruteforce_collides(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                                     const float *spheres, const int64_t *query_off, int32_t group, uint8_t *out,
+                                     void *stream) {
+    ApiGuard g;
+    if (ncloud < 1) {
+        set_error("ncloud = %d must be >= 1", ncloud);
+        return CAPT_EINVAL;
+    }
+    capt_status st = check_offsets(cloud_off, ncloud, "cloud_off");
+    if (!st) st = check_offsets(query_off, ncloud, "query_off");
+    if (st) return st;
+    if (group < 1 || group > 1024) {
+        set_error("group = %d outside 1 .. 1024", group);
+        return CAPT_EINVAL;
+    }
+    for (int32_t c = 0; c < ncloud; ++c)
+        if ((query_off[c + 1] - query_off[c]) % group) {
+            set_error("query range of cloud %d is not a multiple of group", c);
+            return CAPT_EINVAL;
+        }
+    if ((cloud_off[ncloud] > 0 && !xyz) || (query_off[ncloud] > 0 && (!spheres || !out))) {
+        set_error("NULL buffer");
+        return CAPT_EINVAL;
+    }
+    return bruteforce(xyz, cloud_off, ncloud, spheres, query_off, group, out, (hipStream_t)stream);
+}
+
+capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t *query_off, int32_t *leaf,
+                             uint8_t *rejected, int32_t *scanned, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, 1);
+    if (st) return st;
+    return query_stats(f, spheres, query_off, leaf, rejected, scanned, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,719 @@
+// GPU construction of collision-affording point trees (Alg. 1, Sec. IV-A/B).
+//
+// Alg. 1 recurses with a cell c and an afforded set z; on a GPU the same tree
+// is produced level-synchronously:
+//  1. presort: three stable sorts of the padded point ids by (coordinate,
+//     id), one per axis (pad points sit at +inf);
+//  2. splits: at depth d every node is a contiguous, aligned segment of the
+//     three lists.  The node's split value is the coordinate of the last
+//     element of the lower half of the list sorted on axis d mod 3 (the lower
+//     median under (coordinate, id)); the other two lists are stably
+//     partitioned by "goes left", which keeps every half sorted on every
+//     axis.  Levels whose segments exceed one tile run as global passes; the
+//     remaining levels of each 2048-point subtree run in LDS in one launch.
+//  3. leaf cells from the split values of each leaf's ancestors;
+//  4. affordance sets: instead of carrying z down the recursion, each leaf
+//     collects {p : dist(p, cell) <= R} directly, by a near-first walk of the
+//     tree that skips subtrees whose point bounding box is farther than R.
+//     Both constructions give the same set (Lemma 1, case 1); the float64
+//     distance test is monotone under cell shrinking, so they agree exactly.
+//     A count pass sizes the sets, a scan places them (each set starts at a
+//     multiple of SET_ALIGN entries), a fill pass writes them SoA.
+#include <cmath>
+
+#include "capt_internal.h"
+
+namespace capt {
+
+namespace {
+
+constexpr int TB = 256;
+constexpr int LMAX = 2048;   // subtree size finished in LDS
+constexpr int GTILE = 2048;  // tile of the global partition passes
+
+__device__ __forceinline__ uint32_t ord_key(float v) {
+    if (v == 0.0f) v = 0.0f;  // -0 and +0 compare equal
+    uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float coord_of(const float *xyz, int64_t n, uint32_t id, int a) {
+    return (int64_t)id < n ? xyz[3 * (int64_t)id + a] : INFINITY;
+}
+
+__global__ void k_count_nonfinite(const float *__restrict__ xyz, int64_t cnt, uint32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t b = 0;
+    for (; i < cnt; i += stride) b += !isfinite(xyz[i]);
+    if (b) atomicAdd(bad, b);
+}
+
+__global__ void k_presort_keys(const float *__restrict__ xyz, int64_t n, int64_t N, int a,
+                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    keys[j] = j < n ? ord_key(xyz[3 * j + a]) : 0xFFFFFFFFu;
+    vals[j] = (uint32_t)j;
+}
+
+// Global level: split values and "goes left" flags from the list on axis a.
+__global__ void k_glevel_split(const uint32_t *__restrict__ La, const float *__restrict__ xyz,
+                               int64_t n, int64_t N, int d, int a, float *__restrict__ T,
+                               uint8_t *__restrict__ left) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int64_t s = N >> d, h = s >> 1;
+    const int64_t k = q & (s - 1);
+    uint32_t p = La[q];
+    left[p] = (uint8_t)(k < h);
+    const int lg = 63 - __builtin_clzll((unsigned long long)s);   // log2(s)
+    if (k == h - 1) T[((int64_t)1 << d) - 1 + (q >> lg)] = coord_of(xyz, n, p, a);
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lw, uint32_t *total) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    uint32_t inc = v;
+#pragma unroll
+    for (int dd = 1; dd < WAVE; dd <<= 1) {
+        uint32_t t = __shfl_up(inc, dd, WAVE);
+        if (lane >= dd) inc += t;
+    }
+    if (lane == WAVE - 1) lw[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+        uint32_t t = lw[i];
+        off += (i < w) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Global partition, pass 1: per tile count of left-going points, for the two
+// lists given by blockIdx.y.
+__global__ void k_gpart_count(const uint32_t *__restrict__ Lb0, const uint32_t *__restrict__ Lb1,
+                              const uint8_t *__restrict__ left, int64_t N,
+                              uint32_t *__restrict__ sums, int64_t ntile) {
+    __shared__ uint32_t lw[TB / WAVE];
+    const uint32_t *L = blockIdx.y ? Lb1 : Lb0;
+    const int64_t base = (int64_t)blockIdx.x * GTILE + (int64_t)threadIdx.x * 8;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c += left[L[base + i]];
+    uint32_t tot;
+    block_excl_scan(c, lw, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.y * ntile + blockIdx.x] = tot;
+}
+
+// Pass 2: exclusive scan of the tile counts of each list (one block per list).
+__global__ void k_gpart_scan(uint32_t *__restrict__ sums, int64_t ntile) {
+    __shared__ uint32_t lw[TB / WAVE];
+    __shared__ uint32_t carry;
+    uint32_t *S = sums + blockIdx.x * ntile;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < ntile; c0 += TB) {
+        int64_t j = c0 + threadIdx.x;
+        uint32_t v = j < ntile ? S[j] : 0u;
+        uint32_t tot;
+        uint32_t e = block_excl_scan(v, lw, &tot) + carry;
+        if (j < ntile) S[j] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
+// Pass 3: stable scatter within each segment of size s = N >> d.
+__global__ void k_gpart_scatter(const uint32_t *__restrict__ Lb0, const uint32_t *__restrict__ Lb1,
+                                uint32_t *__restrict__ Ob0, uint32_t *__restrict__ Ob1,
+                                const uint8_t *__restrict__ left, int64_t N, int d,
+                                const uint32_t *__restrict__ sums, int64_t ntile) {
+    __shared__ uint32_t lw[TB / WAVE];
+    const uint32_t *L = blockIdx.y ? Lb1 : Lb0;
+    uint32_t *O = blockIdx.y ? Ob1 : Ob0;
+    const uint32_t *S = sums + blockIdx.y * ntile;
+    const int64_t s = N >> d, h = s >> 1;
+    const int64_t base = (int64_t)blockIdx.x * GTILE + (int64_t)threadIdx.x * 8;
+    uint32_t p[8], f[8], c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        p[i] = L[base + i];
+        f[i] = left[p[i]];
+        c += f[i];
+    }
+    uint32_t tot;
+    uint32_t e = block_excl_scan(c, lw, &tot) + S[blockIdx.x];
+    const int64_t seg = base & ~(s - 1);
+    const uint32_t eseg = S[seg / GTILE];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int64_t q = base + i;
+        const int64_t lc = (int64_t)(e - eseg);
+        const int64_t np = f[i] ? seg + lc : seg + h + (q - seg - lc);
+        O[np] = p[i];
+        e += f[i];
+    }
+}
+
+__global__ void k_inverse(const uint32_t *__restrict__ L, int64_t N, uint32_t *__restrict__ inv) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < N) inv[L[q]] = (uint32_t)q;
+}
+
+// The remaining levels d0 .. D-1 of one subtree of S0 = N >> d0 <= LMAX
+// points, in LDS.  Lists hold local indices (positions in the axis-0 list of
+// the subtree).
+__global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict__ L0,
+                                                     const uint32_t *__restrict__ L1,
+                                                     const uint32_t *__restrict__ L2,
+                                                     const uint32_t *__restrict__ inv,
+                                                     const float *__restrict__ xyz, int64_t n,
+                                                     int64_t N, int D, int d0,
+                                                     float *__restrict__ T,
+                                                     int32_t *__restrict__ rep) {
+    __shared__ uint32_t ids[LMAX];
+    __shared__ float cx[3][LMAX];
+    __shared__ uint16_t lst[3][LMAX];
+    __shared__ uint16_t tmp[LMAX];
+    __shared__ uint16_t escan[LMAX];
+    __shared__ uint8_t flag[LMAX];
+    __shared__ uint32_t lw[TB / WAVE];
+    const int S0 = (int)(N >> d0);
+    const int64_t seg = (int64_t)blockIdx.x * S0;
+    for (int k = threadIdx.x; k < S0; k += TB) {
+        uint32_t id = L0[seg + k];
+        ids[k] = id;
+        for (int a = 0; a < 3; ++a) cx[a][k] = coord_of(xyz, n, id, a);
+        lst[0][k] = (uint16_t)k;
+        lst[1][k] = (uint16_t)(inv[L1[seg + k]] - (uint32_t)seg);
+        lst[2][k] = (uint16_t)(inv[L2[seg + k]] - (uint32_t)seg);
+    }
+    __syncthreads();
+    for (int d = d0; d < D; ++d) {
+        const int s = (int)(N >> d), h = s >> 1, a = d % 3;
+        const int64_t node0 = ((int64_t)1 << d) - 1 + (int64_t)blockIdx.x * (S0 / s);
+        for (int j = threadIdx.x; j < S0 / s; j += TB) T[node0 + j] = cx[a][lst[a][j * s + h - 1]];
+        for (int k = threadIdx.x; k < S0; k += TB) flag[lst[a][k]] = (uint8_t)((k & (s - 1)) < h);
+        __syncthreads();
+        for (int b = 1; b <= 2; ++b) {
+            uint16_t *lb = lst[(a + b) % 3];
+            // exclusive scan of flags over the S0 positions (8 per thread)
+            const int per = (S0 + TB - 1) / TB;
+            const int k0 = threadIdx.x * per;
+            uint32_t c = 0;
+            for (int i = 0; i < per; ++i) {
+                int k = k0 + i;
+                if (k < S0) c += flag[lb[k]];
+            }
+            uint32_t tot;
+            uint32_t e = block_excl_scan(c, lw, &tot);
+            for (int i = 0; i < per; ++i) {
+                int k = k0 + i;
+                if (k < S0) {
+                    escan[k] = (uint16_t)e;
+                    e += flag[lb[k]];
+                }
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < S0; k += TB) {
+                const int sg = k & ~(s - 1);
+                const int lc = (int)escan[k] - (int)escan[sg];
+                const uint16_t v = lb[k];
+                const int np = flag[v] ? sg + lc : sg + h + (k - sg - lc);
+                tmp[np] = v;
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < S0; k += TB) lb[k] = tmp[k];
+            __syncthreads();
+        }
+    }
+    for (int k = threadIdx.x; k < S0; k += TB) rep[seg + k] = (int32_t)ids[lst[0][k]];
+}
+
+// Leaf cells from the split values of the ancestors (Alg. 1: the left child
+// takes hi = T_i, the right child lo = T_i on the node's axis).
+__global__ void k_leaf_cells(const float *__restrict__ T, int64_t N, int D,
+                             float *__restrict__ cells) {
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    float c[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+    int64_t i = 0;
+    for (int d = 0; d < D; ++d) {
+        int a = d % 3;
+        int bit = (int)((l >> (D - 1 - d)) & 1);
+        if (bit) c[a] = T[i];
+        else c[3 + a] = T[i];
+        i = 2 * i + 1 + bit;
+    }
+    for (int k = 0; k < 6; ++k) cells[6 * l + k] = c[k];
+}
+
+// Bounding boxes of the real representatives below every node (Eytzinger
+// nodes 0 .. 2N-2; leaves are N-1 .. 2N-2).  Empty: lo = +inf, hi = -inf.
+__global__ void k_box_leaves(const int32_t *__restrict__ rep, const float *__restrict__ xyz,
+                             int64_t n, int64_t N, float *__restrict__ nbox) {
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    float *b = nbox + 6 * (N - 1 + l);
+    int64_t id = rep[l];
+    for (int a = 0; a < 3; ++a) {
+        float v = id < n ? xyz[3 * id + a] : 0.0f;
+        b[a] = id < n ? v : INFINITY;
+        b[3 + a] = id < n ? v : -INFINITY;
+    }
+}
+
+__global__ void k_box_level(int64_t first, int64_t count, float *__restrict__ nbox) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    int64_t i = first + j;
+    const float *L = nbox + 6 * (2 * i + 1);
+    const float *R = nbox + 6 * (2 * i + 2);
+    float *b = nbox + 6 * i;
+    for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(L[a], R[a]);
+        b[3 + a] = fmaxf(L[3 + a], R[3 + a]);
+    }
+}
+
+// float64 helpers, every operation rounded on its own
+__device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
+__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+
+// "c affords p at r_max": float64 distance from p to the closed cell.
+__device__ __forceinline__ bool affords(const double c[6], float px, float py, float pz,
+                                        double R2) {
+    const double p[3] = {(double)px, (double)py, (double)pz};
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double below = dsub(c[a], p[a]);
+        double above = dsub(p[a], c[3 + a]);
+        double g = below > above ? below : above;
+        if (g < 0.0) g = 0.0;
+        d2 = dadd(d2, dmul(g, g));
+    }
+    return d2 <= R2;
+}
+
+// Lower bound of the float64 distance from the cell to any point of a box.
+__device__ __forceinline__ bool box_may_afford(const double c[6], const float *b, double R2) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double g1 = dsub((double)b[a], c[3 + a]);   // box lo - cell hi
+        double g2 = dsub(c[a], (double)b[3 + a]);   // cell lo - box hi
+        double g = g1 > g2 ? g1 : g2;
+        if (g < 0.0) g = 0.0;
+        d2 = dadd(d2, dmul(g, g));
+    }
+    return d2 <= R2;
+}
+
+struct AffordArgs {
+    const float *T;
+    const float *cells;
+    const float *nbox;
+    const int32_t *rep;
+    const float *xyz;
+    int64_t n, N;
+    int D;
+    int prune;
+    double R2;      // (r_max (1 + 2^-20))^2
+    double thr;     // r_min^2 (1 - 2^-18)
+};
+
+__device__ __forceinline__ bool leaf_pruned(const AffordArgs &A, const double c[6], int64_t id) {
+    if (!A.prune || id >= A.n) return false;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (!isfinite(c[k])) return false;
+    double far2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = (double)A.xyz[3 * id + a];
+        double lo = dsub(t, c[a]);
+        double hi = dsub(c[3 + a], t);
+        double l2 = dmul(lo, lo), h2 = dmul(hi, hi);
+        far2 = dadd(far2, l2 > h2 ? l2 : h2);
+    }
+    return far2 <= A.thr;
+}
+
+// Count (FILL = false) or write (FILL = true) the affordance set of each leaf.
+template <bool FILL>
+__global__ void __launch_bounds__(TB) k_afford(AffordArgs A, uint32_t *__restrict__ count,
+                                               const uint32_t *__restrict__ start,
+                                               unsigned long long *__restrict__ totals,
+                                               float *__restrict__ px, float *__restrict__ py,
+                                               float *__restrict__ pz, int32_t *__restrict__ pidx,
+                                               Leaf *__restrict__ leaf, uint8_t *__restrict__ pruned) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= A.N) return;
+    double c[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] = (double)A.cells[6 * l + k];
+    const int64_t id = A.rep[l];
+    uint32_t cnt = 0;
+    uint32_t s0 = FILL ? start[l] : 0u;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    auto emit = [&](int64_t pid) {
+        if (FILL) {
+            float x = A.xyz[3 * pid], y = A.xyz[3 * pid + 1], z = A.xyz[3 * pid + 2];
+            px[s0 + cnt] = x;
+            py[s0 + cnt] = y;
+            pz[s0 + cnt] = z;
+            pidx[s0 + cnt] = (int32_t)pid;
+            lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+            hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+        }
+        ++cnt;
+    };
+    const bool pr = leaf_pruned(A, c, id);
+    if (pr) {
+        emit(id);
+    } else {
+        // near-first depth-first walk; a node is visited only if its point box
+        // may lie within R of the cell
+        float key[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float lo_ = (float)c[a], hi_ = (float)c[3 + a];
+            key[a] = (isfinite(lo_) && isfinite(hi_)) ? 0.5f * lo_ + 0.5f * hi_
+                     : isfinite(lo_) ? lo_ : isfinite(hi_) ? hi_ : 0.0f;
+        }
+        int32_t stack[33];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            const int64_t i = stack[--sp];
+            const float *b = A.nbox + 6 * i;
+            if (b[0] > b[3]) continue;   // no real point below
+            if (!box_may_afford(c, b, A.R2)) continue;
+            if (i >= A.N - 1) {
+                const int64_t pid = A.rep[i - (A.N - 1)];
+                if (pid < A.n && affords(c, A.xyz[3 * pid], A.xyz[3 * pid + 1], A.xyz[3 * pid + 2], A.R2))
+                    emit(pid);
+                continue;
+            }
+            const int d = 31 - __builtin_clz((unsigned)(i + 1));
+            const bool left_first = key[d % 3] <= A.T[i];
+            if (left_first) {
+                stack[sp++] = (int32_t)(2 * i + 2);
+                stack[sp++] = (int32_t)(2 * i + 1);
+            } else {
+                stack[sp++] = (int32_t)(2 * i + 1);
+                stack[sp++] = (int32_t)(2 * i + 2);
+            }
+        }
+    }
+    if (!FILL) {
+        count[l] = cnt;
+        unsigned long long padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
+        atomicAdd(&totals[0], (unsigned long long)cnt);
+        atomicAdd(&totals[1], padded);
+        if (pr) atomicAdd(&totals[2], 1ull);
+    } else {
+        const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
+        for (uint32_t k = cnt; k < padded; ++k) {
+            px[s0 + k] = INFINITY;
+            py[s0 + k] = INFINITY;
+            pz[s0 + k] = INFINITY;
+            pidx[s0 + k] = -1;
+        }
+        Leaf L;
+        for (int a = 0; a < 3; ++a) {
+            L.lo[a] = lo[a];
+            L.hi[a] = hi[a];
+        }
+        L.start = s0;
+        L.count = cnt;
+        leaf[l] = L;
+        pruned[l] = (uint8_t)pr;
+    }
+}
+
+__global__ void k_pad_counts(const uint32_t *__restrict__ cnt, int64_t N, uint32_t *__restrict__ out) {
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    uint32_t c = cnt[l];
+    out[l] = c ? ((c + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+}
+
+inline unsigned nblk(int64_t n, int tb = TB) { return (unsigned)((n + tb - 1) / tb); }
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Per-cloud scratch kept from the count phase to the fill phase.
+struct CloudWork {
+    Scratch scratch;
+    float *cells = nullptr;
+    float *nbox = nullptr;
+    uint32_t *count = nullptr;
+    uint32_t *start = nullptr;
+    unsigned long long *totals = nullptr;   // [0] entries [1] padded [2] pruned
+    uint32_t *bad = nullptr;
+    int32_t *rep = nullptr;
+    AffordArgs args{};
+};
+
+capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, uint32_t flags,
+                         hipStream_t s, CloudHost &C, CloudWork &W) {
+    int64_t N = 1;
+    int D = 0;
+    while (N < n) {
+        N <<= 1;
+        ++D;
+    }
+    if (D > 30) {
+        set_error("cloud of %lld points exceeds 2^30", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    C.n = n;
+    C.N = N;
+    C.D = D;
+    // fixed per-cloud block: T, leaves, points, rep, pruned flags
+    const size_t oT = 0;
+    const size_t oLeaf = align256(oT + sizeof(float) * (size_t)(N > 1 ? N - 1 : 1));
+    const size_t oPts = align256(oLeaf + sizeof(Leaf) * (size_t)N);
+    const size_t oRep = align256(oPts + sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
+    const size_t oPr = align256(oRep + sizeof(int32_t) * (size_t)N);
+    const size_t fixed_bytes = align256(oPr + (size_t)N);
+    C.fixed = dev_alloc(fixed_bytes, s);
+    if (!C.fixed) {
+        set_error("device allocation of %zu bytes failed", fixed_bytes);
+        return CAPT_ENOMEM;
+    }
+    C.fixed_bytes = fixed_bytes;
+    char *F = static_cast<char *>(C.fixed);
+    float *T = reinterpret_cast<float *>(F + oT);
+    C.dev.T = T;
+    C.dev.leaf = reinterpret_cast<Leaf *>(F + oLeaf);
+    float *pts = reinterpret_cast<float *>(F + oPts);
+    C.dev.pts = pts;
+    C.rep = reinterpret_cast<int32_t *>(F + oRep);
+    C.pruned_flag = reinterpret_cast<uint8_t *>(F + oPr);
+    C.dev.n = n;
+    C.dev.D = D;
+    C.dev.flags = flags;
+    if (n > 0) CAPT_HIP(hipMemcpyAsync(pts, xyz, sizeof(float) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s));
+
+    // scratch
+    const size_t wN = (size_t)N;
+    const size_t radix = radix_tmp_words(N);
+    const size_t ntile = (size_t)((N + GTILE - 1) / GTILE);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t oL = take(sizeof(uint32_t) * 6 * wN);     // 3 lists x 2 buffers
+    const size_t oK = take(sizeof(uint32_t) * 2 * wN);     // sort keys x 2
+    const size_t oInv = take(sizeof(uint32_t) * wN);
+    const size_t oLeft = take(wN);
+    const size_t oSums = take(sizeof(uint32_t) * (2 * ntile + 16));
+    const size_t oRad = take(sizeof(uint32_t) * radix);
+    const size_t oCells = take(sizeof(float) * 6 * wN);
+    const size_t oBox = take(sizeof(float) * 6 * (2 * wN));
+    const size_t oCnt = take(sizeof(uint32_t) * (wN + 1));
+    const size_t oStart = take(sizeof(uint32_t) * (wN + 1));
+    const size_t oTot = take(sizeof(unsigned long long) * 4);
+    const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words(N + 1));
+    if (!W.scratch.alloc(off, s)) {
+        set_error("device allocation of %zu scratch bytes failed", off);
+        return CAPT_ENOMEM;
+    }
+    char *Sb = W.scratch.as<char>();
+    uint32_t *Lbuf = reinterpret_cast<uint32_t *>(Sb + oL);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(Sb + oK);
+    uint32_t *inv = reinterpret_cast<uint32_t *>(Sb + oInv);
+    uint8_t *left = reinterpret_cast<uint8_t *>(Sb + oLeft);
+    uint32_t *sums = reinterpret_cast<uint32_t *>(Sb + oSums);
+    uint32_t *rad = reinterpret_cast<uint32_t *>(Sb + oRad);
+    W.cells = reinterpret_cast<float *>(Sb + oCells);
+    W.nbox = reinterpret_cast<float *>(Sb + oBox);
+    W.count = reinterpret_cast<uint32_t *>(Sb + oCnt);
+    W.start = reinterpret_cast<uint32_t *>(Sb + oStart);
+    W.totals = reinterpret_cast<unsigned long long *>(Sb + oTot);
+    uint32_t *scan_tmp = reinterpret_cast<uint32_t *>(Sb + oScan);
+    W.bad = reinterpret_cast<uint32_t *>(W.totals + 3);
+    W.rep = C.rep;
+    CAPT_HIP(hipMemsetAsync(W.totals, 0, sizeof(unsigned long long) * 4, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(std::min<int64_t>(nblk(3 * n), 4096)), dim3(TB), 0, s,
+                           xyz, 3 * n, W.bad);
+        CAPT_LAUNCH_CHECK();
+    }
+
+    // 1. presort on each axis: L[a] (buffer 0) sorted by (coordinate, id)
+    uint32_t *L[3][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 2; ++b) L[a][b] = Lbuf + (size_t)(2 * a + b) * wN;
+    int cur[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, a, keys, L[a][0]);
+        CAPT_LAUNCH_CHECK();
+        int where = 0;
+        capt_status st = radix_sort_u32(keys, L[a][0], keys + wN, L[a][1], N, 32, rad, s, &where);
+        if (st) return st;
+        cur[a] = where;
+    }
+
+    // 2. splits: global levels while segments exceed LMAX, then LDS levels
+    int d = 0;
+    for (; d < D && (N >> d) > LMAX; ++d) {
+        const int a = d % 3;
+        const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+        hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[a][cur[a]], xyz, n, N, d, a, T,
+                           left);
+        CAPT_LAUNCH_CHECK();
+        const int64_t nt = N / GTILE;
+        hipLaunchKernelGGL(k_gpart_count, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]],
+                           L[b2][cur[b2]], left, N, sums, nt);
+        CAPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gpart_scan, dim3(2), dim3(TB), 0, s, sums, nt);
+        CAPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gpart_scatter, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]],
+                           L[b2][cur[b2]], L[b1][cur[b1] ^ 1], L[b2][cur[b2] ^ 1], left, N, d, sums, nt);
+        CAPT_LAUNCH_CHECK();
+        cur[b1] ^= 1;
+        cur[b2] ^= 1;
+    }
+    hipLaunchKernelGGL(k_inverse, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], N, inv);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(TB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]], inv, xyz, n, N, D, d, T,
+                       C.rep);
+    CAPT_LAUNCH_CHECK();
+
+    // 3. leaf cells, point boxes of every node
+    hipLaunchKernelGGL(k_leaf_cells, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, W.cells);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_box_leaves, dim3(nblk(N)), dim3(TB), 0, s, C.rep, xyz, n, N, W.nbox);
+    CAPT_LAUNCH_CHECK();
+    for (int dd = D - 1; dd >= 0; --dd) {
+        const int64_t first = ((int64_t)1 << dd) - 1, count = (int64_t)1 << dd;
+        hipLaunchKernelGGL(k_box_level, dim3(nblk(count)), dim3(TB), 0, s, first, count, W.nbox);
+        CAPT_LAUNCH_CHECK();
+    }
+
+    // 4. affordance counts and placement
+    AffordArgs &A = W.args;
+    A.T = T;
+    A.cells = W.cells;
+    A.nbox = W.nbox;
+    A.rep = C.rep;
+    A.xyz = xyz;
+    A.n = n;
+    A.N = N;
+    A.D = D;
+    A.prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
+    const double R = (double)r_max * (1.0 + 0x1p-20);
+    A.R2 = R * R;
+    A.thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
+    hipLaunchKernelGGL((k_afford<false>), dim3(nblk(N)), dim3(TB), 0, s, A, W.count, nullptr, W.totals,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.start);
+    CAPT_LAUNCH_CHECK();
+    capt_status st = scan_exclusive_u32(W.start, W.start, N, nullptr, nullptr, scan_tmp, s);
+    if (st) return st;
+    return CAPT_OK;
+}
+
+capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsigned long long tot[4]) {
+    C.set_total = (int64_t)tot[0];
+    C.set_padded = (int64_t)tot[1];
+    C.pruned = (int64_t)tot[2];
+    if (tot[1] >= (1ull << 32)) {
+        set_error("affordance sets hold %llu entries, more than 2^32", tot[1]);
+        return CAPT_EUNSUPPORTED;
+    }
+    const size_t E = (size_t)(tot[1] > 0 ? tot[1] : 1);
+    const size_t bytes = align256(sizeof(float) * E) * 3 + align256(sizeof(int32_t) * E);
+    C.sets = dev_alloc(bytes, s);
+    if (!C.sets) {
+        set_error("device allocation of %zu bytes for affordance sets failed", bytes);
+        return CAPT_ENOMEM;
+    }
+    C.sets_bytes = bytes;
+    char *P = static_cast<char *>(C.sets);
+    float *px = reinterpret_cast<float *>(P);
+    float *py = reinterpret_cast<float *>(P + align256(sizeof(float) * E));
+    float *pz = reinterpret_cast<float *>(P + 2 * align256(sizeof(float) * E));
+    int32_t *pidx = reinterpret_cast<int32_t *>(P + 3 * align256(sizeof(float) * E));
+    C.dev.px = px;
+    C.dev.py = py;
+    C.dev.pz = pz;
+    C.dev.pidx = pidx;
+    hipLaunchKernelGGL((k_afford<true>), dim3(nblk(C.N)), dim3(TB), 0, s, W.args, nullptr, W.start, nullptr,
+                       px, py, pz, pidx, const_cast<Leaf *>(C.dev.leaf), C.pruned_flag);
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
+}
+
+}  // namespace
+
+void free_cloud(CloudHost &c) {
+    if (c.fixed) dev_free(c.fixed, nullptr);
+    if (c.sets) dev_free(c.sets, nullptr);
+    c.fixed = c.sets = nullptr;
+}
+
+capt_status upload_views(capt_forest_s *f, hipStream_t s) {
+    const size_t bytes = sizeof(CloudDev) * f->clouds.size();
+    f->d_clouds = static_cast<CloudDev *>(dev_alloc(bytes, s));
+    if (!f->d_clouds) {
+        set_error("device allocation of %zu bytes failed", bytes);
+        return CAPT_ENOMEM;
+    }
+    std::vector<CloudDev> h(f->clouds.size());
+    for (size_t c = 0; c < h.size(); ++c) h[c] = f->clouds[c].dev;
+    CAPT_HIP(hipMemcpyAsync(f->d_clouds, h.data(), bytes, hipMemcpyHostToDevice, s));
+    CAPT_HIP(hipStreamSynchronize(s));
+    return CAPT_OK;
+}
+
+capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min,
+                         float r_max, uint32_t flags, hipStream_t s, capt_forest_s *f) {
+    f->clouds.resize(ncloud);
+    f->r_min = r_min;
+    f->r_max = r_max;
+    f->flags = flags;
+    std::vector<CloudWork> work(ncloud);
+    for (int c = 0; c < ncloud; ++c) {
+        const int64_t n = cloud_off[c + 1] - cloud_off[c];
+        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, s, f->clouds[c], work[c]);
+        if (st) return st;
+    }
+    // one device-to-host read of every cloud's totals
+    std::vector<unsigned long long> tot(4 * (size_t)ncloud);
+    for (int c = 0; c < ncloud; ++c)
+        CAPT_HIP(hipMemcpyAsync(&tot[4 * c], work[c].totals, sizeof(unsigned long long) * 4,
+                                hipMemcpyDeviceToHost, s));
+    CAPT_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < ncloud; ++c) {
+        const uint32_t bad = (uint32_t)(tot[4 * c + 3] & 0xFFFFFFFFull);
+        if (bad) {
+            set_error("cloud %d holds %u non-finite coordinates", c, bad);
+            return CAPT_EINVAL;
+        }
+    }
+    int64_t pruned = 0;
+    for (int c = 0; c < ncloud; ++c) {
+        capt_status st = build_phase2(s, f->clouds[c], work[c], &tot[4 * c]);
+        if (st) return st;
+        pruned += f->clouds[c].pruned;
+    }
+    f->pruned_total = pruned;
+    capt_status st = upload_views(f, s);  // synchronises: scratch is released after
+    return st;
+}
+
+}  // namespace capt

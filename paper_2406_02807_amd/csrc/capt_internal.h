@@ -1,0 +1,205 @@
+// Internal declarations of the CAPT HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/capt.h"
+
+namespace capt {
+
+constexpr int WAVE = 64;
+
+// One leaf record: float32 bounding box of the stored set, then the set's
+// first entry and length in the per-cloud SoA arrays.  32 bytes, so one leaf
+// is two 16-byte loads.
+struct alignas(16) Leaf {
+    float lo[3];
+    float hi[3];
+    uint32_t start;
+    uint32_t count;
+};
+static_assert(sizeof(Leaf) == 32, "leaf record is 32 bytes");
+
+// Per-cloud view of a forest, resident in device memory for the batched
+// kernel and passed by value to the single-cloud kernels.
+struct CloudDev {
+    const float *T;        // [N-1] split values, Eytzinger order
+    const Leaf *leaf;      // [N]
+    const float *px;       // set entries, structure of arrays
+    const float *py;
+    const float *pz;
+    const int32_t *pidx;   // original index of each set entry (-1 = padding)
+    const float *pts;      // [n][3] the cloud as built
+    int64_t n;
+    int32_t D;
+    uint32_t flags;
+};
+
+// Stored-set alignment: every set starts at a multiple of this many entries
+// and is padded with +inf entries up to one.
+constexpr uint32_t SET_ALIGN = 16;
+
+// ---------------------------------------------------------------------------
+// Host-side error state and helpers (api.hip)
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+capt_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+#define CAPT_HIP(call)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) return ::capt::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define CAPT_LAUNCH_CHECK() CAPT_HIP(hipGetLastError())
+
+// RAII scratch buffer from the configured allocator.
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    Scratch() = default;
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    ~Scratch() { release(); }
+    bool alloc(size_t bytes, hipStream_t st) {
+        release();
+        s = st;
+        p = dev_alloc(bytes ? bytes : 16, st);
+        return p != nullptr;
+    }
+    void release() {
+        if (p) dev_free(p, s);
+        p = nullptr;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Device properties used for launch planning.
+struct DeviceInfo {
+    int cus = 256;
+    int lds_per_block = 65536;
+};
+const DeviceInfo &device_info();
+
+// ---------------------------------------------------------------------------
+// Primitives (primitives.hip)
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of n uint32 values (n may be given on the device
+// through n_dev, in which case `n` is only the capacity).  out may alias in.
+// total (device, may be NULL) receives the sum.  tmp must hold
+// scan_tmp_words(n) uint32 words.
+size_t scan_tmp_words(int64_t n);
+capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                               const int64_t *n_dev, uint32_t *total, uint32_t *tmp,
+                               hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// key.  Keys/values ping-pong between the two buffers; the sorted result ends
+// in (k0, v0) when the number of 8-bit passes is even, else in (k1, v1); the
+// return value of radix_sort_* tells which (0 or 1) through *where.
+size_t radix_tmp_words(int64_t n);
+capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                           int bits, uint32_t *tmp, hipStream_t s, int *where);
+capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                           int bits, uint32_t *tmp, hipStream_t s, int *where);
+
+// ---------------------------------------------------------------------------
+// Forest (api.hip / build.hip)
+// ---------------------------------------------------------------------------
+struct CloudHost {
+    int64_t n = 0;
+    int64_t N = 1;
+    int32_t D = 0;
+    int64_t set_total = 0;     // stored entries without padding
+    int64_t set_padded = 0;    // stored entries with padding
+    int64_t pruned = 0;
+    void *fixed = nullptr;     // T, leaves, pts, rep, pruned flags
+    void *sets = nullptr;      // px, py, pz, pidx
+    size_t fixed_bytes = 0;
+    size_t sets_bytes = 0;
+    CloudDev dev{};
+    int32_t *rep = nullptr;    // device [N]
+    uint8_t *pruned_flag = nullptr;  // device [N]
+};
+
+struct BatchPlan;
+
+}  // namespace capt
+
+struct capt_forest_s {
+    std::vector<capt::CloudHost> clouds;
+    capt::CloudDev *d_clouds = nullptr;   // device copy of every cloud's view
+    float r_min = 0.f, r_max = 0.f;
+    uint32_t flags = 0;
+    int64_t pruned_total = 0;
+    capt::BatchPlan *plan = nullptr;      // cached batched launch (query.hip)
+};
+
+namespace capt {
+
+// build.hip
+capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                         float r_min, float r_max, uint32_t flags, hipStream_t s,
+                         capt_forest_s *f);
+void free_cloud(CloudHost &c);
+capt_status upload_views(capt_forest_s *f, hipStream_t s);
+
+// query.hip
+capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,
+                     int32_t group, uint8_t *out, uint32_t flags, hipStream_t s);
+capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off,
+                        int32_t *leaf, uint8_t *rejected, int32_t *scanned, hipStream_t s);
+capt_status bruteforce(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                       const float *spheres, const int64_t *query_off, int32_t group,
+                       uint8_t *out, hipStream_t s);
+capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s);
+void free_plan(BatchPlan *p);
+capt_tuning &tuning();
+
+// clearance.hip
+capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t *query_off,
+                          float *clr, int32_t *witness, hipStream_t s);
+capt_status clearance_bwd(capt_forest_s *f, const float *spheres, const int64_t *query_off,
+                          const int32_t *witness, const float *grad, float *grad_sph,
+                          hipStream_t s);
+
+// filter.hip
+capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz,
+                   int32_t *out_index, int64_t *n_out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Device helpers shared by the kernels of this library
+// ---------------------------------------------------------------------------
+// The float32 sphere-point predicate: ((dx*dx + dy*dy) + dz*dz) <= r*r,
+// every operation rounded on its own (the library is compiled with
+// -ffp-contract=off; the explicit _rn intrinsics make the intent visible).
+__device__ __forceinline__ float sqdist(float ax, float ay, float az, float bx, float by,
+                                        float bz) {
+    float dx = __fsub_rn(ax, bx);
+    float dy = __fsub_rn(ay, by);
+    float dz = __fsub_rn(az, bz);
+    float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+    return __fadd_rn(s, __fmul_rn(dz, dz));
+}
+
+// Squared distance from a point to a float32 box, with the same rounding
+// order as sqdist (so it never exceeds sqdist to any point inside the box).
+__device__ __forceinline__ float box_sqdist(float x, float y, float z, const float lo[3],
+                                            const float hi[3]) {
+    float gx = fmaxf(fmaxf(__fsub_rn(lo[0], x), __fsub_rn(x, hi[0])), 0.0f);
+    float gy = fmaxf(fmaxf(__fsub_rn(lo[1], y), __fsub_rn(y, hi[1])), 0.0f);
+    float gz = fmaxf(fmaxf(__fsub_rn(lo[2], z), __fsub_rn(z, hi[2])), 0.0f);
+    float s = __fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy));
+    return __fadd_rn(s, __fmul_rn(gz, gz));
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace capt

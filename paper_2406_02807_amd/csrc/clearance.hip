@@ -1,0 +1,181 @@
+// Differentiable clearance against CAPTs: forward (nearest affordance-set
+// point, clamped at r_max) and its hand-written backward.
+//
+// Forward mapping: a wavefront takes 64 spheres (one per lane), descends the
+// tree and applies the AABB shortcut (if even the leaf box is at least r_max
+// away, the clamp is active and no point needs reading).  The remaining
+// spheres are then processed one after another by the whole wave: the 64
+// lanes stream the sphere's set in coalesced 64-entry steps keeping a running
+// (squared distance, index) minimum, and one butterfly reduction per sphere
+// yields the argmin (ties -> smallest original index).  Sets here are full
+// scans, so lanes across the set keep loads contiguous and every lane busy.
+//
+// Backward: thread per sphere; reads the witness point from the cloud copy
+// kept in the forest, 48 bytes of traffic per sphere.
+#include <climits>
+#include <cmath>
+
+#include "capt_internal.h"
+
+namespace capt {
+
+namespace {
+
+__device__ __forceinline__ uint32_t descend_c(const float4 &q, const float *Tl, int L,
+                                              const float *__restrict__ Tg, int D) {
+    uint32_t i = 0;
+    int a = 0;
+    for (int lv = 0; lv < D; ++lv) {
+        const float t = lv < L ? Tl[i] : Tg[i];
+        const float x = a == 0 ? q.x : (a == 1 ? q.y : q.z);
+        i = 2 * i + 1 + (x > t ? 1u : 0u);
+        a = (a == 2) ? 0 : a + 1;
+    }
+    return i;
+}
+
+__global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, float r_max,
+                            float *__restrict__ clr, int32_t *__restrict__ wit, int L) {
+    extern __shared__ float Tl[];
+    const int nT = (1 << L) - 1;
+    for (int i = threadIdx.x; i < nT; i += blockDim.x) Tl[i] = C.T[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t ntiles = (nsph + WAVE - 1) / WAVE;
+    const int64_t N = (int64_t)1 << C.D;
+    for (int64_t t = wid; t < ntiles; t += waves) {
+        const int64_t s = t * WAVE + lane;
+        const bool valid = s < nsph;
+        const float4 q = valid ? sph[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint32_t lf = descend_c(q, Tl, L, C.T, C.D) - (uint32_t)(N - 1);
+        uint32_t start = 0, count = 0;
+        bool need = false;
+        if (valid) {
+            const Leaf leaf = C.leaf[lf];
+            start = leaf.start;
+            count = leaf.count;
+            if (count > 0) {
+                const float b2 = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi);
+                need = !(sqrtf(b2) >= r_max);
+            }
+        }
+        float best = INFINITY;
+        int32_t besti = INT_MAX;
+        uint64_t todo = __ballot(need);
+        while (todo) {
+            const int o = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const float ox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x), o));
+            const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.y), o));
+            const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.z), o));
+            const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)start, o);
+            const uint32_t ct = (uint32_t)__builtin_amdgcn_readlane((int)count, o);
+            float m = INFINITY;
+            int32_t mi = INT_MAX;
+            for (uint32_t k = lane; k < ct; k += WAVE) {
+                const uint32_t e = st + k;
+                const float d2 = sqdist(ox, oy, oz, C.px[e], C.py[e], C.pz[e]);
+                const int32_t id = C.pidx[e];
+                if (d2 < m || (d2 == m && id < mi)) {
+                    m = d2;
+                    mi = id;
+                }
+            }
+#pragma unroll
+            for (int off = WAVE / 2; off >= 1; off >>= 1) {
+                const float om = __shfl_xor(m, off, WAVE);
+                const int32_t oi = __shfl_xor(mi, off, WAVE);
+                if (om < m || (om == m && oi < mi)) {
+                    m = om;
+                    mi = oi;
+                }
+            }
+            if (lane == o) {
+                best = m;
+                besti = mi;
+            }
+        }
+        if (valid) {
+            const float d = need ? sqrtf(best) : INFINITY;
+            if (d < r_max) {
+                clr[s] = __fsub_rn(d, q.w);
+                wit[s] = besti;
+            } else {
+                clr[s] = __fsub_rn(r_max, q.w);
+                wit[s] = -1;
+            }
+        }
+    }
+}
+
+__global__ void k_clearance_bwd(const float *__restrict__ pts, const float4 *__restrict__ sph,
+                                int64_t nsph, const int32_t *__restrict__ wit,
+                                const float *__restrict__ grad, float4 *__restrict__ gout) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsph) return;
+    const float g = grad[s];
+    const int32_t w = wit[s];
+    float4 r = make_float4(0.f, 0.f, 0.f, -g);
+    if (w >= 0) {
+        const float4 q = sph[s];
+        const float dx = __fsub_rn(q.x, pts[3 * (int64_t)w]);
+        const float dy = __fsub_rn(q.y, pts[3 * (int64_t)w + 1]);
+        const float dz = __fsub_rn(q.z, pts[3 * (int64_t)w + 2]);
+        const float d = sqrtf(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz)));
+        if (d > 0.0f) {
+            const float k = g / d;
+            r.x = k * dx;
+            r.y = k * dy;
+            r.z = k * dz;
+        }
+    }
+    gout[s] = r;
+}
+
+int lds_levels_c(int D) {
+    int L = std::min(D, 14);
+    const size_t cap = (size_t)device_info().lds_per_block;
+    while (L > 0 && sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
+    return L;
+}
+
+}  // namespace
+
+capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t *qoff, float *clr,
+                          int32_t *witness, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        const CloudDev &C = f->clouds[c].dev;
+        const int L = lds_levels_c(C.D);
+        const int threads = 512;
+        const int64_t ntiles = (m + WAVE - 1) / WAVE;
+        int64_t blocks = std::min<int64_t>((ntiles + 7) / 8, (int64_t)device_info().cus * 2);
+        blocks = std::max<int64_t>(blocks, 1);
+        const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
+        hipLaunchKernelGGL(k_clearance, dim3((unsigned)blocks), dim3(threads), lds, s, C,
+                           reinterpret_cast<const float4 *>(spheres + 4 * qoff[c]), m, f->r_max, clr + qoff[c],
+                           witness + qoff[c], L);
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+capt_status clearance_bwd(capt_forest_s *f, const float *spheres, const int64_t *qoff, const int32_t *witness,
+                          const float *grad, float *grad_sph, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        hipLaunchKernelGGL(k_clearance_bwd, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           f->clouds[c].dev.pts, reinterpret_cast<const float4 *>(spheres + 4 * qoff[c]), m,
+                           witness + qoff[c], grad + qoff[c], reinterpret_cast<float4 *>(grad_sph + 4 * qoff[c]));
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+}  // namespace capt

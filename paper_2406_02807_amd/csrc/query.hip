@@ -1,0 +1,543 @@
+// Collision queries against CAPTs (Alg. 3, Sec. IV-D) on wave64 CDNA4.
+//
+// Mapping.  One wavefront owns a tile of up to 64 spheres: one sphere per lane
+// (64 / g whole configurations of g spheres, or a 64-sphere slice of a larger
+// configuration).  Each lane descends the tree branch-free (the top levels of
+// T sit in LDS) and tests its leaf's AABB.  The surviving spheres' affordance
+// sets are then scanned as ONE flattened list of (sphere, set entry) pairs:
+// an exclusive wave scan of the remaining set lengths places every sphere's
+// pairs, each of the 64 lanes takes one pair per step (binary search over the
+// scan finds its sphere), loads the entry from the SoA set arrays - runs of
+// consecutive lanes read consecutive addresses of one set - and tests it.  A
+// ballot after every step marks the configurations that were hit; their
+// spheres drop out of the next scan (early exit, Sec. I and IV-D).  This keeps
+// every lane busy whatever the mix of set sizes, which the paper's CPU layout
+// (lanes across one set at a time) does not.
+//
+// Kernels: k_collide_cloud (one cloud, persistent, static tile stride),
+// k_collide_batched (many clouds, persistent, tiles popped from a queue sorted
+// by descending cost), k_brute (baseline), k_query_stats (work accounting).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "capt_internal.h"
+
+namespace capt {
+
+namespace {
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float axis_of(const float4 &q, int a) {
+    return a == 0 ? q.x : (a == 1 ? q.y : q.z);
+}
+
+// Branch-free descent: i <- 2i + 1 + (x_d > T_i), ties go left.  The first
+// `L` levels read T from LDS.
+__device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, int L,
+                                            const float *__restrict__ Tg, int D) {
+    uint32_t i = 0;
+    int a = 0;
+    int lv = 0;
+    for (; lv < L; ++lv) {
+        const float t = Tl[i];
+        i = 2 * i + 1 + (axis_of(q, a) > t ? 1u : 0u);
+        a = (a == 2) ? 0 : a + 1;
+    }
+    for (; lv < D; ++lv) {
+        const float t = Tg[i];
+        i = 2 * i + 1 + (axis_of(q, a) > t ? 1u : 0u);
+        a = (a == 2) ? 0 : a + 1;
+    }
+    return i;
+}
+
+// Process one tile of up to 64 spheres against one cloud.  Lane l holds
+// sphere l of the tile (valid if l < nsph); lanes of configuration c are
+// c*g .. c*g+g-1 (g <= 64), or all lanes belong to one configuration (g > 64,
+// cfg_of_lane = 0).  Returns, per lane, whether that lane's configuration was
+// hit.
+__device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L,
+                                          const float4 *__restrict__ sph, int nsph, int g) {
+    const int lane = lane_id();
+    const bool valid = lane < nsph;
+    float4 q = valid ? sph[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float r2 = __fmul_rn(q.w, q.w);
+    const int64_t N = (int64_t)1 << C.D;
+    const uint32_t node = descend(q, Tl, L, C.T, C.D);
+    const uint32_t lf = node - (uint32_t)(N - 1);
+    Leaf leaf;
+    if (valid) {
+        leaf = C.leaf[lf];
+    } else {
+        leaf.count = 0;
+        leaf.start = 0;
+    }
+    bool alive = valid && leaf.count > 0;
+    if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
+
+    const int gg = g > WAVE ? WAVE : g;
+    const int cfg = g > WAVE ? 0 : lane / gg;
+    const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
+    bool done = false;
+    uint32_t rem = alive ? leaf.count : 0u;
+    uint32_t pos = leaf.start;
+    const float *__restrict__ PX = C.px;
+    const float *__restrict__ PY = C.py;
+    const float *__restrict__ PZ = C.pz;
+    while (true) {
+        if (done) rem = 0;
+        const uint32_t incl = wave_incl_scan(rem, lane);
+        const uint32_t excl = incl - rem;
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (total == 0) break;
+        // owner of pair slot `lane`: the last sphere whose first slot <= lane
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t e = __shfl(excl, o + step, WAVE);
+            if (e <= (uint32_t)lane) o += step;
+        }
+        const uint32_t base = __shfl(pos - excl, o, WAVE);
+        const float ox = __shfl(q.x, o, WAVE);
+        const float oy = __shfl(q.y, o, WAVE);
+        const float oz = __shfl(q.z, o, WAVE);
+        const float orr = __shfl(r2, o, WAVE);
+        bool hit = false;
+        if ((uint32_t)lane < total) {
+            const uint32_t e = base + (uint32_t)lane;
+            hit = sqdist(ox, oy, oz, PX[e], PY[e], PZ[e]) <= orr;
+        }
+        const uint64_t hm = __ballot(hit);
+        const uint32_t take = excl >= WAVE ? 0u : min(rem, (uint32_t)WAVE - excl);
+        if (hm) {
+            bool mine = false;
+            if (take) {
+                const uint64_t m = take >= WAVE ? ~0ull : ((1ull << take) - 1);
+                mine = ((hm >> excl) & m) != 0;
+            }
+            const uint64_t sh = __ballot(mine);
+            if (valid) done = done || (((sh >> (cfg * gg)) & gmask) != 0);
+        }
+        rem -= take;
+        pos += take;
+    }
+    return done;
+}
+
+__global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int g,
+                                uint8_t *__restrict__ out, int L) {
+    extern __shared__ float Tl[];
+    const int nT = (1 << L) - 1;
+    for (int i = threadIdx.x; i < nT; i += blockDim.x) Tl[i] = C.T[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (g <= WAVE) {
+        const int cpt = WAVE / g;                 // configurations per tile
+        const int64_t ncfg = nsph / g;
+        const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+        for (int64_t t = wid; t < ntiles; t += waves) {
+            const int64_t c0 = t * cpt;
+            const int nc = (int)min<int64_t>(cpt, ncfg - c0);
+            const bool hit = wave_tile(C, Tl, L, sph + c0 * g, nc * g, g);
+            if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
+        }
+    } else {
+        const int64_t ncfg = nsph / g;
+        for (int64_t c = wid; c < ncfg; c += waves) {
+            bool hit = false;
+            for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
+                const int ns = min(WAVE, g - s0);
+                hit = wave_tile(C, Tl, L, sph + c * g + s0, ns, g);
+                hit = __shfl(hit, 0, WAVE);
+            }
+            if (lane == 0) out[c] = (uint8_t)hit;
+        }
+    }
+}
+
+// One queue entry of the batched launch.
+struct Tile {
+    int32_t cloud;
+    int32_t ncfg;
+    int64_t cfg0;   // global configuration index (= output index)
+};
+
+__global__ void k_reset_counter(unsigned int *ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = 0u;
+}
+
+__global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
+                                  int64_t ntiles, unsigned int *__restrict__ ctr,
+                                  const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
+    const int lane = lane_id();
+    while (true) {
+        unsigned int t = 0;
+        if (lane == 0) t = atomicAdd(ctr, 1u);
+        t = __shfl(t, 0, WAVE);
+        if ((int64_t)t >= ntiles) break;
+        const Tile tile = tiles[t];
+        const CloudDev C = clouds[tile.cloud];
+        if (g <= WAVE) {
+            const int cpt = WAVE / g;
+            for (int c = 0; c < tile.ncfg; c += cpt) {
+                const int64_t c0 = tile.cfg0 + c;
+                const int nc = min(cpt, tile.ncfg - c);
+                const bool hit = wave_tile(C, nullptr, 0, sph + c0 * g, nc * g, g);
+                if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
+            }
+        } else {
+            for (int c = 0; c < tile.ncfg; ++c) {
+                const int64_t cc = tile.cfg0 + c;
+                bool hit = false;
+                for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
+                    const int ns = min(WAVE, g - s0);
+                    hit = wave_tile(C, nullptr, 0, sph + cc * g + s0, ns, g);
+                    hit = __shfl(hit, 0, WAVE);
+                }
+                if (lane == 0) out[cc] = (uint8_t)hit;
+            }
+        }
+    }
+}
+
+// GPU brute force: one wave per tile of spheres (as above); the cloud is
+// streamed in index order, 64 points per step (one per lane, broadcast with
+// readlane), same predicate; after every step a ballot retires the tile once
+// every configuration in it has been hit.
+__global__ void k_brute(const float *__restrict__ pts, int64_t n, const float4 *__restrict__ sph,
+                        int64_t nsph, int g, uint8_t *__restrict__ out) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t ncfg = nsph / g;
+    const int gg = g > WAVE ? WAVE : g;
+    const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
+    const int cpt = g > WAVE ? 1 : WAVE / g;
+    const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+    for (int64_t t = wid; t < ntiles; t += waves) {
+        const int64_t c0 = t * cpt;
+        const int nc = (int)min<int64_t>(cpt, ncfg - c0);
+        bool any_slice = false;                   // g > 64: configuration hit so far
+        const int nslice = g > WAVE ? (g + WAVE - 1) / WAVE : 1;
+        bool done = false;
+        for (int sl = 0; sl < nslice && !any_slice; ++sl) {
+            const int ns = g > WAVE ? min(WAVE, g - sl * WAVE) : nc * g;
+            const bool valid = lane < ns;
+            const int64_t s0 = c0 * g + (int64_t)sl * WAVE;
+            const float4 q = valid ? sph[s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float r2 = __fmul_rn(q.w, q.w);
+            const int cfg = g > WAVE ? 0 : lane / gg;
+            bool hit = false;
+            for (int64_t j0 = 0; j0 < n; j0 += WAVE) {
+                const int64_t j = j0 + lane;
+                float x = INFINITY, y = INFINITY, z = INFINITY;
+                if (j < n) {
+                    x = pts[3 * j];
+                    y = pts[3 * j + 1];
+                    z = pts[3 * j + 2];
+                }
+                const int cnt = (int)min<int64_t>(WAVE, n - j0);
+                for (int k = 0; k < cnt; ++k) {
+                    const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+                    const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), k));
+                    const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z), k));
+                    hit = hit || (valid && sqdist(q.x, q.y, q.z, bx, by, bz) <= r2);
+                }
+                const uint64_t hm = __ballot(hit);
+                const bool cdone = valid && (((hm >> (cfg * gg)) & gmask) != 0);
+                if (__ballot(valid && !cdone) == 0) break;
+            }
+            const uint64_t hm = __ballot(hit);
+            done = valid && (((hm >> (cfg * gg)) & gmask) != 0);
+            any_slice = hm != 0;
+        }
+        if (g <= WAVE) {
+            if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)done;
+        } else if (lane == 0) {
+            out[c0] = (uint8_t)any_slice;
+        }
+    }
+}
+
+// Per-sphere work accounting (thread per sphere, not tuned).
+__global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_t nsph,
+                              int32_t *__restrict__ leaf_out, uint8_t *__restrict__ rej_out,
+                              int32_t *__restrict__ scanned_out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsph) return;
+    const float4 q = sph[s];
+    const float r2 = __fmul_rn(q.w, q.w);
+    const int64_t N = (int64_t)1 << C.D;
+    const uint32_t node = descend(q, nullptr, 0, C.T, C.D);
+    const uint32_t lf = node - (uint32_t)(N - 1);
+    const Leaf L = C.leaf[lf];
+    const bool rej = L.count == 0 || box_sqdist(q.x, q.y, q.z, L.lo, L.hi) > r2;
+    int32_t m = 0;
+    if (!rej) {
+        for (uint32_t k = 0; k < L.count; ++k) {
+            ++m;
+            const uint32_t e = L.start + k;
+            if (sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2) break;
+        }
+    }
+    if (leaf_out) leaf_out[s] = (int32_t)lf;
+    if (rej_out) rej_out[s] = (uint8_t)rej;
+    if (scanned_out) scanned_out[s] = m;
+}
+
+__global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r_min, float r_max,
+                              unsigned int *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned int b = 0;
+    for (; i < m; i += stride) {
+        const float r = sph[i].w;
+        b += !(r >= r_min && r <= r_max);
+    }
+    if (b) atomicAdd(bad, b);
+}
+
+}  // namespace
+
+capt_tuning &tuning() {
+    static capt_tuning t = {16, 2, 64, 14};
+    return t;
+}
+
+struct BatchPlan {
+    const float *spheres = nullptr;
+    uint8_t *out = nullptr;
+    int32_t group = 0;
+    std::vector<int64_t> qoff;
+    capt_tuning tun{};
+    Tile *d_tiles = nullptr;
+    unsigned int *d_ctr = nullptr;
+    int64_t ntiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+void free_plan(BatchPlan *p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();   // a replay may still read the tile queue
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_tiles) dev_free(p->d_tiles, nullptr);
+    if (p->d_ctr) dev_free(p->d_ctr, nullptr);
+    delete p;
+}
+
+namespace {
+
+int lds_levels_for(int D) {
+    int L = std::min(D, std::max(0, std::min(14, (int)tuning().lds_levels)));
+    const size_t cap = (size_t)device_info().lds_per_block;
+    while (L > 0 && sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
+    return L;
+}
+
+capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
+                         hipStream_t s) {
+    if (nsph <= 0) return CAPT_OK;
+    const capt_tuning &t = tuning();
+    const int L = lds_levels_for(C.D);
+    const int threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
+    const int64_t ncfg = nsph / g;
+    const int cpt = g <= WAVE ? WAVE / g : 1;
+    const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+    const int64_t wpb = threads / WAVE;
+    int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
+    blocks = std::max<int64_t>(1, std::min(blocks, (ntiles + wpb - 1) / wpb));
+    const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
+    hipLaunchKernelGGL(k_collide_cloud, dim3((unsigned)blocks), dim3(threads), lds, s, C,
+                       reinterpret_cast<const float4 *>(spheres), nsph, g, out, L);
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
+}
+
+capt_status make_plan(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, uint8_t *out,
+                      BatchPlan *p) {
+    const int nc = (int)f->clouds.size();
+    const capt_tuning &t = tuning();
+    const int tile_cfgs = std::max(1, (int)t.tile_cfgs);
+    std::vector<Tile> tiles;
+    std::vector<double> cost;
+    for (int c = 0; c < nc; ++c) {
+        const int64_t c0 = qoff[c] / g, c1 = qoff[c + 1] / g;
+        const CloudHost &H = f->clouds[c];
+        // per-configuration cost estimate: descent plus a mean set scan
+        const double per = (double)H.D + (double)H.set_total / (double)H.N;
+        for (int64_t k = c0; k < c1; k += tile_cfgs) {
+            Tile tl;
+            tl.cloud = c;
+            tl.cfg0 = k;
+            tl.ncfg = (int32_t)std::min<int64_t>(tile_cfgs, c1 - k);
+            tiles.push_back(tl);
+            cost.push_back(per * tl.ncfg);
+        }
+    }
+    std::vector<size_t> order(tiles.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<Tile> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    p->ntiles = (int64_t)sorted.size();
+    const size_t tb = sizeof(Tile) * std::max<size_t>(1, sorted.size());
+    p->d_tiles = static_cast<Tile *>(dev_alloc(tb, nullptr));
+    p->d_ctr = static_cast<unsigned int *>(dev_alloc(256, nullptr));
+    if (!p->d_tiles || !p->d_ctr) {
+        set_error("device allocation for the tile queue failed");
+        return CAPT_ENOMEM;
+    }
+    if (!sorted.empty()) CAPT_HIP(hipMemcpy(p->d_tiles, sorted.data(), sizeof(Tile) * sorted.size(), hipMemcpyHostToDevice));
+    p->spheres = spheres;
+    p->out = out;
+    p->group = g;
+    p->qoff.assign(qoff, qoff + nc + 1);
+    p->tun = t;
+    return CAPT_OK;
+}
+
+capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
+    const capt_tuning &t = tuning();
+    const int threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
+    int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
+    const int64_t wpb = threads / WAVE;
+    blocks = std::max<int64_t>(1, std::min(blocks, (p->ntiles + wpb - 1) / wpb));
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p->d_ctr);
+    CAPT_LAUNCH_CHECK();
+    if (p->ntiles > 0) {
+        hipLaunchKernelGGL(k_collide_batched, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                           p->d_tiles, p->ntiles, p->d_ctr, reinterpret_cast<const float4 *>(p->spheres),
+                           p->group, p->out);
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+bool same_tuning(const capt_tuning &a, const capt_tuning &b) {
+    return a.waves_per_group == b.waves_per_group && a.groups_per_cu == b.groups_per_cu &&
+           a.tile_cfgs == b.tile_cfgs && a.lds_levels == b.lds_levels;
+}
+
+}  // namespace
+
+capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s) {
+    if (m <= 0) return CAPT_OK;
+    Scratch sc;
+    if (!sc.alloc(256, s)) {
+        set_error("device allocation failed");
+        return CAPT_ENOMEM;
+    }
+    CAPT_HIP(hipMemsetAsync(sc.p, 0, 4, s));
+    const int64_t blocks = std::min<int64_t>((m + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_radii, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const float4 *>(spheres), m, r_min, r_max, sc.as<unsigned int>());
+    CAPT_LAUNCH_CHECK();
+    unsigned int bad = 0;
+    CAPT_HIP(hipMemcpyAsync(&bad, sc.p, 4, hipMemcpyDeviceToHost, s));
+    CAPT_HIP(hipStreamSynchronize(s));
+    if (bad) {
+        set_error("%u query radii lie outside [r_min, r_max] = [%g, %g]", bad, (double)r_min, (double)r_max);
+        return CAPT_ERADIUS;
+    }
+    return CAPT_OK;
+}
+
+capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, uint8_t *out,
+                     uint32_t flags, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    if (flags & CAPT_CHECK_RADII) {
+        capt_status st = check_radii(spheres, qoff[nc], f->r_min, f->r_max, s);
+        if (st) return st;
+    }
+    if (nc == 1 || (flags & CAPT_PER_CLOUD)) {
+        for (int c = 0; c < nc; ++c) {
+            const int64_t m = qoff[c + 1] - qoff[c];
+            capt_status st = launch_cloud(f->clouds[c].dev, spheres + 4 * qoff[c], m, g, out + qoff[c] / g, s);
+            if (st) return st;
+        }
+        return CAPT_OK;
+    }
+    BatchPlan *p = f->plan;
+    const bool reuse = p && p->spheres == spheres && p->out == out && p->group == g &&
+                       std::equal(p->qoff.begin(), p->qoff.end(), qoff) && same_tuning(p->tun, tuning());
+    if (!reuse) {
+        free_plan(f->plan);
+        f->plan = nullptr;
+        p = new BatchPlan();
+        capt_status st = make_plan(f, spheres, qoff, g, out, p);
+        if (st) {
+            free_plan(p);
+            return st;
+        }
+        f->plan = p;
+    }
+    if (flags & CAPT_NO_GRAPH) return enqueue_batched(f, p, s);
+    if (!p->exec) {
+        CAPT_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        CAPT_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+        capt_status st = enqueue_batched(f, p, p->cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap, &graph);
+        if (st) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        CAPT_HIP(e);
+        p->graph = graph;
+        CAPT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    }
+    CAPT_HIP(hipGraphLaunch(p->exec, s));
+    return CAPT_OK;
+}
+
+capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t *leaf,
+                        uint8_t *rejected, int32_t *scanned, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        const int64_t o = qoff[c];
+        hipLaunchKernelGGL(k_query_stats, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, f->clouds[c].dev,
+                           reinterpret_cast<const float4 *>(spheres + 4 * o), m, leaf ? leaf + o : nullptr,
+                           rejected ? rejected + o : nullptr, scanned ? scanned + o : nullptr);
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+capt_status bruteforce(const float *xyz, const int64_t *cloud_off, int32_t ncloud, const float *spheres,
+                       const int64_t *qoff, int32_t g, uint8_t *out, hipStream_t s) {
+    for (int c = 0; c < ncloud; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        const int64_t n = cloud_off[c + 1] - cloud_off[c];
+        const int64_t ncfg = m / g;
+        const int cpt = g <= WAVE ? WAVE / g : 1;
+        const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+        const int threads = 256;
+        int64_t blocks = std::min<int64_t>((ntiles + 3) / 4, (int64_t)device_info().cus * 8);
+        blocks = std::max<int64_t>(blocks, 1);
+        hipLaunchKernelGGL(k_brute, dim3((unsigned)blocks), dim3(threads), 0, s, xyz + 3 * cloud_off[c], n,
+                           reinterpret_cast<const float4 *>(spheres + 4 * qoff[c]), m, g, out + qoff[c] / g);
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+}  // namespace capt

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+symbol declared in include/capt.h is exported, and argument validation
+rejects bad calls with CAPT_EINVAL before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2406_02807_amd as capt
+    if not os.path.exists(capt.LIB_PATH):
+        from paper_2406_02807_amd import build_lib
+        build_lib.build()
+    return capt.load_library()
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "capt.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:capt_status|void|const char \*)\s*(capt_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_five_hot_path_calls():
+    names = declared_symbols()
+    for n in ["capt_filter", "capt_build", "capt_collides", "capt_clearance", "capt_clearance_backward"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_2406_02807_amd as capt
+    names = declared_symbols()
+    assert sorted(names) == sorted(capt.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_no_gpu_needed_for_validation(lib):
+    import paper_2406_02807_amd as capt
+    P = C.c_void_p
+    h = C.c_void_p()
+    off = np.array([0, 10], np.int64)
+    offp = off.ctypes.data_as(P)
+    # NULL output handle
+    assert lib.capt_build(P(1), offp, 1, 0.01, 0.05, 0, None, None) == capt.CAPT_EINVAL
+    # r_min > r_max, negative radius, NaN radius
+    assert lib.capt_build(P(1), offp, 1, 0.06, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert lib.capt_build(P(1), offp, 1, -0.01, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert lib.capt_build(P(1), offp, 1, 0.0, float("nan"), 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert b"r_min" in lib.capt_last_error()
+    # non-monotone offsets, bad first offset, zero clouds, NULL points
+    bad = np.array([0, 5, 3], np.int64)
+    assert lib.capt_build(P(1), bad.ctypes.data_as(P), 2, 0.0, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    bad0 = np.array([1, 5], np.int64)
+    assert lib.capt_build(P(1), bad0.ctypes.data_as(P), 1, 0.0, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert lib.capt_build(P(1), offp, 0, 0.0, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert lib.capt_build(None, offp, 1, 0.0, 0.05, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    # unknown flag
+    assert lib.capt_build(P(1), offp, 1, 0.0, 0.05, 0x80, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert h.value is None
+    # queries on a NULL forest
+    q = np.array([0, 60], np.int64)
+    assert lib.capt_collides(None, P(1), q.ctypes.data_as(P), 60, P(1), 0, None) == capt.CAPT_EINVAL
+    assert lib.capt_clearance(None, P(1), q.ctypes.data_as(P), P(1), P(1), None) == capt.CAPT_EINVAL
+    # filter: negative / NaN radius, NULL count
+    n_out = C.c_int64()
+    assert lib.capt_filter(P(1), 10, -1.0, P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
+    assert lib.capt_filter(P(1), 10, float("nan"), P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
+    assert lib.capt_filter(P(1), 10, 0.01, P(1), None, None, None) == capt.CAPT_EINVAL
+    # brute force: group not dividing the range
+    q7 = np.array([0, 7], np.int64)
+    assert lib.capt_bruteforce_collides(P(1), offp, 1, P(1), q7.ctypes.data_as(P), 2, P(1), None) == capt.CAPT_EINVAL
+    # import: garbage blob
+    junk = C.create_string_buffer(b"\x00" * 64, 64)
+    assert lib.capt_import(junk, 64, None, C.byref(h)) == capt.CAPT_EINVAL
+    # tuning ranges
+    t = capt.capt_tuning(17, 0, 0, 0)
+    assert lib.capt_set_tuning(C.byref(t)) == capt.CAPT_EINVAL
+    # allocator: both or neither
+    assert lib.capt_set_allocator(P(1), None, None) == capt.CAPT_EINVAL
+    assert lib.capt_set_allocator(None, None, None) == capt.CAPT_OK
+
+
+def test_blob_roundtrip_pack_parse():
+    import paper_2406_02807_amd as capt
+    rng = np.random.default_rng(0)
+    pts = rng.random((5, 3)).astype(np.float32)
+    N = 8
+    T = rng.random(N - 1).astype(np.float32)
+    rep = np.arange(N, dtype=np.int32)
+    aabb = rng.random((N, 6)).astype(np.float32)
+    pr = np.zeros(N, np.uint8)
+    off = np.array([0, 1, 2, 3, 4, 5, 5, 5, 5], np.int64)
+    idx = np.arange(5, dtype=np.int32)
+    b = capt.make_blob(pts, T, rep, aabb, pr, off, idx, 0.01, 0.05)
+    p = capt.parse_blob(b)
+    assert (p.n, p.N, p.D) == (5, 8, 3)
+    assert np.array_equal(p.points, pts) and np.array_equal(p.T, T) and np.array_equal(p.idx, idx)
+    assert np.array_equal(p.aabb, aabb) and np.array_equal(p.off, off)
+
+
+def test_product_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2406_02807_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "capt_oracle" not in txt, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2406_02807_amd" not in txt and "capt_internal" not in txt, f

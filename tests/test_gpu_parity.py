@@ -1,0 +1,310 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle.
+
+Booleans, tree arrays, set memberships and filter outputs must match bit for
+bit; clearance values and gradients within 1e-4 (relative) of the float64
+oracle.  Sizes span several tiles and ragged tails; the full-size workloads
+are checked on sampled outputs (oracle) and on all outputs through
+properties (CAPT answers equal the GPU brute force, Lemma 1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from cases import adversarial_clouds, mixed_queries, nonfinite_queries
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def capt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_02807_amd as capt
+    capt.load_library()
+    return capt
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def canonical_sets(off, idx):
+    """Sort every leaf's entries so sets compare as sets."""
+    sizes = np.diff(off)
+    leaf = np.repeat(np.arange(len(sizes)), sizes)
+    order = np.lexsort((idx, leaf))
+    return sizes, idx[order]
+
+
+def compare_build(capt, orc, pts, r_min, r_max, prune=True):
+    f = capt.capt_build(dev(pts), r_min, r_max, prune=prune)
+    b = capt.parse_blob(capt.capt_export(f))
+    t = orc.build_tree(pts, r_min, r_max, prune=prune)
+    assert (b.n, b.N, b.D) == (t.n, t.N, t.D)
+    assert np.array_equal(bits(b.T), bits(t.T)), "split values differ"
+    assert np.array_equal(b.rep, t.rep), "representatives differ"
+    assert np.array_equal(b.pruned, t.pruned), "pruned leaves differ"
+    sg, ig = canonical_sets(b.off, b.idx)
+    so, io = canonical_sets(t.off, t.idx)
+    assert np.array_equal(sg, so), "set sizes differ"
+    assert np.array_equal(ig, io), "set members differ"
+    assert np.array_equal(bits(b.aabb), bits(t.aabb)), "AABBs differ"
+    return f, b, t
+
+
+# ---------------------------------------------------------------------------
+# Query on an imported oracle tree (isolates the query from the build)
+# ---------------------------------------------------------------------------
+def test_query_imported_oracle_tree_uniform(capt, orc):
+    w = synth.workload(1)
+    _say("case: uniform-2k imported, 100000 spheres")
+    t = orc.build_tree(w.cloud, w.r_min, w.r_max)
+    f = capt.capt_import(capt.make_blob(w.cloud, t.T, t.rep, t.aabb, t.pruned, t.off, t.idx, w.r_min, w.r_max))
+    got = capt.capt_collides(f, dev(w.spheres), 1).cpu().numpy()
+    want = orc.brute_f32(w.cloud, w.spheres)
+    assert np.array_equal(got, want)
+    assert 0.05 < want.mean() < 0.95
+
+
+@pytest.mark.parametrize("name", sorted(adversarial_clouds()))
+def test_query_imported_adversarial(capt, orc, name):
+    pts = adversarial_clouds()[name]
+    for (r_min, r_max) in [(0.01, 0.05), (0.0, 0.03), (0.02, 0.02)]:
+        _say(f"case: imported {name} r=({r_min},{r_max})")
+        t = orc.build_tree(pts, r_min, r_max)
+        f = capt.capt_import(capt.make_blob(pts, t.T, t.rep, t.aabb, t.pruned, t.off, t.idx, r_min, r_max))
+        sph = mixed_queries(pts, max(r_min, 1e-3), r_max, 3000, 11, tree=t)
+        sph = np.concatenate([sph, nonfinite_queries(r_max)])
+        want = orc.brute_f32(pts, sph)
+        for g in (1, 3):
+            m = len(sph) - len(sph) % g
+            got = capt.capt_collides(f, dev(sph[:m]), g).cpu().numpy()
+            assert np.array_equal(got, want[:m].reshape(-1, g).max(1)), (name, g)
+
+
+# ---------------------------------------------------------------------------
+# Build parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(adversarial_clouds()))
+def test_build_matches_oracle_adversarial(capt, orc, name):
+    pts = adversarial_clouds()[name]
+    for (r_min, r_max, prune) in [(0.01, 0.05, True), (0.0, 0.03, True), (0.05, 0.06, True),
+                                  (0.05, 0.06, False)]:
+        _say(f"case: build {name} r=({r_min},{r_max}) prune={prune}")
+        compare_build(capt, orc, pts, r_min, r_max, prune)
+
+
+def test_build_matches_oracle_uniform_2k(capt, orc):
+    w = synth.workload(1)
+    _say("case: build uniform-2k")
+    f, b, t = compare_build(capt, orc, w.cloud, w.r_min, w.r_max)
+    got = capt.capt_collides(f, dev(w.spheres), 1).cpu().numpy()
+    assert np.array_equal(got, orc.brute_f32(w.cloud, w.spheres))
+
+
+def test_build_matches_oracle_tabletop_filtered(capt, orc):
+    cloud = synth.tabletop_cloud(50_000, 2001)
+    keep, _ = orc.filter(cloud, 0.01)
+    pts = cloud[keep]
+    _say(f"case: build tabletop filtered n={len(pts)}")
+    compare_build(capt, orc, pts, 0.015, 0.08)
+    compare_build(capt, orc, pts, 0.0, 0.08)
+
+
+def test_build_empty_cloud(capt, orc):
+    _say("case: build empty")
+    f = capt.capt_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda"), 0.01, 0.05)
+    b = capt.parse_blob(capt.capt_export(f))
+    assert (b.n, b.N, len(b.idx)) == (0, 1, 0)
+    sph = dev(np.array([[0, 0, 0, 0.05]] * 64, np.float32))
+    assert capt.capt_collides(f, sph, 1).cpu().numpy().sum() == 0
+
+
+def test_build_rejects_nonfinite(capt):
+    pts = np.random.default_rng(0).random((100, 3)).astype(np.float32)
+    pts[17, 1] = np.nan
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_build(dev(pts), 0.01, 0.05)
+    assert e.value.status == capt.CAPT_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# End-to-end query with configuration groups
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [1, 7, 60, 64, 100])
+def test_collides_groups_tabletop(capt, orc, g):
+    pts = synth.tabletop_cloud(12_000, 91)
+    _say(f"case: collides tabletop-12k g={g}")
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    if g == 60:
+        sph = synth.posed_spheres(synth.chain_template(2003), 3001, synth.WORKSPACE, 92)
+    else:
+        sph = synth.uniform_spheres(g * 1501, synth.WORKSPACE, 0.015, 0.08, 93)
+    got = capt.capt_collides(f, dev(sph), g).cpu().numpy()
+    want = orc.brute_f32(pts, sph, g)
+    assert np.array_equal(got, want)
+    assert 0 < want.sum() < len(want)
+
+
+def test_check_radii_flag(capt):
+    pts = synth.tabletop_cloud(2000, 5)
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    sph = synth.uniform_spheres(640, synth.WORKSPACE, 0.015, 0.08, 6)
+    capt.capt_collides(f, dev(sph), 1, flags=capt.CAPT_CHECK_RADII)
+    sph[100, 3] = 0.2
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_collides(f, dev(sph), 1, flags=capt.CAPT_CHECK_RADII)
+    assert e.value.status == capt.CAPT_ERADIUS
+
+
+def test_query_stats_match_oracle_replay(capt, orc):
+    pts = synth.tabletop_cloud(8000, 41)
+    _say("case: query stats")
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    b = capt.parse_blob(capt.capt_export(f))
+    sph = synth.uniform_spheres(20_000, synth.WORKSPACE, 0.015, 0.08, 42)
+    leaf, rej, sc = [x.cpu().numpy() for x in capt.capt_query_stats(f, dev(sph))]
+    hit, leaf_o, rej_o, sc_o = orc.query(b.N, b.D, b.T, b.aabb, b.off, b.points[b.idx], sph)
+    assert np.array_equal(leaf, leaf_o) and np.array_equal(rej, rej_o) and np.array_equal(sc, sc_o)
+    assert np.array_equal(hit, orc.brute_f32(pts, sph))
+
+
+# ---------------------------------------------------------------------------
+# GPU brute force (the benchmark's baseline) is exact too
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [1, 60, 100])
+def test_bruteforce_matches_oracle(capt, orc, g):
+    pts = synth.tabletop_cloud(5000, 51)
+    _say(f"case: brute g={g}")
+    sph = synth.uniform_spheres(g * 700, synth.WORKSPACE, 0.015, 0.08, 52)
+    got = capt.capt_bruteforce_collides(dev(pts), dev(sph), g).cpu().numpy()
+    assert np.array_equal(got, orc.brute_f32(pts, sph, g))
+
+
+# ---------------------------------------------------------------------------
+# Filter parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,rf", [("tabletop-50k", 0.01), ("tabletop-50k", 0.03), ("uniform-1000", 0.05),
+                                     ("dups-300", 0.0), ("identical-64", 0.01), ("single", 0.01),
+                                     ("collinear-129", 0.004), ("negzero", 0.001), ("room-60k", 0.005)])
+def test_filter_matches_oracle(capt, orc, name, rf):
+    if name == "tabletop-50k":
+        pts = synth.tabletop_cloud(50_000, 2001)
+    elif name == "room-60k":
+        pts = synth.room_cloud(54_000, 6_000, 5001)
+    else:
+        pts = adversarial_clouds()[name]
+    _say(f"case: filter {name} rf={rf}")
+    kept, _ = orc.filter(pts, rf)
+    out, idx = capt.capt_filter(dev(pts), rf)
+    assert np.array_equal(idx.cpu().numpy(), kept)
+    assert np.array_equal(bits(out.cpu().numpy()), bits(pts[kept]))
+
+
+# ---------------------------------------------------------------------------
+# Batched ragged forests
+# ---------------------------------------------------------------------------
+def test_batched_matches_per_cloud_and_oracle(capt, orc):
+    w = synth.workload(3, scale=0.02)
+    _say(f"case: batched {len(w.cloud)} clouds, {sum(len(s) for s in w.spheres)} spheres")
+    cloud_off = np.concatenate([[0], np.cumsum([len(c) for c in w.cloud])])
+    query_off = np.concatenate([[0], np.cumsum([len(s) for s in w.spheres])])
+    xyz = dev(np.concatenate(w.cloud))
+    sph = dev(np.concatenate(w.spheres))
+    f = capt.capt_build(xyz, w.r_min, w.r_max, cloud_off=cloud_off)
+    a = capt.capt_collides(f, sph, 60, query_off=query_off).cpu().numpy()
+    b = capt.capt_collides(f, sph, 60, query_off=query_off, flags=capt.CAPT_PER_CLOUD).cpu().numpy()
+    c = capt.capt_collides(f, sph, 60, query_off=query_off, flags=capt.CAPT_NO_GRAPH).cpu().numpy()
+    # graph replay gives the same answer again
+    d = capt.capt_collides(f, sph, 60, query_off=query_off).cpu().numpy()
+    br = capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off, query_off=query_off).cpu().numpy()
+    want = np.concatenate([orc.brute_f32(w.cloud[i], w.spheres[i], 60) for i in range(len(w.cloud))])
+    for x in (a, b, c, d, br):
+        assert np.array_equal(x, want)
+
+
+# ---------------------------------------------------------------------------
+# Clearance and its gradient
+# ---------------------------------------------------------------------------
+def test_clearance_and_gradient(capt, orc):
+    cloud = synth.tabletop_cloud(50_000, 2001)
+    keep, _ = orc.filter(cloud, 0.01)
+    pts = cloud[keep]
+    r_max = 0.08
+    sph = synth.uniform_spheres(6000, synth.WORKSPACE, 0.015, 0.08, 4002)
+    _say("case: clearance")
+    f = capt.capt_build(dev(pts), 0.0, r_max)
+    s = dev(sph).requires_grad_(True)
+    clr, wit = capt.clearance(f, s)
+    loss = torch.nn.functional.softplus(-clr / 0.01).sum()
+    loss.backward()
+    clr_o, wit_o, grad_o = orc.clearance_f64(pts, sph, r_max)
+    c = clr.detach().cpu().numpy().astype(np.float64)
+    assert (np.abs(c - clr_o) <= 1e-4 * np.maximum(np.abs(clr_o), r_max)).all()
+    w = wit.cpu().numpy()
+    P = pts.astype(np.float64)
+    x = sph[:, :3].astype(np.float64)
+    same = w == wit_o
+    # a different witness must be an equally near point (within 1e-6 m)
+    for i in np.where(~same)[0]:
+        if w[i] < 0 or wit_o[i] < 0:
+            d = np.sqrt(((x[i] - P[max(w[i], wit_o[i])]) ** 2).sum())
+            assert abs(d - r_max) < 1e-6
+        else:
+            assert abs(np.linalg.norm(x[i] - P[w[i]]) - np.linalg.norm(x[i] - P[wit_o[i]])) < 1e-6
+    assert same.mean() > 0.99
+    # analytic gradient of the loss in float64 from the oracle
+    z = -clr_o / 0.01
+    dl = -1.0 / (1.0 + np.exp(-z)) / 0.01
+    g_ref = np.concatenate([grad_o * dl[:, None], -dl[:, None]], 1)
+    g = s.grad.cpu().numpy().astype(np.float64)
+    ok = same
+    err = np.linalg.norm(g[ok] - g_ref[ok], axis=1)
+    assert (err <= 1e-4 * np.linalg.norm(g_ref[ok], axis=1) + 1e-6).all()
+
+
+def test_clearance_rejects_pruned_forest(capt):
+    pts = adversarial_clouds()["lattice-216"]
+    f = capt.capt_build(dev(pts), 0.05, 0.06)
+    if f.info()["pruned"] == 0:
+        pytest.skip("no leaf pruned")
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_clearance(f, dev(np.zeros((4, 4), np.float32) + 0.05))
+    assert e.value.status == capt.CAPT_EPRUNED
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+def test_full_size_tabletop_1M_configurations(capt, orc):
+    w = synth.workload(2)
+    _say("case: full tabletop 1M configurations")
+    xyz = dev(w.cloud)
+    fx, fidx = capt.capt_filter(xyz, w.r_filter)
+    keep, _ = orc.filter(w.cloud, w.r_filter)
+    assert np.array_equal(fidx.cpu().numpy(), keep)
+    f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+    sph = dev(w.spheres)
+    got = capt.capt_collides(f, sph, 60).cpu().numpy()
+    # every answer against the GPU brute force (Lemma 1 at full size)
+    br = capt.capt_bruteforce_collides(fx.contiguous(), sph, 60).cpu().numpy()
+    assert np.array_equal(got, br)
+    # sampled answers against the oracle
+    rng = np.random.default_rng(1)
+    cfg = np.sort(rng.choice(len(got), 1500, replace=False))
+    sub = w.spheres.reshape(-1, 60, 4)[cfg].reshape(-1, 4)
+    want = orc.brute_f32(w.cloud[keep], sub, 60)
+    assert np.array_equal(got[cfg], want)
