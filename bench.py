@@ -1,0 +1,350 @@
+"""Benchmark of the CAPT hot path on one MI355X.
+
+Workload (the tabletop scene): 50,000 points on 24 boxes and 8 cylinders in a
+2 x 2 x 1.5 m workspace with 2 mm noise, Morton filter at r_filter = 1 cm,
+CAPT with r_min = 0.015, r_max = 0.08, then 1,000,000 robot configurations of
+60 spheres each (rigid random poses of a seeded chain template), one boolean
+per configuration with early exit.
+
+One step = filter -> build -> collide, the whole collision path, on inputs
+already resident in HBM.  `value` is sphere queries per second over the whole
+step (60,000,000 spheres / step time).  Printed as one JSON line, with:
+  roofline      the query kernel's algorithmic bytes (per configuration: the
+                spheres, leaf records and set entries a sequential scan in
+                stored order reads up to the first colliding sphere) over its
+                HIP-event-timed duration, against 8 TB/s
+  cpu_baseline  the oracle's filter + build + CollisionCheck (one thread, early
+                exit per configuration) on the same workload
+  brute         the GPU brute force on the same spheres (answers compared)
+and, unless --no-extras, the batched ragged workload (64 clouds, one
+persistent launch vs one launch per cloud vs GPU brute force) and the
+clearance forward/backward workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sphere collision queries/sec (ns/query) on 1 GPU vs GPU brute force, bit-exact"
+HBM_PEAK_GBS = 8000.0
+LEAF_BYTES = 32      # AABB (24 B) + set start and length (8 B)
+SPHERE_BYTES = 16
+ENTRY_BYTES = 12     # x, y, z of one set entry
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(capt, forest, spheres_dev, group):
+    """Sum over configurations of the bytes a sequential scan in stored order
+    reads up to (and including) the first colliding sphere, plus one output
+    byte per configuration."""
+    import torch
+    leaf, rej, scanned = capt.capt_query_stats(forest, spheres_dev)
+    hit = capt.capt_collides(forest, spheres_dev, 1)
+    torch.cuda.synchronize()
+    rej = rej.cpu().numpy().astype(np.int64)
+    sc = scanned.cpu().numpy().astype(np.int64)
+    hit = hit.cpu().numpy().astype(bool)
+    per = SPHERE_BYTES + LEAF_BYTES + ENTRY_BYTES * np.where(rej == 1, 0, sc)
+    per = per.reshape(-1, group)
+    h = hit.reshape(-1, group)
+    first = np.where(h.any(1), h.argmax(1), group - 1)
+    mask = np.arange(group)[None, :] <= first[:, None]
+    canonical = int((per * mask).sum()) + h.shape[0]
+    return canonical, {
+        "aabb_reject_rate": float(rej.mean()),
+        "mean_scanned_per_sphere": float(sc.mean()),
+        "spheres_read_canonical": int(mask.sum()),
+    }
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per launch measured with rocprofv3 counters (committed under
+    profiles/), or None when missing or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_collide_cloud_tabletop_traffic.json")
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for f in ("query.hip", "capt_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2406_02807_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def cpu_baseline(w, group, n_cfg_sample):
+    import oracle
+    t0 = time.perf_counter()
+    keep, _ = oracle.filter(w.cloud, w.r_filter)
+    pts = w.cloud[keep]
+    tree = oracle.build_tree(pts, w.r_min, w.r_max)
+    t1 = time.perf_counter()
+    sph = w.spheres[: n_cfg_sample * group]
+    out = oracle.query_serial(tree.N, tree.D, tree.T, tree.aabb, tree.off, pts[tree.idx], sph, group)
+    t2 = time.perf_counter()
+    total_cfg = len(w.spheres) // group
+    est = (t1 - t0) + (t2 - t1) * total_cfg / n_cfg_sample
+    return {
+        "value": len(w.spheres) / est,
+        "unit": "queries/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle filter + build on the full 50,000-point cloud ({t1 - t0:.2f} s) and "
+                   f"single-thread CollisionCheck with per-configuration early exit on the first "
+                   f"{n_cfg_sample:,} of {total_cfg:,} configurations ({t2 - t1:.2f} s), scaled to the "
+                   f"full workload"),
+        "ns_per_query_query_only": (t2 - t1) / len(sph) * 1e9,
+    }, out
+
+
+def bench_batched(capt, torch, reps=5):
+    import synth
+    w = synth.workload(3)
+    cloud_off = np.concatenate([[0], np.cumsum([len(c) for c in w.cloud])])
+    query_off = np.concatenate([[0], np.cumsum([len(s) for s in w.spheres])])
+    xyz = torch.from_numpy(np.concatenate(w.cloud)).cuda()
+    sph = torch.from_numpy(np.concatenate(w.spheres)).cuda()
+    f = capt.capt_build(xyz, w.r_min, w.r_max, cloud_off=cloud_off)
+    out = torch.empty(len(sph) // 60, dtype=torch.uint8, device="cuda")
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    t_batch = timed(lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out), reps)
+    res_batch = out.clone()
+    t_per = timed(lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out,
+                                             flags=capt.CAPT_PER_CLOUD), reps)
+    t_brute = timed(lambda: capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off,
+                                                          query_off=query_off), 1)
+    br = capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off, query_off=query_off)
+    exact = bool(torch.equal(br, res_batch))
+    m = len(sph)
+    f.close()
+    return {
+        "workload": "64 clouds of 1e3-2e5 points (log-uniform), 1e4-2e6 spheres each in 60-sphere "
+                    "configurations, r_min = 0.015, r_max = 0.08",
+        "spheres": m,
+        "cloud_points": int(cloud_off[-1]),
+        "batched_ms": t_batch,
+        "per_cloud_ms": t_per,
+        "brute_per_cloud_ms": t_brute,
+        "batched_queries_per_s": m / (t_batch * 1e-3),
+        "speedup_vs_brute": t_brute / t_batch,
+        "speedup_vs_per_cloud_launch": t_per / t_batch,
+        "exact_vs_brute": exact,
+    }
+
+
+def bench_clearance(capt, torch, pts_dev, reps=5):
+    import synth
+    w = synth.workload(4)
+    f = capt.capt_build(pts_dev, 0.0, w.r_max)
+    sph = torch.from_numpy(w.spheres).cuda()
+    clr, wit = capt.capt_clearance(f, sph)
+    g = torch.ones_like(clr)
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    for _ in range(reps):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record()
+        clr, wit = capt.capt_clearance(f, sph)
+        b.record()
+        capt.capt_clearance_backward(f, sph, wit, g)
+        c.record()
+        torch.cuda.synchronize()
+        tf.append(a.elapsed_time(b))
+        tb.append(b.elapsed_time(c))
+    f.close()
+    m = len(sph)
+    return {
+        "workload": "tabletop cloud after the 1 cm filter, unpruned CAPT (r_max = 0.08), "
+                    "1,000,000 spheres uniform in the workspace",
+        "forward_ms": float(np.median(tf)),
+        "backward_ms": float(np.median(tb)),
+        "forward_queries_per_s": m / (np.median(tf) * 1e-3),
+        "backward_bytes_per_s": 48 * m / (np.median(tb) * 1e-3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=200_000, help="configurations timed on the CPU")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-brute", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(queries shard by configuration with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2406_02807_amd as capt
+    import synth
+
+    capt.load_library()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.perf_counter()
+    w = synth.workload(2)
+    G = w.group
+    log(f"generated workload in {time.perf_counter() - t0:.1f} s: {len(w.cloud)} points, "
+        f"{len(w.spheres)} spheres")
+    xyz = torch.from_numpy(w.cloud).cuda()
+    sph = torch.from_numpy(w.spheres).cuda()
+    out = torch.empty(len(w.spheres) // G, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if ev is not None else None
+        if e:
+            e[0].record()
+        fx, _ = capt.capt_filter(xyz, w.r_filter)
+        if e:
+            e[1].record()
+        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+        if e:
+            e[2].record()
+        capt.capt_collides(f, sph, G, out=out)
+        if e:
+            e[3].record()
+            ev.append(e)
+        return f, fx
+
+    for _ in range(args.warmup):
+        f, fx = step()
+        f.close()
+    torch.cuda.synchronize()
+    events = []
+    forests = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        f, fx = step(events)
+        forests.append(f)
+        if len(forests) > 1:
+            forests.pop(0).close()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_step = t_total / args.steps * 1e3
+    filt = np.array([a.elapsed_time(b) for a, b, _, _ in events])
+    build = np.array([b.elapsed_time(c) for _, b, c, _ in events])
+    query = np.array([c.elapsed_time(d) for _, _, c, d in events])
+    m = len(w.spheres)
+    value = m / (t_total / args.steps)
+
+    forest, fx = forests[-1], fx
+    info = forest.info()
+    alg_bytes, alg = algorithmic_bytes(capt, forest, sph, G)
+    q_ms = float(query.mean())
+    achieved = alg_bytes / (q_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(src_hash())
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "tabletop-50k: 50,000 points on 24 boxes + 8 cylinders (2 mm noise) -> Morton "
+                        "filter r_filter = 0.01 -> CAPT r_min = 0.015, r_max = 0.08 -> 1,000,000 "
+                        "configurations x 60 spheres, one bool per configuration",
+            "points_in": len(w.cloud),
+            "points_after_filter": int(fx.shape[0]),
+            "tree_depth": info["D"],
+            "set_entries": info["set_total"],
+            "spheres": m,
+            "configurations": m // G,
+        },
+        "ns_per_query": ms_step * 1e6 / m,
+        "phase_ms": {"filter": float(filt.mean()), "build": float(build.mean()), "query": q_ms},
+        "query_only_queries_per_s": m / (q_ms * 1e-3),
+        "collision_rate": float(out.float().mean().item()),
+        "roofline": {
+            "kernel": "k_collide_cloud",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            **alg,
+        },
+    }
+    log(f"step {ms_step:.2f} ms: filter {filt.mean():.2f}, build {build.mean():.2f}, query {q_ms:.2f}")
+
+    if not args.no_brute:
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        br = capt.capt_bruteforce_collides(fx.contiguous(), sph, G)
+        b.record()
+        torch.cuda.synchronize()
+        tb = a.elapsed_time(b)
+        result["brute"] = {
+            "ms": tb,
+            "queries_per_s": m / (tb * 1e-3),
+            "capt_query_speedup": tb / q_ms,
+            "capt_step_speedup": tb / ms_step,
+            "exact": bool(torch.equal(br, out)),
+        }
+        log(f"brute force {tb:.1f} ms, exact {result['brute']['exact']}")
+    for f in forests:
+        f.close()
+
+    if not args.no_extras:
+        result["batched"] = bench_batched(capt, torch)
+        log(f"batched: {result['batched']}")
+        result["clearance"] = bench_clearance(capt, torch, fx.contiguous())
+        log(f"clearance: {result['clearance']}")
+
+    if not args.no_cpu:
+        cb, ref = cpu_baseline(w, G, min(args.cpu_sample, m // G))
+        result["cpu_baseline"] = cb
+        result["cpu_baseline_agrees"] = bool(np.array_equal(ref, out[: len(ref)].cpu().numpy()))
+        log(f"cpu baseline {cb['value']:.3g} queries/s")
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

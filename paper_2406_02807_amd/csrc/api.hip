@@ -458,7 +458,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
             }
         }
         for (int a = 0; a < 3; ++a)
-            if (memcmp(&lo[a], &aabb[6 * l + a], 4) != 0 || memcmp(&hi[a], &aabb[6 * l + 3 + a], 4) != 0) {
+            if (!(lo[a] == aabb[6 * l + a]) || !(hi[a] == aabb[6 * l + 3 + a])) {
                 set_error("blob AABB of leaf %lld is not the bounding box of its set", (long long)l);
                 return CAPT_EINVAL;
             }
