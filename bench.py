@@ -50,8 +50,7 @@ def algorithmic_bytes(capt, forest, spheres_dev, group):
     reads up to (and including) the first colliding sphere, plus one output
     byte per configuration."""
     import torch
-    leaf, rej, scanned = capt.capt_query_stats(forest, spheres_dev)
-    hit = capt.capt_collides(forest, spheres_dev, 1)
+    leaf, rej, scanned, hit = capt.capt_query_stats(forest, spheres_dev)
     torch.cuda.synchronize()
     rej = rej.cpu().numpy().astype(np.int64)
     sc = scanned.cpu().numpy().astype(np.int64)
@@ -203,7 +202,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(queries shard by configuration with no exchange; see DESIGN.md)", file=sys.stderr)

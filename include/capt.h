@@ -208,13 +208,14 @@ capt_status capt_bruteforce_collides(const float *xyz, const int64_t *cloud_off,
 
 /*
  * Work accounting for one collision query (not on the hot path): per sphere,
- * the leaf reached, whether the leaf AABB rejected it, and how many set
- * entries a scan in stored order tests before its first hit (the whole set
- * if none).  Any output may be NULL.
- *   leaf [M] int32, rejected [M] uint8, scanned [M] int32
+ * the leaf reached, whether the leaf AABB rejected it, how many set entries a
+ * scan in stored order tests up to and including its first hit (the whole set
+ * if none), and whether it hit.  Any output may be NULL.
+ *   leaf [M] int32, rejected [M] uint8, scanned [M] int32, hit [M] uint8
  */
 capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t *query_off,
-                             int32_t *leaf, uint8_t *rejected, int32_t *scanned, void *stream);
+                             int32_t *leaf, uint8_t *rejected, int32_t *scanned, uint8_t *hit,
+                             void *stream);
 
 /*
  * Launch shape of the batched collision kernel (chosen by the autotuner).

@@ -68,7 +68,7 @@ def load_library(path: str = LIB_PATH):
         "capt_import": [P, C.c_size_t, P, P],
         "capt_set_allocator": [P, P, P],
         "capt_bruteforce_collides": [P, P, i32, P, P, i32, P, P],
-        "capt_query_stats": [P, P, P, P, P, P, P],
+        "capt_query_stats": [P, P, P, P, P, P, P, P],
         "capt_set_tuning": [P],
         "capt_get_tuning": [P],
     }
@@ -259,7 +259,7 @@ def capt_bruteforce_collides(xyz, spheres, group: int = 1, cloud_off=None, query
 
 
 def capt_query_stats(forest: Forest, spheres, query_off=None, stream=None):
-    """Per sphere: (leaf int32, aabb_rejected uint8, scanned int32)."""
+    """Per sphere: (leaf int32, aabb_rejected uint8, scanned int32, hit uint8)."""
     import torch
     lib = load_library()
     spheres = _dev(spheres, torch.float32, 4, "spheres")
@@ -268,9 +268,10 @@ def capt_query_stats(forest: Forest, spheres, query_off=None, stream=None):
     leaf = torch.empty((M,), dtype=torch.int32, device=spheres.device)
     rej = torch.empty((M,), dtype=torch.uint8, device=spheres.device)
     sc = torch.empty((M,), dtype=torch.int32, device=spheres.device)
+    hit = torch.empty((M,), dtype=torch.uint8, device=spheres.device)
     _check(lib.capt_query_stats(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p),
-                                _ptr(leaf), _ptr(rej), _ptr(sc), _stream(stream)))
-    return leaf, rej, sc
+                                _ptr(leaf), _ptr(rej), _ptr(sc), _ptr(hit), _stream(stream)))
+    return leaf, rej, sc, hit
 
 
 def capt_set_tuning(waves_per_group=0, groups_per_cu=0, tile_cfgs=0, lds_levels=0):

@@ -587,11 +587,11 @@ capt_status capt_bruteforce_collides(const float *xyz, const int64_t *cloud_off,
 }
 
 capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t *query_off, int32_t *leaf,
-                             uint8_t *rejected, int32_t *scanned, void *stream) {
+                             uint8_t *rejected, int32_t *scanned, uint8_t *hit, void *stream) {
     ApiGuard g;
     capt_status st = check_queries(f, spheres, query_off, 1);
     if (st) return st;
-    return query_stats(f, spheres, query_off, leaf, rejected, scanned, (hipStream_t)stream);
+    return query_stats(f, spheres, query_off, leaf, rejected, scanned, hit, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -155,7 +155,7 @@ capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                      int32_t group, uint8_t *out, uint32_t flags, hipStream_t s);
 capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off,
-                        int32_t *leaf, uint8_t *rejected, int32_t *scanned, hipStream_t s);
+                        int32_t *leaf, uint8_t *rejected, int32_t *scanned, uint8_t *hit, hipStream_t s);
 capt_status bruteforce(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                        const float *spheres, const int64_t *query_off, int32_t group,
                        uint8_t *out, hipStream_t s);

@@ -274,7 +274,7 @@ __global__ void k_brute(const float *__restrict__ pts, int64_t n, const float4 *
 // Per-sphere work accounting (thread per sphere, not tuned).
 __global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_t nsph,
                               int32_t *__restrict__ leaf_out, uint8_t *__restrict__ rej_out,
-                              int32_t *__restrict__ scanned_out) {
+                              int32_t *__restrict__ scanned_out, uint8_t *__restrict__ hit_out) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nsph) return;
     const float4 q = sph[s];
@@ -285,16 +285,18 @@ __global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_
     const Leaf L = C.leaf[lf];
     const bool rej = L.count == 0 || box_sqdist(q.x, q.y, q.z, L.lo, L.hi) > r2;
     int32_t m = 0;
+    bool hit = false;
     if (!rej) {
-        for (uint32_t k = 0; k < L.count; ++k) {
+        for (uint32_t k = 0; k < L.count && !hit; ++k) {
             ++m;
             const uint32_t e = L.start + k;
-            if (sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2) break;
+            hit = sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2;
         }
     }
     if (leaf_out) leaf_out[s] = (int32_t)lf;
     if (rej_out) rej_out[s] = (uint8_t)rej;
     if (scanned_out) scanned_out[s] = m;
+    if (hit_out) hit_out[s] = (uint8_t)hit;
 }
 
 __global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r_min, float r_max,
@@ -507,7 +509,7 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
 }
 
 capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t *leaf,
-                        uint8_t *rejected, int32_t *scanned, hipStream_t s) {
+                        uint8_t *rejected, int32_t *scanned, uint8_t *hit, hipStream_t s) {
     const int nc = (int)f->clouds.size();
     for (int c = 0; c < nc; ++c) {
         const int64_t m = qoff[c + 1] - qoff[c];
@@ -515,7 +517,8 @@ capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *q
         const int64_t o = qoff[c];
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, f->clouds[c].dev,
                            reinterpret_cast<const float4 *>(spheres + 4 * o), m, leaf ? leaf + o : nullptr,
-                           rejected ? rejected + o : nullptr, scanned ? scanned + o : nullptr);
+                           rejected ? rejected + o : nullptr, scanned ? scanned + o : nullptr,
+                           hit ? hit + o : nullptr);
         CAPT_LAUNCH_CHECK();
     }
     return CAPT_OK;

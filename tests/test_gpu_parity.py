@@ -177,10 +177,10 @@ def test_query_stats_match_oracle_replay(capt, orc):
     f = capt.capt_build(dev(pts), 0.015, 0.08)
     b = capt.parse_blob(capt.capt_export(f))
     sph = synth.uniform_spheres(20_000, synth.WORKSPACE, 0.015, 0.08, 42)
-    leaf, rej, sc = [x.cpu().numpy() for x in capt.capt_query_stats(f, dev(sph))]
-    hit, leaf_o, rej_o, sc_o = orc.query(b.N, b.D, b.T, b.aabb, b.off, b.points[b.idx], sph)
+    leaf, rej, sc, hit = [x.cpu().numpy() for x in capt.capt_query_stats(f, dev(sph))]
+    hit_o, leaf_o, rej_o, sc_o = orc.query(b.N, b.D, b.T, b.aabb, b.off, b.points[b.idx], sph)
     assert np.array_equal(leaf, leaf_o) and np.array_equal(rej, rej_o) and np.array_equal(sc, sc_o)
-    assert np.array_equal(hit, orc.brute_f32(pts, sph))
+    assert np.array_equal(hit, hit_o) and np.array_equal(hit, orc.brute_f32(pts, sph))
 
 
 # ---------------------------------------------------------------------------
