@@ -38,10 +38,32 @@ capt_status hip_fail(hipError_t e, const char *what, const char *file, int line)
     return e == hipErrorOutOfMemory ? CAPT_ENOMEM : CAPT_EHIP;
 }
 
+namespace {
+// The default allocator is the device's stream-ordered pool; its release
+// threshold is raised once per device so freed blocks stay cached for the
+// next build instead of going back to the driver.
+void keep_pool_cached() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    done[dev] = true;
+}
+}  // namespace
+
 void *dev_alloc(size_t bytes, hipStream_t s) {
     if (g_alloc.alloc) return g_alloc.alloc(bytes, s, g_alloc.ctx);
+    keep_pool_cached();
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
@@ -54,7 +76,7 @@ void dev_free(void *p, hipStream_t s) {
         g_alloc.release(p, s, g_alloc.ctx);
         return;
     }
-    (void)hipFree(p);
+    (void)hipFreeAsync(p, s);
 }
 
 const DeviceInfo &device_info() {

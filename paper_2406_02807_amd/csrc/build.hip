@@ -253,197 +253,314 @@ __global__ void k_leaf_cells(const float *__restrict__ T, int64_t N, int D,
     for (int k = 0; k < 6; ++k) cells[6 * l + k] = c[k];
 }
 
-// Bounding boxes of the real representatives below every node (Eytzinger
-// nodes 0 .. 2N-2; leaves are N-1 .. 2N-2).  Empty: lo = +inf, hi = -inf.
-__global__ void k_box_leaves(const int32_t *__restrict__ rep, const float *__restrict__ xyz,
-                             int64_t n, int64_t N, float *__restrict__ nbox) {
-    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= N) return;
-    float *b = nbox + 6 * (N - 1 + l);
-    int64_t id = rep[l];
-    for (int a = 0; a < 3; ++a) {
-        float v = id < n ? xyz[3 * id + a] : 0.0f;
-        b[a] = id < n ? v : INFINITY;
-        b[3 + a] = id < n ? v : -INFINITY;
-    }
-}
-
-__global__ void k_box_level(int64_t first, int64_t count, float *__restrict__ nbox) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count) return;
-    int64_t i = first + j;
-    const float *L = nbox + 6 * (2 * i + 1);
-    const float *R = nbox + 6 * (2 * i + 2);
-    float *b = nbox + 6 * i;
-    for (int a = 0; a < 3; ++a) {
-        b[a] = fminf(L[a], R[a]);
-        b[3 + a] = fmaxf(L[3 + a], R[3 + a]);
-    }
-}
-
 // float64 helpers, every operation rounded on its own
 __device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
 __device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
 
-// "c affords p at r_max": float64 distance from p to the closed cell.
-__device__ __forceinline__ bool affords(const double c[6], float px, float py, float pz,
-                                        double R2) {
-    const double p[3] = {(double)px, (double)py, (double)pz};
-    double d2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double below = dsub(c[a], p[a]);
-        double above = dsub(p[a], c[3 + a]);
-        double g = below > above ? below : above;
-        if (g < 0.0) g = 0.0;
-        d2 = dadd(d2, dmul(g, g));
+// r_min pruning of one leaf (Sec. IV-B): bounded cell whose farthest corner is
+// within r_min of the representative (float64, margin 2^-18).
+__global__ void k_prune(const float *__restrict__ cells, const int32_t *__restrict__ rep,
+                        const float *__restrict__ xyz, int64_t n, int64_t N, int prune, double thr,
+                        uint8_t *__restrict__ pruned, unsigned long long *__restrict__ totals) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    const int64_t id = rep[l];
+    bool pr = prune && id < n;
+    const float *c = cells + 6 * l;
+    for (int k = 0; k < 6 && pr; ++k) pr = isfinite(c[k]);
+    if (pr) {
+        double far2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double t = (double)xyz[3 * id + a];
+            const double lo = dsub(t, (double)c[a]);
+            const double hi = dsub((double)c[3 + a], t);
+            const double l2 = dmul(lo, lo), h2 = dmul(hi, hi);
+            far2 = dadd(far2, l2 > h2 ? l2 : h2);
+        }
+        pr = far2 <= thr;
     }
-    return d2 <= R2;
+    pruned[l] = (uint8_t)pr;
+    if (pr) atomicAdd(&totals[2], 1ull);
 }
 
-// Lower bound of the float64 distance from the cell to any point of a box.
-__device__ __forceinline__ bool box_may_afford(const double c[6], const float *b, double R2) {
-    double d2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double g1 = dsub((double)b[a], c[3 + a]);   // box lo - cell hi
-        double g2 = dsub(c[a], (double)b[3 + a]);   // cell lo - box hi
-        double g = g1 > g2 ? g1 : g2;
-        if (g < 0.0) g = 0.0;
-        d2 = dadd(d2, dmul(g, g));
-    }
-    return d2 <= R2;
-}
-
-struct AffordArgs {
-    const float *T;
-    const float *cells;
-    const float *nbox;
-    const int32_t *rep;
-    const float *xyz;
-    int64_t n, N;
-    int D;
-    int prune;
-    double R2;      // (r_max (1 + 2^-20))^2
-    double thr;     // r_min^2 (1 - 2^-18)
+// ---------------------------------------------------------------------------
+// Affordance sets through a uniform grid over the points
+// ---------------------------------------------------------------------------
+// Grid of cubic bins of side g (>= R) over the cloud's bounding box.  Points
+// are sorted by bin with x fastest, so the bins of one (y, z) row are one
+// contiguous run of points.  A leaf's candidates are the rows covering its
+// cell grown by R (one extra bin on every side absorbs rounding); every
+// candidate then takes the exact float64 "affords" test.
+struct Grid {
+    double origin[3];
+    double g;
+    double lo[3], hi[3];    // bounding box of the points
+    int32_t dims[3];
+    int32_t pad;
+    int64_t ncells;
 };
 
-__device__ __forceinline__ bool leaf_pruned(const AffordArgs &A, const double c[6], int64_t id) {
-    if (!A.prune || id >= A.n) return false;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        if (!isfinite(c[k])) return false;
-    double far2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double t = (double)A.xyz[3 * id + a];
-        double lo = dsub(t, c[a]);
-        double hi = dsub(c[3 + a], t);
-        double l2 = dmul(lo, lo), h2 = dmul(hi, hi);
-        far2 = dadd(far2, l2 > h2 ? l2 : h2);
-    }
-    return far2 <= A.thr;
+__global__ void k_grid_bbox(const float *__restrict__ xyz, int64_t n, float *__restrict__ bb) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        for (int a = 0; a < 3; ++a) {
+            const float v = xyz[3 * j + a];
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int off = WAVE / 2; off >= 1; off >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
+        }
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        for (int a = 0; a < 3; ++a) {
+            // order-preserving integer views (finite values; signed zeros tie)
+            const int il = __float_as_int(lo[a]), ih = __float_as_int(hi[a]);
+            if (il >= 0) atomicMin(reinterpret_cast<int *>(&bb[a]), il);
+            else atomicMax(reinterpret_cast<unsigned int *>(&bb[a]), (unsigned int)il);
+            if (ih >= 0) atomicMax(reinterpret_cast<int *>(&bb[3 + a]), ih);
+            else atomicMin(reinterpret_cast<unsigned int *>(&bb[3 + a]), (unsigned int)ih);
+        }
 }
 
-// Count (FILL = false) or write (FILL = true) the affordance set of each leaf.
-template <bool FILL>
-__global__ void __launch_bounds__(TB) k_afford(AffordArgs A, uint32_t *__restrict__ count,
-                                               const uint32_t *__restrict__ start,
-                                               unsigned long long *__restrict__ totals,
-                                               float *__restrict__ px, float *__restrict__ py,
-                                               float *__restrict__ pz, int32_t *__restrict__ pidx,
-                                               Leaf *__restrict__ leaf, uint8_t *__restrict__ pruned) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= A.N) return;
-    double c[6];
+__global__ void k_grid_init(float *bb) {
+    if (threadIdx.x < 3) {
+        bb[threadIdx.x] = INFINITY;
+        bb[3 + threadIdx.x] = -INFINITY;
+    }
+}
+
+__global__ void k_grid_setup(const float *__restrict__ bb, double R, int64_t cap, Grid *G) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Grid g;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = (double)bb[a];
+        g.hi[a] = (double)bb[3 + a];
+        if (!(g.lo[a] <= g.hi[a]) || !isfinite(g.lo[a]) || !isfinite(g.hi[a])) g.lo[a] = g.hi[a] = 0.0;   // empty cloud
+        g.origin[a] = g.lo[a];
+        ext = fmax(ext, g.hi[a] - g.lo[a]);
+    }
+    double step = R;
+    if (ext / step > 1000.0) step = ext / 1000.0;
+    int64_t total = 0;
+    for (int it = 0; it < 64; ++it) {
+        total = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.dims[a] = (int32_t)floor((g.hi[a] - g.lo[a]) / step) + 1;
+            total *= g.dims[a];
+        }
+        if (total <= cap) break;
+        step *= 1.25;
+    }
+    g.g = step;
+    g.pad = 0;
+    g.ncells = total;
+    *G = g;
+}
+
+__device__ __forceinline__ int32_t bin_of(double v, double origin, double g, int32_t dim) {
+    double t = floor((v - origin) / g);
+    if (!(t >= 0.0)) t = 0.0;   // also catches NaN (non-finite input is rejected after the build's sync)
+    if (t > (double)(dim - 1)) t = (double)(dim - 1);
+    return (int32_t)t;
+}
+
+__global__ void k_grid_keys(const float *__restrict__ xyz, int64_t n, const Grid *__restrict__ G,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                            uint32_t *__restrict__ cellcnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const Grid g = *G;
+    int32_t b[3];
+    for (int a = 0; a < 3; ++a) b[a] = bin_of((double)xyz[3 * j + a], g.origin[a], g.g, g.dims[a]);
+    const uint32_t c = (uint32_t)(((int64_t)b[2] * g.dims[1] + b[1]) * g.dims[0] + b[0]);
+    key[j] = c;
+    val[j] = (uint32_t)j;
+    atomicAdd(&cellcnt[c], 1u);
+}
+
+__global__ void k_grid_gather(const float *__restrict__ xyz, const uint32_t *__restrict__ val, int64_t n,
+                              float *__restrict__ sx, float *__restrict__ sy, float *__restrict__ sz) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t id = val[k];
+    sx[k] = xyz[3 * id];
+    sy[k] = xyz[3 * id + 1];
+    sz[k] = xyz[3 * id + 2];
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_b(uint32_t v, int lane) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c[k] = (double)A.cells[6 * l + k];
-    const int64_t id = A.rep[l];
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+struct AffArgs {
+    const float *cells;
+    const int32_t *rep;
+    const uint8_t *pruned;
+    const float *xyz;
+    const Grid *grid;
+    const uint32_t *cstart;    // [ncells + 1] first sorted point of every bin
+    const float *sx, *sy, *sz; // points sorted by bin
+    const uint32_t *sid;       // original index of each sorted point
+    int64_t n, N;
+    double R2;                 // (r_max (1 + 2^-20))^2
+    double R;
+};
+
+// One wavefront per leaf.  COUNT: write the set size.  FILL: write the set
+// (rows in order, points in bin order), its padding, AABB and leaf record.
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__restrict__ count,
+                                                     const uint32_t *__restrict__ pstart,
+                                                     float *__restrict__ px, float *__restrict__ py,
+                                                     float *__restrict__ pz, int32_t *__restrict__ pidx,
+                                                     Leaf *__restrict__ leaf) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (l >= A.N) return;
+    const uint32_t out0 = FILL ? pstart[l] : 0u;
     uint32_t cnt = 0;
-    uint32_t s0 = FILL ? start[l] : 0u;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    auto emit = [&](int64_t pid) {
-        if (FILL) {
-            float x = A.xyz[3 * pid], y = A.xyz[3 * pid + 1], z = A.xyz[3 * pid + 2];
-            px[s0 + cnt] = x;
-            py[s0 + cnt] = y;
-            pz[s0 + cnt] = z;
-            pidx[s0 + cnt] = (int32_t)pid;
+    auto emit = [&](bool ok, float x, float y, float z, int32_t id) {
+        const uint64_t m = __ballot(ok);
+        if (FILL && ok) {
+            const uint32_t pos = out0 + cnt + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            px[pos] = x;
+            py[pos] = y;
+            pz[pos] = z;
+            pidx[pos] = id;
             lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
             hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
         }
-        ++cnt;
+        cnt += (uint32_t)__popcll(m);
     };
-    const bool pr = leaf_pruned(A, c, id);
-    if (pr) {
-        emit(id);
-    } else {
-        // near-first depth-first walk; a node is visited only if its point box
-        // may lie within R of the cell
-        float key[3];
-#pragma unroll
+    const int64_t rid = A.rep[l];
+    if (A.pruned[l]) {
+        const float x = A.xyz[3 * rid], y = A.xyz[3 * rid + 1], z = A.xyz[3 * rid + 2];
+        emit(lane == 0, x, y, z, (int32_t)rid);
+    } else if (A.n > 0) {
+        const Grid g = *A.grid;
+        const float *c = A.cells + 6 * l;
+        double cl[3], ch[3];
+        int32_t b0[3], b1[3];
+        bool empty = false;
         for (int a = 0; a < 3; ++a) {
-            float lo_ = (float)c[a], hi_ = (float)c[3 + a];
-            key[a] = (isfinite(lo_) && isfinite(hi_)) ? 0.5f * lo_ + 0.5f * hi_
-                     : isfinite(lo_) ? lo_ : isfinite(hi_) ? hi_ : 0.0f;
-        }
-        int32_t stack[33];
-        int sp = 0;
-        stack[sp++] = 0;
-        while (sp > 0) {
-            const int64_t i = stack[--sp];
-            const float *b = A.nbox + 6 * i;
-            if (b[0] > b[3]) continue;   // no real point below
-            if (!box_may_afford(c, b, A.R2)) continue;
-            if (i >= A.N - 1) {
-                const int64_t pid = A.rep[i - (A.N - 1)];
-                if (pid < A.n && affords(c, A.xyz[3 * pid], A.xyz[3 * pid + 1], A.xyz[3 * pid + 2], A.R2))
-                    emit(pid);
+            cl[a] = (double)c[a];
+            ch[a] = (double)c[3 + a];
+            const double lo_b = fmax(cl[a] - A.R, g.lo[a]);
+            const double hi_b = fmin(ch[a] + A.R, g.hi[a]);
+            if (!(lo_b <= hi_b)) {
+                empty = true;
+                b0[a] = 0;
+                b1[a] = -1;
                 continue;
             }
-            const int d = 31 - __builtin_clz((unsigned)(i + 1));
-            const bool left_first = key[d % 3] <= A.T[i];
-            if (left_first) {
-                stack[sp++] = (int32_t)(2 * i + 2);
-                stack[sp++] = (int32_t)(2 * i + 1);
-            } else {
-                stack[sp++] = (int32_t)(2 * i + 1);
-                stack[sp++] = (int32_t)(2 * i + 2);
+            b0[a] = max(bin_of(lo_b, g.origin[a], g.g, g.dims[a]) - 1, 0);
+            b1[a] = min(bin_of(hi_b, g.origin[a], g.g, g.dims[a]) + 1, g.dims[a] - 1);
+        }
+        if (!empty) {
+            const int64_t ny = b1[1] - b0[1] + 1;
+            const int64_t nrows = ny * (int64_t)(b1[2] - b0[2] + 1);
+            for (int64_t r0 = 0; r0 < nrows; r0 += WAVE) {
+                const int64_t r = r0 + lane;
+                uint32_t s = 0, e = 0;
+                if (r < nrows) {
+                    const int64_t y = b0[1] + r % ny, z = b0[2] + r / ny;
+                    const int64_t row = (z * g.dims[1] + y) * g.dims[0];
+                    s = A.cstart[row + b0[0]];
+                    e = A.cstart[row + b1[0] + 1];
+                }
+                uint32_t rem = e - s, pos = s;
+                while (true) {
+                    const uint32_t incl = wave_incl_scan_b(rem, lane);
+                    const uint32_t excl = incl - rem;
+                    const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+                    if (total == 0) break;
+                    int o = 0;
+#pragma unroll
+                    for (int step = 32; step >= 1; step >>= 1) {
+                        const uint32_t ev = __shfl(excl, o + step, WAVE);
+                        if (ev <= (uint32_t)lane) o += step;
+                    }
+                    const uint32_t base = __shfl(pos - excl, o, WAVE);
+                    bool ok = false;
+                    float x = 0.f, y = 0.f, z = 0.f;
+                    int32_t id = -1;
+                    if ((uint32_t)lane < total) {
+                        const uint32_t k = base + (uint32_t)lane;
+                        x = A.sx[k];
+                        y = A.sy[k];
+                        z = A.sz[k];
+                        id = (int32_t)A.sid[k];
+                        const double pp[3] = {(double)x, (double)y, (double)z};
+                        double d2 = 0.0;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double below = dsub(cl[a], pp[a]);
+                            const double above = dsub(pp[a], ch[a]);
+                            double gg = below > above ? below : above;
+                            if (gg < 0.0) gg = 0.0;
+                            d2 = dadd(d2, dmul(gg, gg));
+                        }
+                        ok = d2 <= A.R2;
+                    }
+                    emit(ok, x, y, z, id);
+                    const uint32_t take = excl >= WAVE ? 0u : min(rem, (uint32_t)WAVE - excl);
+                    rem -= take;
+                    pos += take;
+                }
             }
         }
     }
     if (!FILL) {
-        count[l] = cnt;
-        unsigned long long padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
-        atomicAdd(&totals[0], (unsigned long long)cnt);
-        atomicAdd(&totals[1], padded);
-        if (pr) atomicAdd(&totals[2], 1ull);
-    } else {
-        const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
-        for (uint32_t k = cnt; k < padded; ++k) {
-            px[s0 + k] = INFINITY;
-            py[s0 + k] = INFINITY;
-            pz[s0 + k] = INFINITY;
-            pidx[s0 + k] = -1;
+        if (lane == 0) count[l] = cnt;
+        return;
+    }
+    // wave reductions of the AABB, padding, leaf record
+    for (int a = 0; a < 3; ++a)
+        for (int off = WAVE / 2; off >= 1; off >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
         }
+    const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+    for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
+        px[out0 + k] = INFINITY;
+        py[out0 + k] = INFINITY;
+        pz[out0 + k] = INFINITY;
+        pidx[out0 + k] = -1;
+    }
+    if (lane == 0) {
         Leaf L;
         for (int a = 0; a < 3; ++a) {
             L.lo[a] = lo[a];
             L.hi[a] = hi[a];
         }
-        L.start = s0;
+        L.start = out0;
         L.count = cnt;
         leaf[l] = L;
-        pruned[l] = (uint8_t)pr;
     }
 }
 
-__global__ void k_pad_counts(const uint32_t *__restrict__ cnt, int64_t N, uint32_t *__restrict__ out) {
+__global__ void k_pad_counts(const uint32_t *__restrict__ cnt, int64_t N, uint32_t *__restrict__ out,
+                             unsigned long long *__restrict__ totals) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= N) return;
     uint32_t c = cnt[l];
-    out[l] = c ? ((c + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+    uint32_t p = c ? ((c + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+    out[l] = p;
+    if (c) {
+        atomicAdd(&totals[0], (unsigned long long)c);
+        atomicAdd(&totals[1], (unsigned long long)p);
+    }
 }
 
 inline unsigned nblk(int64_t n, int tb = TB) { return (unsigned)((n + tb - 1) / tb); }
@@ -453,14 +570,11 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Per-cloud scratch kept from the count phase to the fill phase.
 struct CloudWork {
     Scratch scratch;
-    float *cells = nullptr;
-    float *nbox = nullptr;
-    uint32_t *count = nullptr;
-    uint32_t *start = nullptr;
-    unsigned long long *totals = nullptr;   // [0] entries [1] padded [2] pruned
-    uint32_t *bad = nullptr;
-    int32_t *rep = nullptr;
-    AffordArgs args{};
+    uint32_t *count = nullptr;     // entries per leaf
+    uint32_t *pstart = nullptr;    // exclusive scan of padded counts
+    uint32_t *scan_tmp = nullptr;
+    unsigned long long *totals = nullptr;   // [0] entries [1] padded [2] pruned [3] non-finite
+    AffArgs args{};
 };
 
 capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, uint32_t flags,
@@ -506,7 +620,10 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
 
     // scratch
     const size_t wN = (size_t)N;
-    const size_t radix = radix_tmp_words(N);
+    const size_t wn = (size_t)std::max<int64_t>(n, 1);
+    const int64_t cell_cap = std::max<int64_t>(4096, 4 * n);
+    int cell_bits = 1;
+    while (((int64_t)1 << cell_bits) < cell_cap) ++cell_bits;
     const size_t ntile = (size_t)((N + GTILE - 1) / GTILE);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -515,17 +632,20 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         return o;
     };
     const size_t oL = take(sizeof(uint32_t) * 6 * wN);     // 3 lists x 2 buffers
-    const size_t oK = take(sizeof(uint32_t) * 2 * wN);     // sort keys x 2
+    const size_t oK = take(sizeof(uint32_t) * 2 * std::max(wN, wn));   // sort keys x 2
+    const size_t oV = take(sizeof(uint32_t) * 2 * wn);     // grid sort values x 2
     const size_t oInv = take(sizeof(uint32_t) * wN);
     const size_t oLeft = take(wN);
     const size_t oSums = take(sizeof(uint32_t) * (2 * ntile + 16));
-    const size_t oRad = take(sizeof(uint32_t) * radix);
+    const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words(std::max<int64_t>(N, n)));
     const size_t oCells = take(sizeof(float) * 6 * wN);
-    const size_t oBox = take(sizeof(float) * 6 * (2 * wN));
     const size_t oCnt = take(sizeof(uint32_t) * (wN + 1));
-    const size_t oStart = take(sizeof(uint32_t) * (wN + 1));
+    const size_t oPs = take(sizeof(uint32_t) * (wN + 1));
     const size_t oTot = take(sizeof(unsigned long long) * 4);
-    const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words(N + 1));
+    const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words(std::max<int64_t>(N, cell_cap) + 1));
+    const size_t oGrid = take(sizeof(Grid) + 64);
+    const size_t oCs = take(sizeof(uint32_t) * ((size_t)cell_cap + 1));
+    const size_t oS = take(sizeof(float) * 3 * wn);
     if (!W.scratch.alloc(off, s)) {
         set_error("device allocation of %zu scratch bytes failed", off);
         return CAPT_ENOMEM;
@@ -533,22 +653,25 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     char *Sb = W.scratch.as<char>();
     uint32_t *Lbuf = reinterpret_cast<uint32_t *>(Sb + oL);
     uint32_t *keys = reinterpret_cast<uint32_t *>(Sb + oK);
+    uint32_t *gval = reinterpret_cast<uint32_t *>(Sb + oV);
     uint32_t *inv = reinterpret_cast<uint32_t *>(Sb + oInv);
     uint8_t *left = reinterpret_cast<uint8_t *>(Sb + oLeft);
     uint32_t *sums = reinterpret_cast<uint32_t *>(Sb + oSums);
     uint32_t *rad = reinterpret_cast<uint32_t *>(Sb + oRad);
-    W.cells = reinterpret_cast<float *>(Sb + oCells);
-    W.nbox = reinterpret_cast<float *>(Sb + oBox);
+    float *cells = reinterpret_cast<float *>(Sb + oCells);
     W.count = reinterpret_cast<uint32_t *>(Sb + oCnt);
-    W.start = reinterpret_cast<uint32_t *>(Sb + oStart);
+    W.pstart = reinterpret_cast<uint32_t *>(Sb + oPs);
     W.totals = reinterpret_cast<unsigned long long *>(Sb + oTot);
-    uint32_t *scan_tmp = reinterpret_cast<uint32_t *>(Sb + oScan);
-    W.bad = reinterpret_cast<uint32_t *>(W.totals + 3);
-    W.rep = C.rep;
+    W.scan_tmp = reinterpret_cast<uint32_t *>(Sb + oScan);
+    Grid *grid = reinterpret_cast<Grid *>(Sb + oGrid);
+    float *bb = reinterpret_cast<float *>(Sb + oGrid + sizeof(Grid));
+    uint32_t *cstart = reinterpret_cast<uint32_t *>(Sb + oCs);
+    float *sxyz = reinterpret_cast<float *>(Sb + oS);
+    uint32_t *bad = reinterpret_cast<uint32_t *>(W.totals + 3);
     CAPT_HIP(hipMemsetAsync(W.totals, 0, sizeof(unsigned long long) * 4, s));
     if (n > 0) {
         hipLaunchKernelGGL(k_count_nonfinite, dim3(std::min<int64_t>(nblk(3 * n), 4096)), dim3(TB), 0, s,
-                           xyz, 3 * n, W.bad);
+                           xyz, 3 * n, bad);
         CAPT_LAUNCH_CHECK();
     }
 
@@ -588,43 +711,71 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     }
     hipLaunchKernelGGL(k_inverse, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], N, inv);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(TB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]], inv, xyz, n, N, D, d, T,
-                       C.rep);
+    hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(TB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]],
+                       inv, xyz, n, N, D, d, T, C.rep);
     CAPT_LAUNCH_CHECK();
 
-    // 3. leaf cells, point boxes of every node
-    hipLaunchKernelGGL(k_leaf_cells, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, W.cells);
+    // 3. leaf cells and pruning
+    hipLaunchKernelGGL(k_leaf_cells, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, cells);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_box_leaves, dim3(nblk(N)), dim3(TB), 0, s, C.rep, xyz, n, N, W.nbox);
+    const int prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
+    const double thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
+    hipLaunchKernelGGL(k_prune, dim3(nblk(N)), dim3(TB), 0, s, cells, C.rep, xyz, n, N, prune, thr,
+                       C.pruned_flag, W.totals);
     CAPT_LAUNCH_CHECK();
-    for (int dd = D - 1; dd >= 0; --dd) {
-        const int64_t first = ((int64_t)1 << dd) - 1, count = (int64_t)1 << dd;
-        hipLaunchKernelGGL(k_box_level, dim3(nblk(count)), dim3(TB), 0, s, first, count, W.nbox);
+
+    // 4. grid of the points: bins of side >= R, points sorted by bin
+    const double R = (double)r_max * (1.0 + 0x1p-20);
+    hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bb);
+    CAPT_LAUNCH_CHECK();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_grid_bbox, dim3(std::min<unsigned>(nblk(n), 512u)), dim3(TB), 0, s, xyz, n, bb);
+        CAPT_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, bb, R, cell_cap, grid);
+    CAPT_LAUNCH_CHECK();
+    CAPT_HIP(hipMemsetAsync(cstart, 0, sizeof(uint32_t) * ((size_t)cell_cap + 1), s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_grid_keys, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, grid, keys, gval, cstart);
+        CAPT_LAUNCH_CHECK();
+    }
+    // bin starts: exclusive scan over the cap; cstart[ncells .. cap] = n
+    capt_status st = scan_exclusive_u32(cstart, cstart, cell_cap + 1, nullptr, nullptr, W.scan_tmp, s);
+    if (st) return st;
+    int where = 0;
+    if (n > 1) {
+        st = radix_sort_u32(keys, gval, keys + wn, gval + wn, n, cell_bits, rad, s, &where);
+        if (st) return st;
+    }
+    const uint32_t *sid = where ? gval + wn : gval;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_grid_gather, dim3(nblk(n)), dim3(TB), 0, s, xyz, sid, n, sxyz, sxyz + wn,
+                           sxyz + 2 * wn);
         CAPT_LAUNCH_CHECK();
     }
 
-    // 4. affordance counts and placement
-    AffordArgs &A = W.args;
-    A.T = T;
-    A.cells = W.cells;
-    A.nbox = W.nbox;
+    // 5. affordance counts and placement
+    AffArgs &A = W.args;
+    A.cells = cells;
     A.rep = C.rep;
+    A.pruned = C.pruned_flag;
     A.xyz = xyz;
+    A.grid = grid;
+    A.cstart = cstart;
+    A.sx = sxyz;
+    A.sy = sxyz + wn;
+    A.sz = sxyz + 2 * wn;
+    A.sid = sid;
     A.n = n;
     A.N = N;
-    A.D = D;
-    A.prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
-    const double R = (double)r_max * (1.0 + 0x1p-20);
+    A.R = R;
     A.R2 = R * R;
-    A.thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
-    hipLaunchKernelGGL((k_afford<false>), dim3(nblk(N)), dim3(TB), 0, s, A, W.count, nullptr, W.totals,
-                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.start);
+    hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, W.totals);
     CAPT_LAUNCH_CHECK();
-    capt_status st = scan_exclusive_u32(W.start, W.start, N, nullptr, nullptr, scan_tmp, s);
-    if (st) return st;
-    return CAPT_OK;
+    return scan_exclusive_u32(W.pstart, W.pstart, N, nullptr, nullptr, W.scan_tmp, s);
 }
 
 capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsigned long long tot[4]) {
@@ -652,8 +803,8 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     C.dev.py = py;
     C.dev.pz = pz;
     C.dev.pidx = pidx;
-    hipLaunchKernelGGL((k_afford<true>), dim3(nblk(C.N)), dim3(TB), 0, s, W.args, nullptr, W.start, nullptr,
-                       px, py, pz, pidx, const_cast<Leaf *>(C.dev.leaf), C.pruned_flag);
+    hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
+                       py, pz, pidx, const_cast<Leaf *>(C.dev.leaf));
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }
@@ -712,8 +863,12 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
         pruned += f->clouds[c].pruned;
     }
     f->pruned_total = pruned;
-    capt_status st = upload_views(f, s);  // synchronises: scratch is released after
-    return st;
+    return CAPT_OK;   // scratch is released stream-ordered; the forest is ready in stream order
+}
+
+capt_status ensure_views(capt_forest_s *f, hipStream_t s) {
+    if (f->d_clouds) return CAPT_OK;
+    return upload_views(f, s);
 }
 
 }  // namespace capt

@@ -150,6 +150,7 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
                          capt_forest_s *f);
 void free_cloud(CloudHost &c);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
+capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)
 
 // query.hip
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,

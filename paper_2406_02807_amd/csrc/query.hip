@@ -66,6 +66,12 @@ __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, in
 // c*g .. c*g+g-1 (g <= 64), or all lanes belong to one configuration (g > 64,
 // cfg_of_lane = 0).  Returns, per lane, whether that lane's configuration was
 // hit.
+//
+// The surviving spheres' sets form one list of (sphere, entry) pairs in lane
+// order; excl is the exclusive prefix of the set lengths.  Step k covers pairs
+// 64k .. 64k+63: lane j takes pair 64k + j, whose sphere is the last lane o
+// with excl_o <= 64k + j (binary search).  The prefix is recomputed only when a
+// hit retires a configuration while others in the tile are still open.
 __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L,
                                           const float4 *__restrict__ sph, int nsph, int g) {
     const int lane = lane_id();
@@ -88,9 +94,10 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     const int gg = g > WAVE ? WAVE : g;
     const int cfg = g > WAVE ? 0 : lane / gg;
     const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
+    const bool single = (g > WAVE) || (2 * g > nsph);   // one configuration in this tile
     bool done = false;
-    uint32_t rem = alive ? leaf.count : 0u;
-    uint32_t pos = leaf.start;
+    uint32_t rem = alive ? leaf.count : 0u;   // pairs of this lane not yet consumed
+    uint32_t pos = leaf.start;                 // first unconsumed entry
     const float *__restrict__ PX = C.px;
     const float *__restrict__ PY = C.py;
     const float *__restrict__ PZ = C.pz;
@@ -100,71 +107,105 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
         const uint32_t excl = incl - rem;
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         if (total == 0) break;
-        // owner of pair slot `lane`: the last sphere whose first slot <= lane
-        int o = 0;
+        const uint32_t base_l = pos - excl;    // entry of pair slot s of this lane = base_l + s
+        bool rescan = false;
+        for (uint32_t k0 = 0; k0 < total && !rescan; k0 += WAVE) {
+            const uint32_t slot = k0 + (uint32_t)lane;
+            int o = 0;
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const uint32_t e = __shfl(excl, o + step, WAVE);
-            if (e <= (uint32_t)lane) o += step;
-        }
-        const uint32_t base = __shfl(pos - excl, o, WAVE);
-        const float ox = __shfl(q.x, o, WAVE);
-        const float oy = __shfl(q.y, o, WAVE);
-        const float oz = __shfl(q.z, o, WAVE);
-        const float orr = __shfl(r2, o, WAVE);
-        bool hit = false;
-        if ((uint32_t)lane < total) {
-            const uint32_t e = base + (uint32_t)lane;
-            hit = sqdist(ox, oy, oz, PX[e], PY[e], PZ[e]) <= orr;
-        }
-        const uint64_t hm = __ballot(hit);
-        const uint32_t take = excl >= WAVE ? 0u : min(rem, (uint32_t)WAVE - excl);
-        if (hm) {
-            bool mine = false;
-            if (take) {
-                const uint64_t m = take >= WAVE ? ~0ull : ((1ull << take) - 1);
-                mine = ((hm >> excl) & m) != 0;
+            for (int step = 32; step >= 1; step >>= 1) {
+                const uint32_t e = __shfl(excl, o + step, WAVE);
+                if (e <= slot) o += step;
             }
-            const uint64_t sh = __ballot(mine);
-            if (valid) done = done || (((sh >> (cfg * gg)) & gmask) != 0);
+            const uint32_t base = __shfl(base_l, o, WAVE);
+            const float ox = __shfl(q.x, o, WAVE);
+            const float oy = __shfl(q.y, o, WAVE);
+            const float oz = __shfl(q.z, o, WAVE);
+            const float orr = __shfl(r2, o, WAVE);
+            bool hit = false;
+            if (slot < total) {
+                const uint32_t e = base + slot;
+                hit = sqdist(ox, oy, oz, PX[e], PY[e], PZ[e]) <= orr;
+            }
+            const uint64_t hm = __ballot(hit);
+            if (hm) {
+                if (single) {
+                    done = valid;
+                    rescan = true;
+                } else {
+                    // pairs of this lane inside the step: [excl, excl + rem) n [k0, k0 + 64)
+                    const uint32_t lo = max(excl, k0), hi = min(excl + rem, k0 + (uint32_t)WAVE);
+                    bool mine = false;
+                    if (lo < hi) {
+                        const uint32_t w = hi - lo;
+                        const uint64_t m = w >= WAVE ? ~0ull : ((1ull << w) - 1);
+                        mine = ((hm >> (lo - k0)) & m) != 0;
+                    }
+                    const uint64_t sh = __ballot(mine);
+                    if (valid) done = done || (((sh >> (cfg * gg)) & gmask) != 0);
+                    // consume what this step covered, then rebuild the prefix
+                    const uint32_t end = k0 + (uint32_t)WAVE;
+                    const uint32_t used = end <= excl ? 0u : min(rem, end - excl);
+                    rem -= used;
+                    pos += used;
+                    rescan = true;
+                }
+            }
         }
-        rem -= take;
-        pos += take;
+        if (!rescan) break;   // every pair consumed without a hit
+        if (single) break;
     }
     return done;
 }
 
+// Per-XCD work queues: blocks are dispatched round-robin over the XCDs, so
+// block b takes tiles from the range and counter of XCD b % NXCD, keeping the
+// queue atomics in that XCD's L2.
+constexpr int NXCD = 8;
+constexpr int CTR_STRIDE = 16;   // one 64-byte line per counter
+
 __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int g,
-                                uint8_t *__restrict__ out, int L) {
+                                uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float Tl[];
     const int nT = (1 << L) - 1;
     for (int i = threadIdx.x; i < nT; i += blockDim.x) Tl[i] = C.T[i];
     __syncthreads();
     const int lane = lane_id();
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (g <= WAVE) {
-        const int cpt = WAVE / g;                 // configurations per tile
-        const int64_t ncfg = nsph / g;
-        const int64_t ntiles = (ncfg + cpt - 1) / cpt;
-        for (int64_t t = wid; t < ntiles; t += waves) {
-            const int64_t c0 = t * cpt;
-            const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-            const bool hit = wave_tile(C, Tl, L, sph + c0 * g, nc * g, g);
-            if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
-        }
-    } else {
-        const int64_t ncfg = nsph / g;
-        for (int64_t c = wid; c < ncfg; c += waves) {
-            bool hit = false;
-            for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
-                const int ns = min(WAVE, g - s0);
-                hit = wave_tile(C, Tl, L, sph + c * g + s0, ns, g);
-                hit = __shfl(hit, 0, WAVE);
+    const int64_t ncfg = nsph / g;
+    const int cpt = g <= WAVE ? WAVE / g : 1;       // configurations per tile
+    const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+    const int nq = (int)min<int64_t>(NXCD, (int64_t)gridDim.x);
+    const int xq = (int)(blockIdx.x % (unsigned)nq);
+    const int64_t t0 = ntiles * xq / nq, t1 = ntiles * (xq + 1) / nq;
+    while (true) {
+        unsigned int c = 0;
+        if (lane == 0) c = atomicAdd(&ctr[xq * CTR_STRIDE], (unsigned int)chunk);
+        c = __shfl(c, 0, WAVE);
+        const int64_t ta = t0 + (int64_t)c;
+        if (ta >= t1) break;
+        const int64_t tb = min<int64_t>(ta + chunk, t1);
+        for (int64_t t = ta; t < tb; ++t) {
+            if (g <= WAVE) {
+                const int64_t c0 = t * cpt;
+                const int nc = (int)min<int64_t>(cpt, ncfg - c0);
+                const bool hit = wave_tile(C, Tl, L, sph + c0 * g, nc * g, g);
+                if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
+            } else {
+                bool hit = false;
+                for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
+                    const int ns = min(WAVE, g - s0);
+                    hit = wave_tile(C, Tl, L, sph + t * g + s0, ns, g);
+                    hit = __shfl(hit, 0, WAVE);
+                }
+                if (lane == 0) out[t] = (uint8_t)hit;
             }
-            if (lane == 0) out[c] = (uint8_t)hit;
         }
     }
+}
+
+__global__ void k_zero_u32(unsigned int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // One queue entry of the batched launch.
@@ -353,7 +394,7 @@ int lds_levels_for(int D) {
 }
 
 capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
-                         hipStream_t s) {
+                         unsigned int *ctr, hipStream_t s) {
     if (nsph <= 0) return CAPT_OK;
     const capt_tuning &t = tuning();
     const int L = lds_levels_for(C.D);
@@ -364,9 +405,14 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     const int64_t wpb = threads / WAVE;
     int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
     blocks = std::max<int64_t>(1, std::min(blocks, (ntiles + wpb - 1) / wpb));
+    // queue chunk: about 8 pops per wave over the whole launch, 1 .. 64 tiles
+    const int64_t per_wave = ntiles / std::max<int64_t>(1, blocks * wpb);
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_wave / 8));
     const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
+    CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_collide_cloud, dim3((unsigned)blocks), dim3(threads), lds, s, C,
-                       reinterpret_cast<const float4 *>(spheres), nsph, g, out, L);
+                       reinterpret_cast<const float4 *>(spheres), nsph, g, out, L, ctr, chunk);
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }
@@ -468,13 +514,22 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
         if (st) return st;
     }
     if (nc == 1 || (flags & CAPT_PER_CLOUD)) {
+        // queue counters, one set per cloud so launches on the stream never share them
+        Scratch ctr;
+        if (!ctr.alloc(sizeof(unsigned int) * NXCD * CTR_STRIDE * (size_t)nc, s)) {
+            set_error("device allocation for queue counters failed");
+            return CAPT_ENOMEM;
+        }
         for (int c = 0; c < nc; ++c) {
             const int64_t m = qoff[c + 1] - qoff[c];
-            capt_status st = launch_cloud(f->clouds[c].dev, spheres + 4 * qoff[c], m, g, out + qoff[c] / g, s);
+            capt_status st = launch_cloud(f->clouds[c].dev, spheres + 4 * qoff[c], m, g, out + qoff[c] / g,
+                                          ctr.as<unsigned int>() + (size_t)c * NXCD * CTR_STRIDE, s);
             if (st) return st;
         }
         return CAPT_OK;
     }
+    capt_status vs = ensure_views(f, s);
+    if (vs) return vs;
     BatchPlan *p = f->plan;
     const bool reuse = p && p->spheres == spheres && p->out == out && p->group == g &&
                        std::equal(p->qoff.begin(), p->qoff.end(), qoff) && same_tuning(p->tun, tuning());
