@@ -218,11 +218,13 @@ capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t 
                              void *stream);
 
 /*
- * Launch shape of the batched collision kernel (chosen by the autotuner).
+ * Launch shape of the collision kernels (chosen by the autotuner).
  *   waves_per_group  wavefronts per workgroup (1 .. 16)
  *   groups_per_cu    persistent workgroups per compute unit (1 .. 16)
- *   tile_cfgs        configurations a workgroup takes per queue pop (1 .. 4096)
- *   lds_levels       tree levels kept in LDS (0 .. 14)
+ *   tile_cfgs        configurations a wavefront takes per queue pop in the
+ *                    batched kernel (1 .. 4096)
+ *   lds_levels       tree levels kept in LDS (1 .. 14)
+ *   scan_unroll      64-pair steps of the set scan kept in flight (1, 2 or 4)
  * Zero fields keep their current value.  Applies to later calls.
  */
 typedef struct {
@@ -230,6 +232,7 @@ typedef struct {
     int32_t groups_per_cu;
     int32_t tile_cfgs;
     int32_t lds_levels;
+    int32_t scan_unroll;
 } capt_tuning;
 
 capt_status capt_set_tuning(const capt_tuning *t);

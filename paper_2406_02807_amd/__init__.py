@@ -41,7 +41,7 @@ class CaptError(RuntimeError):
 
 class capt_tuning(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("groups_per_cu", C.c_int32),
-                ("tile_cfgs", C.c_int32), ("lds_levels", C.c_int32)]
+                ("tile_cfgs", C.c_int32), ("lds_levels", C.c_int32), ("scan_unroll", C.c_int32)]
 
 
 _lib = None
@@ -274,8 +274,8 @@ def capt_query_stats(forest: Forest, spheres, query_off=None, stream=None):
     return leaf, rej, sc, hit
 
 
-def capt_set_tuning(waves_per_group=0, groups_per_cu=0, tile_cfgs=0, lds_levels=0):
-    t = capt_tuning(waves_per_group, groups_per_cu, tile_cfgs, lds_levels)
+def capt_set_tuning(waves_per_group=0, groups_per_cu=0, tile_cfgs=0, lds_levels=0, scan_unroll=0):
+    t = capt_tuning(waves_per_group, groups_per_cu, tile_cfgs, lds_levels, scan_unroll)
     lib = load_library()
     _check(lib.capt_set_tuning(C.byref(t)))
 

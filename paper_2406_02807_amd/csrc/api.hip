@@ -217,7 +217,8 @@ capt_status capt_set_tuning(const capt_tuning *t) {
         return CAPT_EINVAL;
     }
     if (t->waves_per_group < 0 || t->waves_per_group > 16 || t->groups_per_cu < 0 || t->groups_per_cu > 16 ||
-        t->tile_cfgs < 0 || t->tile_cfgs > 4096 || t->lds_levels < 0 || t->lds_levels > 14) {
+        t->tile_cfgs < 0 || t->tile_cfgs > 4096 || t->lds_levels < 0 || t->lds_levels > 14 ||
+        !(t->scan_unroll == 0 || t->scan_unroll == 1 || t->scan_unroll == 2 || t->scan_unroll == 4)) {
         set_error("tuning value out of range");
         return CAPT_EINVAL;
     }
@@ -226,6 +227,7 @@ capt_status capt_set_tuning(const capt_tuning *t) {
     if (t->groups_per_cu) cur.groups_per_cu = t->groups_per_cu;
     if (t->tile_cfgs) cur.tile_cfgs = t->tile_cfgs;
     if (t->lds_levels) cur.lds_levels = t->lds_levels;
+    if (t->scan_unroll) cur.scan_unroll = t->scan_unroll;
     return CAPT_OK;
 }
 

@@ -570,6 +570,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Per-cloud scratch kept from the count phase to the fill phase.
 struct CloudWork {
     Scratch scratch;
+    uint32_t *rad = nullptr;       // radix sort scratch; rad[0] = error word
     uint32_t *count = nullptr;     // entries per leaf
     uint32_t *pstart = nullptr;    // exclusive scan of padded counts
     uint32_t *scan_tmp = nullptr;
@@ -658,6 +659,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     uint8_t *left = reinterpret_cast<uint8_t *>(Sb + oLeft);
     uint32_t *sums = reinterpret_cast<uint32_t *>(Sb + oSums);
     uint32_t *rad = reinterpret_cast<uint32_t *>(Sb + oRad);
+    W.rad = rad;
     float *cells = reinterpret_cast<float *>(Sb + oCells);
     W.count = reinterpret_cast<uint32_t *>(Sb + oCnt);
     W.pstart = reinterpret_cast<uint32_t *>(Sb + oPs);
@@ -669,6 +671,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     float *sxyz = reinterpret_cast<float *>(Sb + oS);
     uint32_t *bad = reinterpret_cast<uint32_t *>(W.totals + 3);
     CAPT_HIP(hipMemsetAsync(W.totals, 0, sizeof(unsigned long long) * 4, s));
+    CAPT_HIP(hipMemsetAsync(rad, 0, sizeof(uint32_t) * 64, s));
     if (n > 0) {
         hipLaunchKernelGGL(k_count_nonfinite, dim3(std::min<int64_t>(nblk(3 * n), 4096)), dim3(TB), 0, s,
                            xyz, 3 * n, bad);
@@ -845,10 +848,18 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     }
     // one device-to-host read of every cloud's totals
     std::vector<unsigned long long> tot(4 * (size_t)ncloud);
-    for (int c = 0; c < ncloud; ++c)
+    std::vector<uint32_t> sort_err((size_t)ncloud);
+    for (int c = 0; c < ncloud; ++c) {
         CAPT_HIP(hipMemcpyAsync(&tot[4 * c], work[c].totals, sizeof(unsigned long long) * 4,
                                 hipMemcpyDeviceToHost, s));
+        CAPT_HIP(hipMemcpyAsync(&sort_err[c], work[c].rad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
     CAPT_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < ncloud; ++c)
+        if (sort_err[c]) {
+            set_error("internal: radix sort look-back bound exceeded while building cloud %d", c);
+            return CAPT_EHIP;
+        }
     for (int c = 0; c < ncloud; ++c) {
         const uint32_t bad = (uint32_t)(tot[4 * c + 3] & 0xFFFFFFFFull);
         if (bad) {

@@ -101,9 +101,10 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
                                hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
-// key.  Keys/values ping-pong between the two buffers; the sorted result ends
-// in (k0, v0) when the number of 8-bit passes is even, else in (k1, v1); the
-// return value of radix_sort_* tells which (0 or 1) through *where.
+// key (n < 2^30).  Keys/values ping-pong between the two buffers; *where tells
+// whether the result is in (k0, v0) (0) or (k1, v1) (1).  tmp must hold
+// radix_tmp_words(n) words; tmp[0] is an error word the caller clears before
+// and checks after (non-zero: an internal wait bound was hit).
 size_t radix_tmp_words(int64_t n);
 capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where);

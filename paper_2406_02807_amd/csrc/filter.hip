@@ -269,6 +269,7 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     uint32_t *stmp = reinterpret_cast<uint32_t *>(B + oScan);
 
     const float rf2 = r_filter * r_filter;
+    CAPT_HIP(hipMemsetAsync(rad, 0, sizeof(uint32_t) * 64, s));
     hipLaunchKernelGGL(k_fstate_init, dim3(1), dim3(64), 0, s, st, n);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(nblk(n), 1024u)), dim3(TB), 0, s, xyz, n, st);
@@ -309,8 +310,14 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, out_xyz, out_index);
     CAPT_LAUNCH_CHECK();
     FState h;
+    uint32_t sort_err = 0;
     CAPT_HIP(hipMemcpyAsync(&h, st, sizeof(FState), hipMemcpyDeviceToHost, s));
+    CAPT_HIP(hipMemcpyAsync(&sort_err, rad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     CAPT_HIP(hipStreamSynchronize(s));
+    if (sort_err) {
+        set_error("internal: radix sort look-back bound exceeded in the filter");
+        return CAPT_EHIP;
+    }
     if (h.bad) {
         set_error("input holds %u non-finite coordinates", h.bad);
         return CAPT_EINVAL;

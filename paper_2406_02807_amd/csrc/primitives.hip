@@ -2,10 +2,10 @@
 //
 // Both work on tiles of 2048 elements per 256-thread workgroup (8 per
 // thread).  The scan is reduce -> scan of tile sums -> rescan-and-add.  The
-// sort makes one pass per 8-bit digit: per-tile digit histogram -> scan of the
-// digit-major histogram table -> stable scatter, where the rank of an element
-// among equal digits inside a tile comes from wave ballots (eight ballots
-// match the digit across the 64 lanes) and per-wave digit counts in LDS.
+// sort counts all digits once, then makes one kernel per 8-bit digit with
+// decoupled look-back for the tile offsets; the rank of an element among
+// equal digits inside a tile comes from wave ballots (eight ballots match the
+// digit across the 64 lanes) and per-wave digit counts in LDS.
 #include "capt_internal.h"
 
 namespace capt {
@@ -125,60 +125,125 @@ __global__ void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t n, const
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort
+// Radix sort (one sweep per digit)
 // ---------------------------------------------------------------------------
-template <class K>
-__global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift,
-                             uint32_t *__restrict__ hist, int64_t nb) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        int64_t j = base + (int64_t)i * TB + threadIdx.x;
-        if (j < n) {
-            uint32_t d = (uint32_t)(keys[j] >> shift) & 255u;
-            atomicAdd(&h[d], 1u);
-        }
-    }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+// k_os_hist counts every digit of every pass in one read of the keys (LSD
+// digit counts do not depend on the order).  Each pass is then ONE kernel:
+// a workgroup takes the next tile id from a counter (so ids follow launch
+// order), counts its tile's digits, publishes them, and obtains the count of
+// each digit in all earlier tiles by looking back over their published words
+// (decoupled look-back); the tile's ranks are then stable within the tile.
+// Published word: bits 30-31 = 1 (tile count) or 2 (inclusive prefix), bits
+// 0-29 = value.  A tile only waits for tiles with smaller ids, which started
+// before it, so the waits end; they are also bounded (see LOOKBACK_SPINS).
+constexpr uint32_t ST_AGG = 1u << 30;
+constexpr uint32_t ST_PRE = 2u << 30;
+constexpr uint32_t ST_VAL = (1u << 30) - 1u;
+constexpr uint32_t LOOKBACK_SPINS = 1u << 20;
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 template <class K>
-__global__ void k_radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
-                                int shift, const uint32_t *__restrict__ offs, int64_t nb) {
+__global__ void k_os_hist(const K *__restrict__ keys, int64_t n, int npass, uint32_t *__restrict__ ghist) {
+    __shared__ uint32_t h[8 * 256];
+    for (int i = threadIdx.x; i < npass * 256; i += TB) h[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * TB;
+    for (int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x; j < n; j += stride) {
+        const K k = keys[j];
+        for (int p = 0; p < npass; ++p) atomicAdd(&h[p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < npass * 256; i += TB)
+        if (h[i]) atomicAdd(&ghist[i], h[i]);
+}
+
+template <class K>
+__global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                   K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                                                   int shift, const uint32_t *__restrict__ ghist,
+                                                   uint32_t *__restrict__ status, uint32_t *__restrict__ tile_ctr,
+                                                   uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t cnt[256];
     __shared__ uint32_t run[256];
-    __shared__ uint32_t cnt[NW][256];
+    __shared__ uint32_t wc[NW][256];
+    __shared__ uint32_t lw[NW];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
-    const int64_t base = (int64_t)blockIdx.x * TILE;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const int64_t base = (int64_t)t * TILE;
+    for (int r = 0; r < IPT; ++r) {
+        const int64_t j = base + (int64_t)r * TB + threadIdx.x;
+        if (j < n) atomicAdd(&cnt[(uint32_t)(kin[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    // publish this tile's digit counts, then look back for the earlier tiles'
+    const int d = threadIdx.x;
+    const uint32_t c = cnt[d];
+    uint32_t excl = 0;
+    if (t == 0) {
+        store_agent(&status[d], ST_PRE | c);
+    } else {
+        store_agent(&status[(size_t)t * 256 + d], ST_AGG | c);
+        int64_t p = (int64_t)t - 1;
+        uint32_t spins = 0;
+        while (p >= 0) {
+            const uint32_t v = load_agent(&status[(size_t)p * 256 + d]);
+            const uint32_t flag = v & ~ST_VAL;
+            if (flag == 0) {
+                if (++spins > LOOKBACK_SPINS) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                continue;
+            }
+            excl += v & ST_VAL;
+            if (flag == ST_PRE) break;
+            --p;
+        }
+        store_agent(&status[(size_t)t * 256 + d], ST_PRE | (excl + c));
+    }
+    // global start of every digit: counts of smaller digits over all tiles
+    uint32_t tot;
+    const uint32_t gex = block_excl_scan(ghist[d], lw, &tot);
+    run[d] = gex + excl;
+    __syncthreads();
     for (int r = 0; r < IPT; ++r) {
 #pragma unroll
-        for (int q = 0; q < NW; ++q) cnt[q][threadIdx.x] = 0;
+        for (int q = 0; q < NW; ++q) wc[q][threadIdx.x] = 0;
         __syncthreads();
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
         const bool valid = j < n;
-        K key = valid ? kin[j] : K(0);
-        uint32_t val = valid ? vin[j] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
-        // lanes of this wave holding the same digit
+        const K key = valid ? kin[j] : K(0);
+        const uint32_t val = valid ? vin[j] : 0u;
+        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot(valid && ((d >> b) & 1u));
-            same &= ((d >> b) & 1u) ? bal : ~bal;
+            const uint64_t bal = __ballot(valid && ((dg >> b) & 1u));
+            same &= ((dg >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = __popcll(same & lt_mask);
-        if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(same);
+        const uint32_t rank = __popcll(same & lt_mask);
+        if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(same);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[d];
-            for (int q = 0; q < w; ++q) pos += cnt[q][d];
+            uint32_t pos = run[dg];
+            for (int q = 0; q < w; ++q) pos += wc[q][dg];
             pos += rank;
             kout[pos] = key;
             vout[pos] = val;
@@ -186,29 +251,42 @@ __global__ void k_radix_scatter(const K *__restrict__ kin, const uint32_t *__res
         __syncthreads();
         uint32_t add = 0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) add += cnt[q][threadIdx.x];
+        for (int q = 0; q < NW; ++q) add += wc[q][threadIdx.x];
         run[threadIdx.x] += add;
         __syncthreads();
     }
 }
 
+// tmp layout: [err (64 words)] [ghist npass*256] [tile counters 64] [status npass*ntiles*256].
+// The error word (tmp[0], set if a look-back wait ever exceeds its bound) is
+// not cleared here: callers clear it once and read it at their next sync.
 template <class K>
-capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int bits,
-                       uint32_t *tmp, hipStream_t s, int *where) {
+capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int bits, uint32_t *tmp, hipStream_t s,
+                       int *where) {
     *where = 0;
     if (n <= 1 || bits <= 0) return CAPT_OK;
-    const int64_t nb = (n + TILE - 1) / TILE;
-    uint32_t *hist = tmp;                         // 256 * nb
-    uint32_t *stmp = tmp + 256 * nb;              // scan scratch
+    if (n >= ((int64_t)1 << 30)) {
+        set_error("radix sort of %lld keys exceeds 2^30", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    const int npass = (bits + 7) / 8;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    uint32_t *err = tmp;
+    uint32_t *ghist = tmp + 64;
+    uint32_t *ctr = ghist + 8 * 256;
+    uint32_t *status = ctr + 64;
+    const int64_t words = 64 + 8 * 256 + 64 + (int64_t)npass * ntiles * 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 1024)), dim3(256), 0, s,
+                       tmp + 64, words - 64, 0u);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(TB), 0, s, k0, n, npass,
+                       ghist);
+    CAPT_LAUNCH_CHECK();
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
-    for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(TB), 0, s, ki, n, shift, hist, nb);
-        CAPT_LAUNCH_CHECK();
-        capt_status st = scan_exclusive_u32(hist, hist, 256 * nb, nullptr, nullptr, stmp, s);
-        if (st) return st;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(TB), 0, s, ki, vi, ko, vo, n,
-                           shift, hist, nb);
+    for (int p = 0; p < npass; ++p) {
+        hipLaunchKernelGGL(k_os_scatter<K>, dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, n, 8 * p,
+                           ghist + p * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
         CAPT_LAUNCH_CHECK();
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
@@ -240,8 +318,8 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, con
 }
 
 size_t radix_tmp_words(int64_t n) {
-    int64_t nb = (n + TILE - 1) / TILE;
-    return (size_t)(256 * nb) + scan_tmp_words(256 * nb);
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    return (size_t)(64 + 8 * 256 + 64 + 8 * ntiles * 256 + 64);
 }
 
 capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,

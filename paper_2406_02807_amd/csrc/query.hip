@@ -72,6 +72,7 @@ __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, in
 // 64k .. 64k+63: lane j takes pair 64k + j, whose sphere is the last lane o
 // with excl_o <= 64k + j (binary search).  The prefix is recomputed only when a
 // hit retires a configuration while others in the tile are still open.
+template <int U>
 __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L,
                                           const float4 *__restrict__ sph, int nsph, int g) {
     const int lane = lane_id();
@@ -109,51 +110,69 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
         if (total == 0) break;
         const uint32_t base_l = pos - excl;    // entry of pair slot s of this lane = base_l + s
         bool rescan = false;
-        for (uint32_t k0 = 0; k0 < total && !rescan; k0 += WAVE) {
-            const uint32_t slot = k0 + (uint32_t)lane;
-            int o = 0;
+        for (uint32_t k0 = 0; k0 < total && !rescan; k0 += U * WAVE) {
+            // U steps of 64 pairs in flight: owners, then loads, then tests
+            float ox[U], oy[U], oz[U], orr[U], px[U], py[U], pz[U];
+            bool in[U];
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const uint32_t e = __shfl(excl, o + step, WAVE);
-                if (e <= slot) o += step;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t slot = k0 + (uint32_t)(u * WAVE + lane);
+                in[u] = slot < total;
+                int o = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const uint32_t e = __shfl(excl, o + step, WAVE);
+                    if (e <= slot) o += step;
+                }
+                const uint32_t base = __shfl(base_l, o, WAVE);
+                const float cx = __shfl(q.x, o, WAVE);
+                const float cy = __shfl(q.y, o, WAVE);
+                const float cz = __shfl(q.z, o, WAVE);
+                const float cr = __shfl(r2, o, WAVE);
+                ox[u] = cx;
+                oy[u] = cy;
+                oz[u] = cz;
+                orr[u] = cr;
+                const uint32_t e = in[u] ? base + slot : 0u;
+                px[u] = in[u] ? PX[e] : 0.f;
+                py[u] = in[u] ? PY[e] : 0.f;
+                pz[u] = in[u] ? PZ[e] : 0.f;
             }
-            const uint32_t base = __shfl(base_l, o, WAVE);
-            const float ox = __shfl(q.x, o, WAVE);
-            const float oy = __shfl(q.y, o, WAVE);
-            const float oz = __shfl(q.z, o, WAVE);
-            const float orr = __shfl(r2, o, WAVE);
-            bool hit = false;
-            if (slot < total) {
-                const uint32_t e = base + slot;
-                hit = sqdist(ox, oy, oz, PX[e], PY[e], PZ[e]) <= orr;
+            uint64_t hm[U];
+            uint64_t any = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool hit = in[u] && sqdist(ox[u], oy[u], oz[u], px[u], py[u], pz[u]) <= orr[u];
+                hm[u] = __ballot(hit);
+                any |= hm[u];
             }
-            const uint64_t hm = __ballot(hit);
-            if (hm) {
+            if (any) {
+                rescan = true;
                 if (single) {
                     done = valid;
-                    rescan = true;
                 } else {
-                    // pairs of this lane inside the step: [excl, excl + rem) n [k0, k0 + 64)
-                    const uint32_t lo = max(excl, k0), hi = min(excl + rem, k0 + (uint32_t)WAVE);
                     bool mine = false;
-                    if (lo < hi) {
-                        const uint32_t w = hi - lo;
-                        const uint64_t m = w >= WAVE ? ~0ull : ((1ull << w) - 1);
-                        mine = ((hm >> (lo - k0)) & m) != 0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const uint32_t c0 = k0 + (uint32_t)(u * WAVE);
+                        const uint32_t lo = max(excl, c0), hi = min(excl + rem, c0 + (uint32_t)WAVE);
+                        if (lo < hi) {
+                            const uint32_t w = hi - lo;
+                            const uint64_t m = w >= WAVE ? ~0ull : ((1ull << w) - 1);
+                            mine = mine || (((hm[u] >> (lo - c0)) & m) != 0);
+                        }
                     }
                     const uint64_t sh = __ballot(mine);
                     if (valid) done = done || (((sh >> (cfg * gg)) & gmask) != 0);
-                    // consume what this step covered, then rebuild the prefix
-                    const uint32_t end = k0 + (uint32_t)WAVE;
+                    // consume what these steps covered, then rebuild the prefix
+                    const uint32_t end = k0 + (uint32_t)(U * WAVE);
                     const uint32_t used = end <= excl ? 0u : min(rem, end - excl);
                     rem -= used;
                     pos += used;
-                    rescan = true;
                 }
             }
         }
-        if (!rescan) break;   // every pair consumed without a hit
-        if (single) break;
+        if (!rescan || single) break;   // all pairs consumed, or the configuration is hit
     }
     return done;
 }
@@ -164,6 +183,7 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
 constexpr int NXCD = 8;
 constexpr int CTR_STRIDE = 16;   // one 64-byte line per counter
 
+template <int U>
 __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float Tl[];
@@ -188,13 +208,13 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
             if (g <= WAVE) {
                 const int64_t c0 = t * cpt;
                 const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-                const bool hit = wave_tile(C, Tl, L, sph + c0 * g, nc * g, g);
+                const bool hit = wave_tile<U>(C, Tl, L, sph + c0 * g, nc * g, g);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             } else {
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile(C, Tl, L, sph + t * g + s0, ns, g);
+                    hit = wave_tile<U>(C, Tl, L, sph + t * g + s0, ns, g);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[t] = (uint8_t)hit;
@@ -219,6 +239,7 @@ __global__ void k_reset_counter(unsigned int *ctr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = 0u;
 }
 
+template <int U>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
                                   const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
@@ -235,7 +256,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
-                const bool hit = wave_tile(C, nullptr, 0, sph + c0 * g, nc * g, g);
+                const bool hit = wave_tile<U>(C, nullptr, 0, sph + c0 * g, nc * g, g);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -244,7 +265,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile(C, nullptr, 0, sph + cc * g + s0, ns, g);
+                    hit = wave_tile<U>(C, nullptr, 0, sph + cc * g + s0, ns, g);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[cc] = (uint8_t)hit;
@@ -355,7 +376,7 @@ __global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r
 }  // namespace
 
 capt_tuning &tuning() {
-    static capt_tuning t = {16, 2, 64, 14};
+    static capt_tuning t = {16, 4, 16, 14, 4};
     return t;
 }
 
@@ -411,8 +432,21 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_collide_cloud, dim3((unsigned)blocks), dim3(threads), lds, s, C,
-                       reinterpret_cast<const float4 *>(spheres), nsph, g, out, L, ctr, chunk);
+    const float4 *sp = reinterpret_cast<const float4 *>(spheres);
+    switch (t.scan_unroll) {
+        case 4:
+            hipLaunchKernelGGL(k_collide_cloud<4>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
+                               ctr, chunk);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_collide_cloud<2>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
+                               ctr, chunk);
+            break;
+        default:
+            hipLaunchKernelGGL(k_collide_cloud<1>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
+                               ctr, chunk);
+            break;
+    }
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }
@@ -469,9 +503,21 @@ capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p->d_ctr);
     CAPT_LAUNCH_CHECK();
     if (p->ntiles > 0) {
-        hipLaunchKernelGGL(k_collide_batched, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
-                           p->d_tiles, p->ntiles, p->d_ctr, reinterpret_cast<const float4 *>(p->spheres),
-                           p->group, p->out);
+        const float4 *sp = reinterpret_cast<const float4 *>(p->spheres);
+        switch (t.scan_unroll) {
+            case 4:
+                hipLaunchKernelGGL(k_collide_batched<4>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_collide_batched<2>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                break;
+            default:
+                hipLaunchKernelGGL(k_collide_batched<1>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                break;
+        }
         CAPT_LAUNCH_CHECK();
     }
     return CAPT_OK;
@@ -479,7 +525,7 @@ capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
 
 bool same_tuning(const capt_tuning &a, const capt_tuning &b) {
     return a.waves_per_group == b.waves_per_group && a.groups_per_cu == b.groups_per_cu &&
-           a.tile_cfgs == b.tile_cfgs && a.lds_levels == b.lds_levels;
+           a.tile_cfgs == b.tile_cfgs && a.lds_levels == b.lds_levels && a.scan_unroll == b.scan_unroll;
 }
 
 }  // namespace

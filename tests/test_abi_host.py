@@ -78,7 +78,9 @@ def test_no_gpu_needed_for_validation(lib):
     junk = C.create_string_buffer(b"\x00" * 64, 64)
     assert lib.capt_import(junk, 64, None, C.byref(h)) == capt.CAPT_EINVAL
     # tuning ranges
-    t = capt.capt_tuning(17, 0, 0, 0)
+    t = capt.capt_tuning(17, 0, 0, 0, 0)
+    assert lib.capt_set_tuning(C.byref(t)) == capt.CAPT_EINVAL
+    t = capt.capt_tuning(0, 0, 0, 0, 3)
     assert lib.capt_set_tuning(C.byref(t)) == capt.CAPT_EINVAL
     # allocator: both or neither
     assert lib.capt_set_allocator(P(1), None, None) == capt.CAPT_EINVAL

@@ -309,3 +309,20 @@ def test_full_size_tabletop_1M_configurations(capt, orc):
     sub = w.spheres.reshape(-1, 60, 4)[cfg].reshape(-1, 4)
     want = orc.brute_f32(w.cloud[keep], sub, 60)
     assert np.array_equal(got[cfg], want)
+
+
+def test_autotuned_shapes_give_identical_answers(capt, orc):
+    from paper_2406_02807_amd import autotune
+    pts = synth.tabletop_cloud(6000, 61)
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    sph = synth.posed_spheres(synth.chain_template(2003), 2000, synth.WORKSPACE, 62)
+    before = capt.capt_get_tuning()
+    try:
+        space = {"waves_per_group": [4, 16], "groups_per_cu": [1, 4], "lds_levels": [8, 14],
+                 "scan_unroll": [1, 2, 4]}
+        best, hist = autotune.autotune(f, dev(sph), 60, space=space, reps=1, rounds=1)
+        assert len(hist) >= 5
+        got = capt.capt_collides(f, dev(sph), 60).cpu().numpy()
+        assert np.array_equal(got, orc.brute_f32(pts, sph, 60))
+    finally:
+        capt.capt_set_tuning(**before)
