@@ -7,10 +7,14 @@
 //  2. the sequential rule "keep j iff it is farther than r_filter from the
 //     last kept point" is made parallel: next[j] = first k > j farther than
 //     r_filter from j, so the kept points are exactly the chain
-//     0 -> next[0] -> next[next[0]] -> ...  The chain is marked with pointer
-//     doubling: jump tables J_t = next^(2^t), then, for t from high to low,
-//     every node marked at a level above t marks J_t of itself;
-//  3. a scan of the marks compacts the survivors in curve order.
+//     0 -> next[0] -> next[next[0]] -> ...  One kernel resolves the chain in
+//     chunks of 2048 positions: a chunk builds the jump tables
+//     J_t = next^(2^t) of its positions in LDS, waits for the previous chunk
+//     to publish where the chain enters it, follows the tables to the chain's
+//     exit and publishes that for the next chunk; it then marks the chain's
+//     nodes inside the chunk top-down over the tables and writes them, in
+//     order, at an offset found by decoupled look-back over earlier chunks'
+//     survivor counts.
 // Only the final count crosses to the host.
 #include <cmath>
 
@@ -29,7 +33,7 @@ struct FState {
     float lo[3];
     float hi[3];
     double scale;
-    int64_t m;          // current number of points
+    int64_t mm[2];      // point count before / after the current pass (alternating)
     unsigned int bad;   // non-finite coordinates
 };
 
@@ -39,7 +43,8 @@ __global__ void k_fstate_init(FState *st, int64_t n) {
             st->lo[a] = INFINITY;
             st->hi[a] = -INFINITY;
         }
-        st->m = n;
+        st->mm[0] = n;
+        st->mm[1] = 0;
         st->bad = 0;
         st->scale = 0.0;
     }
@@ -99,6 +104,11 @@ __global__ void k_grid(FState *st) {
     st->scale = E > 0.0 ? 2097152.0 / E : 0.0;
 }
 
+__global__ void k_clear_u32(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void k_iota(uint32_t *__restrict__ v, int64_t n) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n) v[j] = (uint32_t)j;
@@ -130,7 +140,7 @@ __global__ void k_morton(const float *__restrict__ xyz, const uint32_t *__restri
                          uint32_t *__restrict__ vals) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const int64_t m = st->m;
+    const int64_t m = st->mm[p & 1];
     if (j >= m) {
         keys[j] = ~0ull;
         vals[j] = 0xFFFFFFFFu;
@@ -144,72 +154,184 @@ __global__ void k_morton(const float *__restrict__ xyz, const uint32_t *__restri
     vals[j] = id;
 }
 
-__global__ void k_next(const float *__restrict__ xyz, const uint32_t *__restrict__ ord, int64_t n,
-                       const FState *__restrict__ st, float rf2, uint32_t *__restrict__ next) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t m = st->m;
-    if (j > m || j >= n + 1) return;
-    if (j == m) {
-        next[j] = (uint32_t)m;
-        return;
+constexpr int CT = 256;              // threads of the chain kernel
+constexpr int CI = 8;                // positions per thread
+constexpr int CC = CT * CI;          // chunk length
+constexpr int CR = 11;               // log2(CC): jump tables J_0 .. J_10
+constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"
+constexpr uint32_t PUB = 0x80000000u;
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_c(uint32_t v, uint32_t *lw, uint32_t *total) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += t;
     }
-    const uint32_t a = ord[j];
-    const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
-    int64_t k = j + 1;
-    for (; k < m; ++k) {
-        const uint32_t b = ord[k];
-        if (sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2) break;
+    if (lane == WAVE - 1) lw[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < CT / WAVE; ++i) {
+        const uint32_t t = lw[i];
+        off += (i < w) ? t : 0u;
+        tot += t;
     }
-    next[j] = (uint32_t)k;
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
 }
 
-__global__ void k_jump(const uint32_t *__restrict__ Jp, uint32_t *__restrict__ Jn, int64_t n,
-                       const FState *__restrict__ st) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > st->m || j >= n + 1) return;
-    Jn[j] = Jp[Jp[j]];
-}
-
-__global__ void k_mark_init(int8_t *__restrict__ mark, int64_t n, int top) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n + 1) mark[j] = (int8_t)(j == 0 ? top : -1);
-}
-
-__global__ void k_mark_step(const uint32_t *__restrict__ J, int8_t *__restrict__ mark, int64_t n,
-                            const FState *__restrict__ st, int t) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t m = st->m;
-    if (j >= m || j >= n) return;
-    if (mark[j] > t) {
-        const uint32_t k = J[j];
-        if ((int64_t)k < m) mark[k] = (int8_t)t;
+// One filter pass's keep decisions and compaction (see the file comment).
+// ord: the current points in curve order (original ids); the survivors go to
+// out in the same order and their count to st->mm[(p + 1) & 1].
+__global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ xyz, const uint32_t *__restrict__ ord,
+                                                    FState *__restrict__ st, int p, float rf2,
+                                                    uint32_t *__restrict__ exit_pub, uint32_t *__restrict__ kept_st,
+                                                    uint32_t *__restrict__ chunk_ctr, uint32_t *__restrict__ out,
+                                                    uint32_t *__restrict__ err) {
+    __shared__ uint16_t J[CR][CC];
+    __shared__ uint32_t Nx[CC];
+    __shared__ int8_t mark[CC];
+    __shared__ uint32_t s_chunk, s_entry, s_prefix;
+    __shared__ uint32_t lw[CT / WAVE];
+    if (threadIdx.x == 0) s_chunk = atomicAdd(chunk_ctr, 1u);
+    __syncthreads();
+    const int64_t c = s_chunk;
+    const int64_t m = st->mm[p & 1];
+    const int64_t cs = c * CC;
+    if (cs >= m) return;                      // no position of the chain here (uniform)
+    const int64_t ce = min(cs + (int64_t)CC, m);
+    const int len = (int)(ce - cs);
+    // 1. next pointers and the first jump table
+    for (int i = threadIdx.x; i < CC; i += CT) {
+        if (i < len) {
+            const int64_t j = cs + i;
+            const uint32_t a = ord[j];
+            const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
+            int64_t k = j + 1;
+            for (; k < m; ++k) {
+                const uint32_t b = ord[k];
+                if (sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2)
+                    break;
+            }
+            Nx[i] = (uint32_t)k;
+            J[0][i] = k < ce ? (uint16_t)(k - cs) : OUTL;
+        } else {
+            J[0][i] = OUTL;
+        }
     }
-}
-
-__global__ void k_keep_flags(const int8_t *__restrict__ mark, int64_t n, const FState *__restrict__ st,
-                             uint32_t *__restrict__ flags) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    flags[j] = (j < st->m && mark[j] >= 0) ? 1u : 0u;
-}
-
-__global__ void k_compact(const uint32_t *__restrict__ ord, const uint32_t *__restrict__ flags,
-                          const uint32_t *__restrict__ pos, int64_t n, const FState *__restrict__ st,
-                          uint32_t *__restrict__ cur) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n || j >= st->m) return;
-    if (flags[j]) cur[pos[j]] = ord[j];
-}
-
-__global__ void k_set_count(FState *st, const uint32_t *total) {
-    if (threadIdx.x == 0) st->m = (int64_t)*total;
+    __syncthreads();
+    // 2. jump tables J_t = next^(2^t) inside the chunk
+    for (int t = 1; t < CR; ++t) {
+        for (int i = threadIdx.x; i < CC; i += CT) {
+            const uint16_t v = J[t - 1][i];
+            J[t][i] = v == OUTL ? OUTL : J[t - 1][v];
+        }
+        __syncthreads();
+    }
+    // 3. where the chain enters this chunk, where it leaves; publish the exit
+    if (threadIdx.x == 0) {
+        uint32_t X = 0;
+        if (c > 0) {
+            uint32_t v = 0, spins = 0;
+            while (((v = ld_agent(&exit_pub[c - 1])) & PUB) == 0) {
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(err, 2u);
+                    break;
+                }
+            }
+            X = v & ~PUB;
+        }
+        uint32_t ex = X;
+        if ((int64_t)X < ce) {
+            int cur = (int)(X - cs);
+            for (int t = CR - 1; t >= 0; --t)
+                if (J[t][cur] != OUTL) cur = J[t][cur];
+            ex = Nx[cur];
+        }
+        st_agent(&exit_pub[c], PUB | ex);
+        s_entry = X;
+    }
+    for (int i = threadIdx.x; i < CC; i += CT) mark[i] = -1;
+    __syncthreads();
+    // 4. mark the chain inside the chunk, top-down over the tables
+    const int64_t X = s_entry;
+    if (X < ce) {
+        if (threadIdx.x == 0) mark[X - cs] = (int8_t)CR;
+        __syncthreads();
+        for (int t = CR - 1; t >= 0; --t) {
+            for (int i = threadIdx.x; i < len; i += CT)
+                if (mark[i] > t) {
+                    const uint16_t k = J[t][i];
+                    if (k != OUTL) mark[k] = (int8_t)t;
+                }
+            __syncthreads();
+        }
+    }
+    // 5. survivors of the chunk, in order
+    uint32_t f[CI];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < CI; ++u) {
+        const int i = threadIdx.x * CI + u;
+        f[u] = (i < len && mark[i] >= 0) ? 1u : 0u;
+        cnt += f[u];
+    }
+    uint32_t kept;
+    uint32_t off = block_excl_scan_c(cnt, lw, &kept);
+    // 6. offset of the chunk's survivors: look back over earlier chunks
+    if (threadIdx.x == 0) {
+        uint32_t excl = 0;
+        if (c == 0) {
+            st_agent(&kept_st[0], 0x80000000u | kept);
+        } else {
+            st_agent(&kept_st[c], 0x40000000u | kept);
+            int64_t q = c - 1;
+            uint32_t spins = 0;
+            while (q >= 0) {
+                const uint32_t v = ld_agent(&kept_st[q]);
+                const uint32_t flag = v & 0xC0000000u;
+                if (flag == 0) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(err, 4u);
+                        break;
+                    }
+                    continue;
+                }
+                excl += v & 0x3FFFFFFFu;
+                if (flag == 0x80000000u) break;
+                --q;
+            }
+            st_agent(&kept_st[c], 0x80000000u | (excl + kept));
+        }
+        s_prefix = excl;
+        if (ce == m) st->mm[(p + 1) & 1] = (int64_t)(excl + kept);
+    }
+    __syncthreads();
+    off += s_prefix;
+#pragma unroll
+    for (int u = 0; u < CI; ++u) {
+        const int i = threadIdx.x * CI + u;
+        if (f[u]) out[off++] = ord[cs + i];
+    }
 }
 
 __global__ void k_output(const float *__restrict__ xyz, const uint32_t *__restrict__ cur, int64_t n,
                          const FState *__restrict__ st, float *__restrict__ out_xyz,
                          int32_t *__restrict__ out_index) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n || j >= st->m) return;
+    if (j >= n || j >= st->mm[0]) return;
     const uint32_t id = cur[j];
     out_xyz[3 * j] = xyz[3 * (int64_t)id];
     out_xyz[3 * j + 1] = xyz[3 * (int64_t)id + 1];
@@ -225,10 +347,8 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
         *n_out = 0;
         return CAPT_OK;
     }
-    int levels = 1;
-    while (((int64_t)1 << levels) < n + 1) ++levels;
-    levels += 1;   // J_0 .. J_{levels-1} reach past the chain's end
     const size_t wn = (size_t)n + 1;
+    const int64_t nchunk = (n + CC - 1) / CC;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -241,13 +361,8 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     const size_t oK1 = take(sizeof(uint64_t) * wn);
     const size_t oV0 = take(sizeof(uint32_t) * wn);
     const size_t oV1 = take(sizeof(uint32_t) * wn);
-    const size_t oJ = take(sizeof(uint32_t) * wn * (size_t)levels);
-    const size_t oMark = take(wn);
-    const size_t oFlag = take(sizeof(uint32_t) * wn);
-    const size_t oPos = take(sizeof(uint32_t) * wn);
-    const size_t oTot = take(sizeof(uint32_t) * 4);
+    const size_t oPub = take(sizeof(uint32_t) * (size_t)(2 * nchunk + 64));   // exits, survivor counts, counter
     const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words((int64_t)wn));
-    const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words((int64_t)wn));
     Scratch sc;
     if (!sc.alloc(off, s)) {
         set_error("device allocation of %zu filter scratch bytes failed", off);
@@ -260,19 +375,16 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     uint64_t *k1 = reinterpret_cast<uint64_t *>(B + oK1);
     uint32_t *v0 = reinterpret_cast<uint32_t *>(B + oV0);
     uint32_t *v1 = reinterpret_cast<uint32_t *>(B + oV1);
-    uint32_t *J = reinterpret_cast<uint32_t *>(B + oJ);
-    int8_t *mark = reinterpret_cast<int8_t *>(B + oMark);
-    uint32_t *flags = reinterpret_cast<uint32_t *>(B + oFlag);
-    uint32_t *pos = reinterpret_cast<uint32_t *>(B + oPos);
-    uint32_t *tot = reinterpret_cast<uint32_t *>(B + oTot);
+    uint32_t *pub = reinterpret_cast<uint32_t *>(B + oPub);
     uint32_t *rad = reinterpret_cast<uint32_t *>(B + oRad);
-    uint32_t *stmp = reinterpret_cast<uint32_t *>(B + oScan);
+    uint32_t *exit_pub = pub, *kept_st = pub + nchunk, *chunk_ctr = pub + 2 * nchunk;
+    const int64_t npub = 2 * nchunk + 64;
 
     const float rf2 = r_filter * r_filter;
     CAPT_HIP(hipMemsetAsync(rad, 0, sizeof(uint32_t) * 64, s));
     hipLaunchKernelGGL(k_fstate_init, dim3(1), dim3(64), 0, s, st, n);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(nblk(n), 1024u)), dim3(TB), 0, s, xyz, n, st);
+    hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(nblk(n), 16u)), dim3(TB), 0, s, xyz, n, st);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, st);
     CAPT_LAUNCH_CHECK();
@@ -285,26 +397,10 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
         capt_status e = radix_sort_u64(k0, v0, k1, v1, n, 64, rad, s, &where);
         if (e) return e;
         const uint32_t *ord = where ? v1 : v0;
-        hipLaunchKernelGGL(k_next, dim3(nblk(n + 1)), dim3(TB), 0, s, xyz, ord, n, st, rf2, J);
+        hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)((npub + 255) / 256)), dim3(256), 0, s, pub, npub);
         CAPT_LAUNCH_CHECK();
-        for (int t = 1; t < levels; ++t) {
-            hipLaunchKernelGGL(k_jump, dim3(nblk(n + 1)), dim3(TB), 0, s, J + (size_t)(t - 1) * wn,
-                               J + (size_t)t * wn, n, st);
-            CAPT_LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_mark_init, dim3(nblk(n + 1)), dim3(TB), 0, s, mark, n, levels);
-        CAPT_LAUNCH_CHECK();
-        for (int t = levels - 1; t >= 0; --t) {
-            hipLaunchKernelGGL(k_mark_step, dim3(nblk(n)), dim3(TB), 0, s, J + (size_t)t * wn, mark, n, st, t);
-            CAPT_LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_keep_flags, dim3(nblk(n)), dim3(TB), 0, s, mark, n, st, flags);
-        CAPT_LAUNCH_CHECK();
-        capt_status e2 = scan_exclusive_u32(flags, pos, n, nullptr, tot, stmp, s);
-        if (e2) return e2;
-        hipLaunchKernelGGL(k_compact, dim3(nblk(n)), dim3(TB), 0, s, ord, flags, pos, n, st, cur);
-        CAPT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, s, st, tot);
+        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), 0, s, xyz, ord, st, p, rf2, exit_pub,
+                           kept_st, chunk_ctr, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, out_xyz, out_index);
@@ -315,14 +411,14 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     CAPT_HIP(hipMemcpyAsync(&sort_err, rad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     CAPT_HIP(hipStreamSynchronize(s));
     if (sort_err) {
-        set_error("internal: radix sort look-back bound exceeded in the filter");
+        set_error("internal: a look-back wait bound was exceeded in the filter (code %u)", sort_err);
         return CAPT_EHIP;
     }
     if (h.bad) {
         set_error("input holds %u non-finite coordinates", h.bad);
         return CAPT_EINVAL;
     }
-    *n_out = h.m;
+    *n_out = h.mm[0];
     return CAPT_OK;
 }
 

@@ -187,9 +187,19 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     __syncthreads();
     const uint32_t t = s_tile;
     const int64_t base = (int64_t)t * TILE;
+    // the tile's items stay in registers for the whole pass (one load round)
+    K key[IPT];
+    uint32_t val[IPT];
+#pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        if (j < n) atomicAdd(&cnt[(uint32_t)(kin[j] >> shift) & 255u], 1u);
+        key[r] = j < n ? kin[j] : K(0);
+        val[r] = j < n ? vin[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int64_t j = base + (int64_t)r * TB + threadIdx.x;
+        if (j < n) atomicAdd(&cnt[(uint32_t)(key[r] >> shift) & 255u], 1u);
     }
     __syncthreads();
     // publish this tile's digit counts, then look back for the earlier tiles'
@@ -223,15 +233,14 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     const uint32_t gex = block_excl_scan(ghist[d], lw, &tot);
     run[d] = gex + excl;
     __syncthreads();
+#pragma unroll
     for (int r = 0; r < IPT; ++r) {
 #pragma unroll
         for (int q = 0; q < NW; ++q) wc[q][threadIdx.x] = 0;
         __syncthreads();
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
         const bool valid = j < n;
-        const K key = valid ? kin[j] : K(0);
-        const uint32_t val = valid ? vin[j] : 0u;
-        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -245,8 +254,8 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
             uint32_t pos = run[dg];
             for (int q = 0; q < w; ++q) pos += wc[q][dg];
             pos += rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            kout[pos] = key[r];
+            vout[pos] = val[r];
         }
         __syncthreads();
         uint32_t add = 0;
