@@ -10,9 +10,10 @@ One step = filter -> build -> collide, the whole collision path, on inputs
 already resident in HBM.  `value` is sphere queries per second over the whole
 step (60,000,000 spheres / step time).  Printed as one JSON line, with:
   roofline      the query kernel's algorithmic bytes (per configuration: the
-                spheres, leaf records and set entries a sequential scan in
-                stored order reads up to the first colliding sphere) over its
-                HIP-event-timed duration, against 8 TB/s
+                spheres, leaf records, chunk boxes and surviving 16-entry
+                chunks that a sequential two-level scan in stored order reads
+                up to the first colliding sphere) over its HIP-event-timed
+                duration, against 8 TB/s
   cpu_baseline  the oracle's filter + build + CollisionCheck (one thread, early
                 exit per configuration) on the same workload
   brute         the GPU brute force on the same spheres (answers compared)
@@ -39,6 +40,8 @@ HBM_PEAK_GBS = 8000.0
 LEAF_BYTES = 32      # AABB (24 B) + set start and length (8 B)
 SPHERE_BYTES = 16
 ENTRY_BYTES = 12     # x, y, z of one set entry
+BOX_BYTES = 32       # one chunk box (two float4)
+CHUNK = 16           # set entries per chunk
 
 
 def log(*a):
@@ -46,25 +49,36 @@ def log(*a):
 
 
 def algorithmic_bytes(capt, forest, spheres_dev, group):
-    """Sum over configurations of the bytes a sequential scan in stored order
-    reads up to (and including) the first colliding sphere, plus one output
+    """Sum over configurations of the bytes a sequential two-level scan in
+    stored order reads up to (and including) the first colliding sphere: per
+    sphere its 16 bytes and leaf record, then, unless the leaf AABB rejects
+    it, the chunk boxes it tests and the 16 entries of every chunk whose box
+    is within reach, up to the chunk holding its first hit; plus one output
     byte per configuration."""
     import torch
     leaf, rej, scanned, hit = capt.capt_query_stats(forest, spheres_dev)
+    boxes, chunks = capt.capt_query_chunk_stats(forest, spheres_dev)
     torch.cuda.synchronize()
     rej = rej.cpu().numpy().astype(np.int64)
     sc = scanned.cpu().numpy().astype(np.int64)
     hit = hit.cpu().numpy().astype(bool)
-    per = SPHERE_BYTES + LEAF_BYTES + ENTRY_BYTES * np.where(rej == 1, 0, sc)
+    nb = boxes.cpu().numpy().astype(np.int64)
+    nc = chunks.cpu().numpy().astype(np.int64)
+    per = SPHERE_BYTES + LEAF_BYTES + BOX_BYTES * nb + CHUNK * ENTRY_BYTES * nc
     per = per.reshape(-1, group)
     h = hit.reshape(-1, group)
     first = np.where(h.any(1), h.argmax(1), group - 1)
     mask = np.arange(group)[None, :] <= first[:, None]
     canonical = int((per * mask).sum()) + h.shape[0]
+    m = mask.reshape(-1)
     return canonical, {
         "aabb_reject_rate": float(rej.mean()),
         "mean_scanned_per_sphere": float(sc.mean()),
         "spheres_read_canonical": int(mask.sum()),
+        "one_level_bytes_canonical": int(((SPHERE_BYTES + LEAF_BYTES + ENTRY_BYTES * np.where(rej == 1, 0, sc))
+                                          * m).sum()) + h.shape[0],
+        "mean_boxes_per_read_sphere": float(nb[m].mean()) if m.any() else 0.0,
+        "mean_chunks_per_read_sphere": float(nc[m].mean()) if m.any() else 0.0,
     }
 
 

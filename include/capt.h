@@ -218,13 +218,29 @@ capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t 
                              void *stream);
 
 /*
+ * Work of the collision kernel's two-level set scan (not on the hot path).
+ * capt_collides stores every set as chunks of 16 entries, each with a float32
+ * bounding box, tests the boxes and scans only the entries of chunks whose
+ * box lies within the sphere's radius; a box is never farther than any of its
+ * points, so the answers are those of the full scan of Alg. 3.  Per sphere
+ * whose leaf AABB does not reject it, for a scan in stored order up to and
+ * including the chunk that holds its first hit (all chunks if none):
+ *   boxes  [M] int32  chunk boxes tested
+ *   chunks [M] int32  chunks whose 16 entries were tested
+ * Both are 0 for a rejected sphere.  Either output may be NULL.
+ */
+capt_status capt_query_chunk_stats(capt_forest f, const float *spheres, const int64_t *query_off,
+                                   int32_t *boxes, int32_t *chunks, void *stream);
+
+/*
  * Launch shape of the collision kernels (chosen by the autotuner).
  *   waves_per_group  wavefronts per workgroup (1 .. 16)
  *   groups_per_cu    persistent workgroups per compute unit (1 .. 16)
  *   tile_cfgs        configurations a wavefront takes per queue pop in the
  *                    batched kernel (1 .. 4096)
  *   lds_levels       tree levels kept in LDS (1 .. 14)
- *   scan_unroll      64-pair steps of the set scan kept in flight (1, 2 or 4)
+ *   scan_unroll      64-lane steps of the entry scan kept in flight, 4 chunks
+ *                    per step (1, 2 or 4)
  * Zero fields keep their current value.  Applies to later calls.
  */
 typedef struct {

@@ -28,7 +28,7 @@ CAPT_NO_GRAPH = 0x8
 EXPORTS = [
     "capt_filter", "capt_build", "capt_collides", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
-    "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_set_tuning",
+    "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning",
     "capt_get_tuning",
 ]
 
@@ -69,6 +69,7 @@ def load_library(path: str = LIB_PATH):
         "capt_set_allocator": [P, P, P],
         "capt_bruteforce_collides": [P, P, i32, P, P, i32, P, P],
         "capt_query_stats": [P, P, P, P, P, P, P, P],
+        "capt_query_chunk_stats": [P, P, P, P, P, P],
         "capt_set_tuning": [P],
         "capt_get_tuning": [P],
     }
@@ -272,6 +273,21 @@ def capt_query_stats(forest: Forest, spheres, query_off=None, stream=None):
     _check(lib.capt_query_stats(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p),
                                 _ptr(leaf), _ptr(rej), _ptr(sc), _ptr(hit), _stream(stream)))
     return leaf, rej, sc, hit
+
+
+def capt_query_chunk_stats(forest: Forest, spheres, query_off=None, stream=None):
+    """Per sphere: (chunk boxes tested int32, chunks scanned int32) of the
+    two-level set scan, in stored order up to the chunk of the first hit."""
+    import torch
+    lib = load_library()
+    spheres = _dev(spheres, torch.float32, 4, "spheres")
+    M = spheres.shape[0]
+    off = _offsets([0, M] if query_off is None else query_off, forest.ncloud)
+    boxes = torch.empty((M,), dtype=torch.int32, device=spheres.device)
+    chunks = torch.empty((M,), dtype=torch.int32, device=spheres.device)
+    _check(lib.capt_query_chunk_stats(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p),
+                                      _ptr(boxes), _ptr(chunks), _stream(stream)))
+    return boxes, chunks
 
 
 def capt_set_tuning(waves_per_group=0, groups_per_cu=0, tile_cfgs=0, lds_levels=0, scan_unroll=0):

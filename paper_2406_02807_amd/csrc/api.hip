@@ -89,7 +89,7 @@ const DeviceInfo &device_info() {
         if (hipGetDeviceProperties(&p, dev) != hipSuccess) return;
         info.cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
         info.lds_per_block = p.sharedMemPerBlock > 0 ? (int)p.sharedMemPerBlock : 65536;
-        if (info.lds_per_block > 65536) info.lds_per_block = 65536;
+        if (info.lds_per_block > 163840) info.lds_per_block = 163840;
     });
     return info;
 }
@@ -500,7 +500,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
             return CAPT_EUNSUPPORTED;
         }
     }
-    const size_t E = (size_t)std::max<int64_t>(padded, 1);
+    const size_t E = (size_t)std::max<int64_t>(padded, (int64_t)CHUNK);
     std::vector<float> px(E, INFINITY), py(E, INFINITY), pz(E, INFINITY);
     std::vector<int32_t> pidx(E, -1);
     for (int64_t l = 0; l < h.N; ++l)
@@ -539,7 +539,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const size_t oPr = al(oRep + sizeof(int32_t) * (size_t)h.N);
     c.fixed_bytes = al(oPr + (size_t)h.N);
     c.fixed = dev_alloc(c.fixed_bytes, s);
-    c.sets_bytes = al(sizeof(float) * E) * 3 + al(sizeof(int32_t) * E);
+    c.sets_bytes = sets_bytes(E);
     c.sets = dev_alloc(c.sets_bytes, s);
     if (!c.fixed || !c.sets) {
         destroy_forest(f);
@@ -547,16 +547,22 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
         return CAPT_ENOMEM;
     }
     char *F = static_cast<char *>(c.fixed);
-    char *P = static_cast<char *>(c.sets);
     c.dev.T = reinterpret_cast<float *>(F + oT);
     c.dev.leaf = reinterpret_cast<Leaf *>(F + oLeaf);
     c.dev.pts = reinterpret_cast<float *>(F + oPts);
     c.rep = reinterpret_cast<int32_t *>(F + oRep);
     c.pruned_flag = reinterpret_cast<uint8_t *>(F + oPr);
-    c.dev.px = reinterpret_cast<float *>(P);
-    c.dev.py = reinterpret_cast<float *>(P + al(sizeof(float) * E));
-    c.dev.pz = reinterpret_cast<float *>(P + 2 * al(sizeof(float) * E));
-    c.dev.pidx = reinterpret_cast<int32_t *>(P + 3 * al(sizeof(float) * E));
+    {
+        float *qx, *qy, *qz;
+        int32_t *qi;
+        float4 *qb;
+        sets_layout(c.sets, E, &qx, &qy, &qz, &qi, &qb);
+        c.dev.px = qx;
+        c.dev.py = qy;
+        c.dev.pz = qz;
+        c.dev.pidx = qi;
+        c.dev.cbox = qb;
+    }
     c.dev.n = h.n;
     c.dev.D = h.D;
     c.dev.flags = h.flags;
@@ -574,6 +580,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);
     if (!st) st = cp(const_cast<float *>(c.dev.pz), pz.data(), sizeof(float) * E);
     if (!st) st = cp(const_cast<int32_t *>(c.dev.pidx), pidx.data(), sizeof(int32_t) * E);
+    if (!st) st = chunk_boxes(c.dev.px, c.dev.py, c.dev.pz, c.dev.pidx, padded, const_cast<float4 *>(c.dev.cbox), s);
     if (!st) st = upload_views(f, s);
     if (st) {
         destroy_forest(f);
@@ -616,6 +623,14 @@ capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t 
     capt_status st = check_queries(f, spheres, query_off, 1);
     if (st) return st;
     return query_stats(f, spheres, query_off, leaf, rejected, scanned, hit, (hipStream_t)stream);
+}
+
+capt_status capt_query_chunk_stats(capt_forest f, const float *spheres, const int64_t *query_off, int32_t *boxes,
+                                   int32_t *chunks, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, 1);
+    if (st) return st;
+    return chunk_stats(f, spheres, query_off, boxes, chunks, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -732,7 +732,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bb);
     CAPT_LAUNCH_CHECK();
     if (n > 0) {
-        hipLaunchKernelGGL(k_grid_bbox, dim3(std::min<unsigned>(nblk(n), 512u)), dim3(TB), 0, s, xyz, n, bb);
+        hipLaunchKernelGGL(k_grid_bbox, dim3(std::min<unsigned>(nblk(n), 16u)), dim3(TB), 0, s, xyz, n, bb);
         CAPT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, bb, R, cell_cap, grid);
@@ -789,27 +789,27 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
         set_error("affordance sets hold %llu entries, more than 2^32", tot[1]);
         return CAPT_EUNSUPPORTED;
     }
-    const size_t E = (size_t)(tot[1] > 0 ? tot[1] : 1);
-    const size_t bytes = align256(sizeof(float) * E) * 3 + align256(sizeof(int32_t) * E);
+    const size_t E = (size_t)(tot[1] > 0 ? tot[1] : CHUNK);
+    const size_t bytes = sets_bytes(E);
     C.sets = dev_alloc(bytes, s);
     if (!C.sets) {
         set_error("device allocation of %zu bytes for affordance sets failed", bytes);
         return CAPT_ENOMEM;
     }
     C.sets_bytes = bytes;
-    char *P = static_cast<char *>(C.sets);
-    float *px = reinterpret_cast<float *>(P);
-    float *py = reinterpret_cast<float *>(P + align256(sizeof(float) * E));
-    float *pz = reinterpret_cast<float *>(P + 2 * align256(sizeof(float) * E));
-    int32_t *pidx = reinterpret_cast<int32_t *>(P + 3 * align256(sizeof(float) * E));
+    float *px, *py, *pz;
+    int32_t *pidx;
+    float4 *cbox;
+    sets_layout(C.sets, E, &px, &py, &pz, &pidx, &cbox);
     C.dev.px = px;
     C.dev.py = py;
     C.dev.pz = pz;
     C.dev.pidx = pidx;
+    C.dev.cbox = cbox;
     hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
                        py, pz, pidx, const_cast<Leaf *>(C.dev.leaf));
     CAPT_LAUNCH_CHECK();
-    return CAPT_OK;
+    return chunk_boxes(px, py, pz, pidx, (int64_t)tot[1], cbox, s);
 }
 
 }  // namespace
@@ -875,6 +875,57 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     }
     f->pruned_total = pruned;
     return CAPT_OK;   // scratch is released stream-ordered; the forest is ready in stream order
+}
+
+namespace {
+__global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restrict__ py, const float *__restrict__ pz,
+                              const int32_t *__restrict__ pidx, int64_t nchunk, float4 *__restrict__ cbox) {
+    // CHUNK consecutive lanes share one chunk: one entry each, then a
+    // butterfly min / max over the group (padding entries do not count)
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = e / CHUNK;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (k < nchunk && pidx[e] >= 0) {
+        lo[0] = hi[0] = px[e];
+        lo[1] = hi[1] = py[e];
+        lo[2] = hi[2] = pz[e];
+    }
+#pragma unroll
+    for (int off = CHUNK / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
+        }
+    }
+    if (k < nchunk && (e & (CHUNK - 1)) == 0) {
+        cbox[2 * k] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+        cbox[2 * k + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    }
+}
+}  // namespace
+
+size_t sets_bytes(size_t E) {
+    return align256(sizeof(float) * E) * 3 + align256(sizeof(int32_t) * E) + align256(sizeof(float4) * 2 * (E / CHUNK + 1));
+}
+
+void sets_layout(void *base, size_t E, float **px, float **py, float **pz, int32_t **pidx, float4 **cbox) {
+    char *P = static_cast<char *>(base);
+    const size_t a = align256(sizeof(float) * E);
+    *px = reinterpret_cast<float *>(P);
+    *py = reinterpret_cast<float *>(P + a);
+    *pz = reinterpret_cast<float *>(P + 2 * a);
+    *pidx = reinterpret_cast<int32_t *>(P + 3 * a);
+    *cbox = reinterpret_cast<float4 *>(P + 3 * a + align256(sizeof(int32_t) * E));
+}
+
+capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, int64_t entries,
+                        float4 *cbox, hipStream_t s) {
+    const int64_t nchunk = entries / CHUNK;
+    if (nchunk <= 0) return CAPT_OK;
+    hipLaunchKernelGGL(k_chunk_boxes, dim3(nblk(nchunk * CHUNK)), dim3(TB), 0, s, px, py, pz, pidx, nchunk, cbox);
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
 }
 
 capt_status ensure_views(capt_forest_s *f, hipStream_t s) {

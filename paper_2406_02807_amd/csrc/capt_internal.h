@@ -34,6 +34,7 @@ struct CloudDev {
     const float *py;
     const float *pz;
     const int32_t *pidx;   // original index of each set entry (-1 = padding)
+    const float4 *cbox;    // per 16-entry chunk of the sets: [2k] = lo, [2k+1] = hi
     const float *pts;      // [n][3] the cloud as built
     int64_t n;
     int32_t D;
@@ -41,8 +42,10 @@ struct CloudDev {
 };
 
 // Stored-set alignment: every set starts at a multiple of this many entries
-// and is padded with +inf entries up to one.
+// and is padded with +inf entries up to one.  A chunk of SET_ALIGN entries is
+// also the unit of the second-level bounding boxes the query scan tests.
 constexpr uint32_t SET_ALIGN = 16;
+constexpr uint32_t CHUNK = SET_ALIGN;
 
 // ---------------------------------------------------------------------------
 // Host-side error state and helpers (api.hip)
@@ -122,7 +125,7 @@ struct CloudHost {
     int64_t set_padded = 0;    // stored entries with padding
     int64_t pruned = 0;
     void *fixed = nullptr;     // T, leaves, pts, rep, pruned flags
-    void *sets = nullptr;      // px, py, pz, pidx
+    void *sets = nullptr;      // px, py, pz, pidx, chunk boxes
     size_t fixed_bytes = 0;
     size_t sets_bytes = 0;
     CloudDev dev{};
@@ -152,12 +155,20 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
 void free_cloud(CloudHost &c);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)
+// Bounding box of every CHUNK-entry chunk of the stored sets (padding skipped).
+capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, int64_t entries,
+                        float4 *cbox, hipStream_t s);
+// Bytes of the sets block for `entries` padded entries and its sub-arrays.
+size_t sets_bytes(size_t entries);
+void sets_layout(void *base, size_t entries, float **px, float **py, float **pz, int32_t **pidx, float4 **cbox);
 
 // query.hip
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                      int32_t group, uint8_t *out, uint32_t flags, hipStream_t s);
 capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                         int32_t *leaf, uint8_t *rejected, int32_t *scanned, uint8_t *hit, hipStream_t s);
+capt_status chunk_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off, int32_t *boxes,
+                        int32_t *chunks, hipStream_t s);
 capt_status bruteforce(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                        const float *spheres, const int64_t *query_off, int32_t group,
                        uint8_t *out, hipStream_t s);

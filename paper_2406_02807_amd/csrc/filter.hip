@@ -154,8 +154,8 @@ __global__ void k_morton(const float *__restrict__ xyz, const uint32_t *__restri
     vals[j] = id;
 }
 
-constexpr int CT = 256;              // threads of the chain kernel
-constexpr int CI = 8;                // positions per thread
+constexpr int CT = 1024;             // threads of the chain kernel
+constexpr int CI = 2;                // positions per thread
 constexpr int CC = CT * CI;          // chunk length
 constexpr int CR = 11;               // log2(CC): jump tables J_0 .. J_10
 constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"

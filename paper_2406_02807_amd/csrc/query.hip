@@ -61,20 +61,47 @@ __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, in
     return i;
 }
 
+// Per-wave LDS scratch of the two-level set scan.
+constexpr uint32_t RING = 128;                 // chunks awaiting the entry scan (power of two)
+constexpr uint32_t CPS = WAVE / CHUNK;         // chunks covered by one 64-lane step
+struct WaveLds {
+    float4 sph[WAVE];        // the tile's spheres, w = fl(r*r)
+    uint32_t chunk[RING];    // surviving chunk (global chunk index)
+    uint8_t owner[RING];     // lane of the sphere it belongs to
+};
+static_assert(sizeof(WaveLds) % 16 == 0, "per-wave LDS blocks stay 16-byte aligned");
+
+// LDS written by some lanes of a wave and read by others: the LDS unit serves
+// one wave's requests in order, so only compiler reordering must be stopped.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Process one tile of up to 64 spheres against one cloud.  Lane l holds
 // sphere l of the tile (valid if l < nsph); lanes of configuration c are
-// c*g .. c*g+g-1 (g <= 64), or all lanes belong to one configuration (g > 64,
-// cfg_of_lane = 0).  Returns, per lane, whether that lane's configuration was
-// hit.
+// c*g .. c*g+g-1 (g <= 64), or all lanes belong to one configuration (g > 64).
+// Returns, per lane, whether that lane's configuration was hit.
 //
-// The surviving spheres' sets form one list of (sphere, entry) pairs in lane
-// order; excl is the exclusive prefix of the set lengths.  Step k covers pairs
-// 64k .. 64k+63: lane j takes pair 64k + j, whose sphere is the last lane o
-// with excl_o <= 64k + j (binary search).  The prefix is recomputed only when a
-// hit retires a configuration while others in the tile are still open.
+// A surviving sphere's set is stored as 16-entry chunks, each with a float32
+// bounding box.  Level 1 box-tests the (sphere, chunk) pairs of all surviving
+// spheres as one flattened list (an exclusive wave scan of the chunk counts
+// places each sphere's pairs; lane j of a step finds its sphere by binary
+// search over the scan) and appends the chunks whose box is within r to a
+// per-wave ring in LDS.  Level 2 tests the entries of 4 ring chunks per
+// 64-lane step (lane j: entry j % 16 of chunk j / 16), U steps in flight.  A
+// chunk box never lies farther than any of its points under the same rounding
+// order, so a skipped chunk holds no hit and the answer equals a scan of every
+// entry.  A hit retires its configuration: its spheres' ring chunks are
+// skipped and the level-1 prefix is rebuilt over the spheres still open.
 template <int U>
 __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L,
-                                          const float4 *__restrict__ sph, int nsph, int g) {
+                                          const float4 *__restrict__ sph, int nsph, int g, WaveLds &W) {
     const int lane = lane_id();
     const bool valid = lane < nsph;
     float4 q = valid ? sph[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -91,88 +118,119 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     }
     bool alive = valid && leaf.count > 0;
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
+    wave_lds_sync();   // the previous tile's readers of W are done
+    W.sph[lane] = make_float4(q.x, q.y, q.z, r2);
+    wave_lds_sync();
 
     const int gg = g > WAVE ? WAVE : g;
     const int cfg = g > WAVE ? 0 : lane / gg;
     const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
     const bool single = (g > WAVE) || (2 * g > nsph);   // one configuration in this tile
     bool done = false;
-    uint32_t rem = alive ? leaf.count : 0u;   // pairs of this lane not yet consumed
-    uint32_t pos = leaf.start;                 // first unconsumed entry
+    uint64_t dead = 0;                                    // lanes whose configuration is hit
+    uint32_t rem = alive ? (leaf.count + CHUNK - 1) / CHUNK : 0u;   // chunks not yet box-tested
+    uint32_t cpos = leaf.start / CHUNK;                   // the first of them
+    uint32_t head = 0, tail = 0;                          // ring [head, tail), wave-uniform
+    const float4 *__restrict__ CB = C.cbox;
     const float *__restrict__ PX = C.px;
     const float *__restrict__ PY = C.py;
     const float *__restrict__ PZ = C.pz;
+
+    // Entry scan of the next `nproc` <= U*CPS ring chunks; true if a hit retired
+    // a configuration (then `done` and `dead` are up to date).
+    auto entry_round = [&](uint32_t nproc) -> bool {
+        float4 s[U];
+        float px[U], py[U], pz[U];
+        int own[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t k = (uint32_t)u * CPS + (uint32_t)lane / CHUNK;
+            in[u] = k < nproc;
+            const uint32_t slot = (head + k) & (RING - 1);
+            uint32_t ch = 0;
+            int o = 0;
+            if (in[u]) {
+                ch = W.chunk[slot];
+                o = W.owner[slot];
+            }
+            in[u] = in[u] && !((dead >> o) & 1ull);
+            own[u] = o;
+            s[u] = W.sph[o];
+            const uint32_t e = ch * CHUNK + ((uint32_t)lane & (CHUNK - 1));
+            px[u] = in[u] ? PX[e] : 0.f;
+            py[u] = in[u] ? PY[e] : 0.f;
+            pz[u] = in[u] ? PZ[e] : 0.f;
+        }
+        uint64_t om = 0;   // owners hit by this lane's entries
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (in[u] && sqdist(s[u].x, s[u].y, s[u].z, px[u], py[u], pz[u]) <= s[u].w) om |= 1ull << own[u];
+        head += nproc;
+        if (__ballot(om != 0) == 0) return false;
+        if (single) {
+            done = valid;
+            return true;
+        }
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) om |= __shfl_xor(om, d, WAVE);
+        if (valid) done = done || (((om >> (cfg * gg)) & gmask) != 0);
+        dead = __ballot(done);
+        return true;
+    };
+
     while (true) {
         if (done) rem = 0;
         const uint32_t incl = wave_incl_scan(rem, lane);
         const uint32_t excl = incl - rem;
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         if (total == 0) break;
-        const uint32_t base_l = pos - excl;    // entry of pair slot s of this lane = base_l + s
+        const uint32_t base_l = cpos - excl;   // chunk of pair slot t of this lane = base_l + t
         bool rescan = false;
-        for (uint32_t k0 = 0; k0 < total && !rescan; k0 += U * WAVE) {
-            // U steps of 64 pairs in flight: owners, then loads, then tests
-            float ox[U], oy[U], oz[U], orr[U], px[U], py[U], pz[U];
-            bool in[U];
+        uint32_t end = 0;
+        for (uint32_t k0 = 0; k0 < total && !rescan; k0 += WAVE) {
+            const uint32_t slot = k0 + (uint32_t)lane;
+            int o = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t slot = k0 + (uint32_t)(u * WAVE + lane);
-                in[u] = slot < total;
-                int o = 0;
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1) {
-                    const uint32_t e = __shfl(excl, o + step, WAVE);
-                    if (e <= slot) o += step;
-                }
-                const uint32_t base = __shfl(base_l, o, WAVE);
-                const float cx = __shfl(q.x, o, WAVE);
-                const float cy = __shfl(q.y, o, WAVE);
-                const float cz = __shfl(q.z, o, WAVE);
-                const float cr = __shfl(r2, o, WAVE);
-                ox[u] = cx;
-                oy[u] = cy;
-                oz[u] = cz;
-                orr[u] = cr;
-                const uint32_t e = in[u] ? base + slot : 0u;
-                px[u] = in[u] ? PX[e] : 0.f;
-                py[u] = in[u] ? PY[e] : 0.f;
-                pz[u] = in[u] ? PZ[e] : 0.f;
+            for (int step = 32; step >= 1; step >>= 1) {
+                const uint32_t e = __shfl(excl, o + step, WAVE);
+                if (e <= slot) o += step;
             }
-            uint64_t hm[U];
-            uint64_t any = 0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool hit = in[u] && sqdist(ox[u], oy[u], oz[u], px[u], py[u], pz[u]) <= orr[u];
-                hm[u] = __ballot(hit);
-                any |= hm[u];
+            const uint32_t ch = __shfl(base_l, o, WAVE) + slot;
+            const bool in = slot < total && !((dead >> o) & 1ull);
+            const float4 so = W.sph[o];
+            bool surv = false;
+            if (in) {
+                const float4 a = CB[2 * (size_t)ch];
+                const float4 b = CB[2 * (size_t)ch + 1];
+                const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+                surv = box_sqdist(so.x, so.y, so.z, lo, hi) <= so.w;
             }
-            if (any) {
-                rescan = true;
-                if (single) {
-                    done = valid;
-                } else {
-                    bool mine = false;
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const uint32_t c0 = k0 + (uint32_t)(u * WAVE);
-                        const uint32_t lo = max(excl, c0), hi = min(excl + rem, c0 + (uint32_t)WAVE);
-                        if (lo < hi) {
-                            const uint32_t w = hi - lo;
-                            const uint64_t m = w >= WAVE ? ~0ull : ((1ull << w) - 1);
-                            mine = mine || (((hm[u] >> (lo - c0)) & m) != 0);
-                        }
-                    }
-                    const uint64_t sh = __ballot(mine);
-                    if (valid) done = done || (((sh >> (cfg * gg)) & gmask) != 0);
-                    // consume what these steps covered, then rebuild the prefix
-                    const uint32_t end = k0 + (uint32_t)(U * WAVE);
-                    const uint32_t used = end <= excl ? 0u : min(rem, end - excl);
-                    rem -= used;
-                    pos += used;
+            const uint64_t m = __ballot(surv);
+            if (surv) {
+                const uint32_t at = (tail + lanes_below(m)) & (RING - 1);
+                W.chunk[at] = ch;
+                W.owner[at] = (uint8_t)o;
+            }
+            tail += (uint32_t)__popcll(m);
+            end = k0 + WAVE;
+            wave_lds_sync();
+            // full rounds only; fewer than U*CPS chunks stay for the next batch,
+            // so the ring never holds more than U*CPS + 63 < RING chunks
+            while (tail - head >= (uint32_t)U * CPS) {
+                if (entry_round((uint32_t)U * CPS)) {
+                    if (single) return done;
+                    rescan = true;
                 }
             }
         }
-        if (!rescan || single) break;   // all pairs consumed, or the configuration is hit
+        if (!rescan) break;   // every chunk has been box-tested
+        const uint32_t used = end <= excl ? 0u : min(rem, end - excl);
+        rem -= used;
+        cpos += used;
+    }
+    while (head != tail) {
+        if (entry_round(min(tail - head, (uint32_t)U * CPS)) && single) break;
     }
     return done;
 }
@@ -186,7 +244,9 @@ constexpr int CTR_STRIDE = 16;   // one 64-byte line per counter
 template <int U>
 __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
-    extern __shared__ float Tl[];
+    extern __shared__ float4 lds4[];
+    WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
+    float *Tl = reinterpret_cast<float *>(reinterpret_cast<WaveLds *>(lds4) + blockDim.x / WAVE);
     const int nT = (1 << L) - 1;
     for (int i = threadIdx.x; i < nT; i += blockDim.x) Tl[i] = C.T[i];
     __syncthreads();
@@ -208,13 +268,13 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
             if (g <= WAVE) {
                 const int64_t c0 = t * cpt;
                 const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-                const bool hit = wave_tile<U>(C, Tl, L, sph + c0 * g, nc * g, g);
+                const bool hit = wave_tile<U>(C, Tl, L, sph + c0 * g, nc * g, g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             } else {
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile<U>(C, Tl, L, sph + t * g + s0, ns, g);
+                    hit = wave_tile<U>(C, Tl, L, sph + t * g + s0, ns, g, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[t] = (uint8_t)hit;
@@ -243,6 +303,8 @@ template <int U>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
                                   const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
+    extern __shared__ float4 lds4[];
+    WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
     const int lane = lane_id();
     while (true) {
         unsigned int t = 0;
@@ -256,7 +318,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
-                const bool hit = wave_tile<U>(C, nullptr, 0, sph + c0 * g, nc * g, g);
+                const bool hit = wave_tile<U>(C, nullptr, 0, sph + c0 * g, nc * g, g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -265,7 +327,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile<U>(C, nullptr, 0, sph + cc * g + s0, ns, g);
+                    hit = wave_tile<U>(C, nullptr, 0, sph + cc * g + s0, ns, g, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[cc] = (uint8_t)hit;
@@ -361,6 +423,36 @@ __global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_
     if (hit_out) hit_out[s] = (uint8_t)hit;
 }
 
+// The two-level scan's work per sphere, in stored order, up to and including
+// the chunk that holds the first hit: chunk boxes tested and chunks whose
+// entries were scanned (thread per sphere, not tuned).
+__global__ void k_chunk_stats(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int32_t *__restrict__ boxes,
+                              int32_t *__restrict__ chunks) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsph) return;
+    const float4 q = sph[s];
+    const float r2 = __fmul_rn(q.w, q.w);
+    const int64_t N = (int64_t)1 << C.D;
+    const uint32_t lf = descend(q, nullptr, 0, C.T, C.D) - (uint32_t)(N - 1);
+    const Leaf L = C.leaf[lf];
+    int32_t nb = 0, nc = 0;
+    if (L.count > 0 && box_sqdist(q.x, q.y, q.z, L.lo, L.hi) <= r2) {
+        bool hit = false;
+        const uint32_t c0 = L.start / CHUNK, c1 = c0 + (L.count + CHUNK - 1) / CHUNK;
+        for (uint32_t c = c0; c < c1 && !hit; ++c) {
+            ++nb;
+            const float4 a = C.cbox[2 * (size_t)c], b = C.cbox[2 * (size_t)c + 1];
+            const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+            if (box_sqdist(q.x, q.y, q.z, lo, hi) > r2) continue;
+            ++nc;
+            for (uint32_t e = c * CHUNK; e < (c + 1) * CHUNK && !hit; ++e)
+                hit = sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2;
+        }
+    }
+    if (boxes) boxes[s] = nb;
+    if (chunks) chunks[s] = nc;
+}
+
 __global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r_min, float r_max,
                               unsigned int *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,19 +499,28 @@ void free_plan(BatchPlan *p) {
 
 namespace {
 
-int lds_levels_for(int D) {
+// Tree levels kept in LDS beside `extra` bytes of per-wave scratch.
+int lds_levels_for(int D, size_t extra) {
     int L = std::min(D, std::max(0, std::min(14, (int)tuning().lds_levels)));
     const size_t cap = (size_t)device_info().lds_per_block;
-    while (L > 0 && sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
+    while (L > 0 && extra + sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
     return L;
+}
+
+// Kernels whose dynamic LDS may exceed 64 KB declare the device maximum once.
+template <class K> capt_status allow_lds(K kernel) {
+    CAPT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 device_info().lds_per_block));
+    return CAPT_OK;
 }
 
 capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
                          unsigned int *ctr, hipStream_t s) {
     if (nsph <= 0) return CAPT_OK;
     const capt_tuning &t = tuning();
-    const int L = lds_levels_for(C.D);
     const int threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
+    const size_t wl = sizeof(WaveLds) * (size_t)(threads / WAVE);
+    const int L = lds_levels_for(C.D, wl);
     const int64_t ncfg = nsph / g;
     const int cpt = g <= WAVE ? WAVE / g : 1;
     const int64_t ntiles = (ncfg + cpt - 1) / cpt;
@@ -429,7 +530,13 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     // queue chunk: about 8 pops per wave over the whole launch, 1 .. 64 tiles
     const int64_t per_wave = ntiles / std::max<int64_t>(1, blocks * wpb);
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_wave / 8));
-    const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
+    const size_t lds = wl + sizeof(float) * (size_t)((1 << L) - 1);
+    static const bool lds_ok = allow_lds(k_collide_cloud<4>) == CAPT_OK && allow_lds(k_collide_cloud<2>) == CAPT_OK &&
+                               allow_lds(k_collide_cloud<1>) == CAPT_OK;
+    if (!lds_ok) {
+        set_error("raising the dynamic LDS limit of the collision kernel failed");
+        return CAPT_EHIP;
+    }
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
     CAPT_LAUNCH_CHECK();
     const float4 *sp = reinterpret_cast<const float4 *>(spheres);
@@ -500,21 +607,22 @@ capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
     int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
     const int64_t wpb = threads / WAVE;
     blocks = std::max<int64_t>(1, std::min(blocks, (p->ntiles + wpb - 1) / wpb));
+    const size_t lds = sizeof(WaveLds) * (size_t)wpb;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p->d_ctr);
     CAPT_LAUNCH_CHECK();
     if (p->ntiles > 0) {
         const float4 *sp = reinterpret_cast<const float4 *>(p->spheres);
         switch (t.scan_unroll) {
             case 4:
-                hipLaunchKernelGGL(k_collide_batched<4>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                hipLaunchKernelGGL(k_collide_batched<4>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
             case 2:
-                hipLaunchKernelGGL(k_collide_batched<2>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                hipLaunchKernelGGL(k_collide_batched<2>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
             default:
-                hipLaunchKernelGGL(k_collide_batched<1>, dim3((unsigned)blocks), dim3(threads), 0, s, f->d_clouds,
+                hipLaunchKernelGGL(k_collide_batched<1>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
         }
@@ -620,6 +728,21 @@ capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *q
                            reinterpret_cast<const float4 *>(spheres + 4 * o), m, leaf ? leaf + o : nullptr,
                            rejected ? rejected + o : nullptr, scanned ? scanned + o : nullptr,
                            hit ? hit + o : nullptr);
+        CAPT_LAUNCH_CHECK();
+    }
+    return CAPT_OK;
+}
+
+capt_status chunk_stats(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t *boxes, int32_t *chunks,
+                        hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        const int64_t o = qoff[c];
+        hipLaunchKernelGGL(k_chunk_stats, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, f->clouds[c].dev,
+                           reinterpret_cast<const float4 *>(spheres + 4 * o), m, boxes ? boxes + o : nullptr,
+                           chunks ? chunks + o : nullptr);
         CAPT_LAUNCH_CHECK();
     }
     return CAPT_OK;

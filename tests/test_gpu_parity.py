@@ -183,6 +183,49 @@ def test_query_stats_match_oracle_replay(capt, orc):
     assert np.array_equal(hit, hit_o) and np.array_equal(hit, orc.brute_f32(pts, sph))
 
 
+def _f32_sqdist(q, p):
+    """((dx*dx + dy*dy) + dz*dz) in float32, every operation rounded."""
+    d = (q[None, :3] - p).astype(np.float32)
+    s = d * d
+    return (s[:, 0] + s[:, 1]) + s[:, 2]
+
+
+def _f32_box_sqdist(q, lo, hi):
+    g = np.maximum(np.maximum(lo - q[:3], q[:3] - hi), np.float32(0)).astype(np.float32)
+    s = g * g
+    return (s[0] + s[1]) + s[2]
+
+
+def test_chunk_stats_match_stored_order_replay(capt):
+    """The two-level scan's accounting, replayed on the host from the exported
+    sets in stored order: 16-entry chunks, float32 chunk boxes, early exit at
+    the chunk holding the first hit."""
+    pts = synth.tabletop_cloud(8000, 41)
+    _say("case: chunk stats")
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    b = capt.parse_blob(capt.capt_export(f))
+    sph = synth.uniform_spheres(4000, synth.WORKSPACE, 0.015, 0.08, 43)
+    leaf, rej, _, _ = [x.cpu().numpy() for x in capt.capt_query_stats(f, dev(sph))]
+    nb, nc = [x.cpu().numpy() for x in capt.capt_query_chunk_stats(f, dev(sph))]
+    P = b.points
+    for i, q in enumerate(sph):
+        r2 = np.float32(q[3]) * np.float32(q[3])
+        want_b = want_c = 0
+        if not rej[i]:
+            ids = b.idx[b.off[leaf[i]]:b.off[leaf[i] + 1]]
+            for c0 in range(0, len(ids), 16):
+                cp = P[ids[c0:c0 + 16]]
+                want_b += 1
+                if _f32_box_sqdist(q, cp.min(0), cp.max(0)) > r2:
+                    assert not (_f32_sqdist(q, cp) <= r2).any(), "a skipped chunk holds a hit"
+                    continue
+                want_c += 1
+                if (_f32_sqdist(q, cp) <= r2).any():
+                    break
+        assert (nb[i], nc[i]) == (want_b, want_c), i
+    assert nc.sum() < nb.sum()
+
+
 # ---------------------------------------------------------------------------
 # GPU brute force (the benchmark's baseline) is exact too
 # ---------------------------------------------------------------------------
