@@ -111,6 +111,11 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
 size_t radix_tmp_words(int64_t n);
 capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where);
+// Segmented form: nseg (<= 8) lists of len keys each, sorted independently in
+// the same launches; tmp holds radix_tmp_words_seg(nseg, len) words.
+size_t radix_tmp_words_seg(int nseg, int64_t len);
+capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int nseg, int64_t len,
+                               int bits, uint32_t *tmp, hipStream_t s, int *where);
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where);
 

@@ -1,20 +1,29 @@
 // Morton-curve point-cloud filter (Alg. 2, Sec. IV-C) on the GPU.
 //
-// Per axis permutation (six passes, each on the previous pass's survivors):
-//  1. 63-bit Z-order keys on a 2^21-per-axis grid over the input's cubic
-//     bounding box, then a stable 64-bit radix sort (ties keep the current
-//     order, as a stable sort of the list would);
-//  2. the sequential rule "keep j iff it is farther than r_filter from the
-//     last kept point" is made parallel: next[j] = first k > j farther than
-//     r_filter from j, so the kept points are exactly the chain
-//     0 -> next[0] -> next[next[0]] -> ...  One kernel resolves the chain in
-//     chunks of 2048 positions: a chunk builds the jump tables
-//     J_t = next^(2^t) of its positions in LDS, waits for the previous chunk
-//     to publish where the chain enters it, follows the tables to the chain's
-//     exit and publishes that for the next chunk; it then marks the chain's
-//     nodes inside the chunk top-down over the tables and writes them, in
-//     order, at an offset found by decoupled look-back over earlier chunks'
-//     survivor counts.
+// Six passes, one per axis permutation, each on the previous pass's
+// survivors, in the order of a stable sort of the current list along the
+// pass's Z-order curve (63-bit keys on a 2^21-per-axis grid over the input's
+// cubic bounding box).  Two facts let every sort happen up front:
+//  * every permutation's key is a bijection of the grid cell, so two points
+//    tie under one permutation exactly when they tie under all of them; the
+//    stable order of pass p is therefore "key_p, then original index" whatever
+//    the earlier passes did;
+//  * the survivors of a pass, taken in that order, are the full sorted list
+//    with the dead points skipped.
+// So one segmented radix sort orders all n points under all six keys, and
+// pass p walks segment p with a liveness flag per point.
+//
+// A pass makes the sequential rule "keep j iff it is farther than r_filter
+// from the last kept point" parallel: next[j] = the first live k > j farther
+// than r_filter from j (for a dead j: the first live k > j), so the kept
+// points are the live nodes of the chain 0 -> next[0] -> ...  One kernel
+// resolves the chain in chunks of CC positions: a chunk builds the jump
+// tables J_t = next^(2^t) of its positions in LDS, waits for the previous
+// chunk to publish where the chain enters it, follows the tables to the
+// chain's exit and publishes that for the next chunk; it then marks the
+// chain's nodes inside the chunk top-down over the tables and writes the
+// next pass's liveness flags.  The last pass also writes its survivors in
+// order, at offsets found by decoupled look-back over earlier chunks' counts.
 // Only the final count crosses to the host.
 #include <cmath>
 
@@ -33,7 +42,7 @@ struct FState {
     float lo[3];
     float hi[3];
     double scale;
-    int64_t mm[2];      // point count before / after the current pass (alternating)
+    int64_t mm[2];      // mm[0]: survivors of the last pass (n until it ends)
     unsigned int bad;   // non-finite coordinates
 };
 
@@ -109,11 +118,6 @@ __global__ void k_clear_u32(uint32_t *__restrict__ p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
-__global__ void k_iota(uint32_t *__restrict__ v, int64_t n) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) v[j] = (uint32_t)j;
-}
-
 // Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
     uint64_t x = v & 0x1FFFFFull;
@@ -135,23 +139,24 @@ __device__ __forceinline__ uint32_t cell_of(float v, float lo, double scale) {
 // Axis order of each permutation: xyz, xzy, yxz, yzx, zxy, zyx.
 __constant__ int c_perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
-__global__ void k_morton(const float *__restrict__ xyz, const uint32_t *__restrict__ cur, int64_t n,
-                         const FState *__restrict__ st, int p, uint64_t *__restrict__ keys,
-                         uint32_t *__restrict__ vals) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// All six keys of every point: keys[p * n + id], vals[p * n + id] = id.
+__global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState *__restrict__ st,
+                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const int64_t m = st->mm[p & 1];
-    if (j >= m) {
-        keys[j] = ~0ull;
-        vals[j] = 0xFFFFFFFFu;
-        return;
+    uint64_t sp[3];
+    for (int a = 0; a < 3; ++a) sp[a] = spread3(cell_of(xyz[3 * j + a], st->lo[a], st->scale));
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        // axis X[i] of the permutation fills key bits 3b + (2 - i)
+        keys[p * n + j] = (sp[c_perm[p][0]] << 2) | (sp[c_perm[p][1]] << 1) | sp[c_perm[p][2]];
+        vals[p * n + j] = (uint32_t)j;
     }
-    const uint32_t id = cur[j];
-    uint32_t q[3];
-    for (int a = 0; a < 3; ++a) q[a] = cell_of(xyz[3 * (int64_t)id + a], st->lo[a], st->scale);
-    // axis X[j] fills key bits 3b + (2 - j)
-    keys[j] = (spread3(q[c_perm[p][0]]) << 2) | (spread3(q[c_perm[p][1]]) << 1) | spread3(q[c_perm[p][2]]);
-    vals[j] = id;
+}
+
+__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 constexpr int CT = 1024;             // threads of the chain kernel
@@ -192,14 +197,16 @@ __device__ __forceinline__ uint32_t block_excl_scan_c(uint32_t v, uint32_t *lw, 
     return off + inc - v;
 }
 
-// One filter pass's keep decisions and compaction (see the file comment).
-// ord: the current points in curve order (original ids); the survivors go to
-// out in the same order and their count to st->mm[(p + 1) & 1].
+// One filter pass (see the file comment).  ord: all n points in the pass's
+// curve order (original ids); live_in / live_out: liveness per original id
+// before / after the pass.  With `last`, the survivors also go to out in
+// order and their count to st->mm[0].
 __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ xyz, const uint32_t *__restrict__ ord,
-                                                    FState *__restrict__ st, int p, float rf2,
-                                                    uint32_t *__restrict__ exit_pub, uint32_t *__restrict__ kept_st,
-                                                    uint32_t *__restrict__ chunk_ctr, uint32_t *__restrict__ out,
-                                                    uint32_t *__restrict__ err) {
+                                                    int64_t n, const uint8_t *__restrict__ live_in,
+                                                    uint8_t *__restrict__ live_out, FState *__restrict__ st,
+                                                    float rf2, int last, uint32_t *__restrict__ exit_pub,
+                                                    uint32_t *__restrict__ kept_st, uint32_t *__restrict__ chunk_ctr,
+                                                    uint32_t *__restrict__ out, uint32_t *__restrict__ err) {
     __shared__ uint16_t J[CR][CC];
     __shared__ uint32_t Nx[CC];
     __shared__ int8_t mark[CC];
@@ -208,22 +215,26 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     if (threadIdx.x == 0) s_chunk = atomicAdd(chunk_ctr, 1u);
     __syncthreads();
     const int64_t c = s_chunk;
-    const int64_t m = st->mm[p & 1];
     const int64_t cs = c * CC;
-    if (cs >= m) return;                      // no position of the chain here (uniform)
-    const int64_t ce = min(cs + (int64_t)CC, m);
+    if (cs >= n) return;                      // uniform
+    const int64_t ce = min(cs + (int64_t)CC, n);
     const int len = (int)(ce - cs);
     // 1. next pointers and the first jump table
     for (int i = threadIdx.x; i < CC; i += CT) {
         if (i < len) {
             const int64_t j = cs + i;
             const uint32_t a = ord[j];
-            const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
             int64_t k = j + 1;
-            for (; k < m; ++k) {
-                const uint32_t b = ord[k];
-                if (sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2)
-                    break;
+            if (live_in[a]) {
+                const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
+                for (; k < n; ++k) {
+                    const uint32_t b = ord[k];
+                    if (live_in[b] &&
+                        sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2)
+                        break;
+                }
+            } else {
+                while (k < n && !live_in[ord[k]]) ++k;
             }
             Nx[i] = (uint32_t)k;
             J[0][i] = k < ce ? (uint16_t)(k - cs) : OUTL;
@@ -279,15 +290,21 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
             __syncthreads();
         }
     }
-    // 5. survivors of the chunk, in order
+    // 5. the pass's survivors: live chain nodes
     uint32_t f[CI];
     uint32_t cnt = 0;
 #pragma unroll
     for (int u = 0; u < CI; ++u) {
         const int i = threadIdx.x * CI + u;
-        f[u] = (i < len && mark[i] >= 0) ? 1u : 0u;
+        f[u] = 0u;
+        if (i < len) {
+            const uint32_t a = ord[cs + i];
+            f[u] = (mark[i] >= 0 && live_in[a]) ? 1u : 0u;
+            live_out[a] = (uint8_t)f[u];
+        }
         cnt += f[u];
     }
+    if (!last) return;
     uint32_t kept;
     uint32_t off = block_excl_scan_c(cnt, lw, &kept);
     // 6. offset of the chunk's survivors: look back over earlier chunks
@@ -316,7 +333,7 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
             st_agent(&kept_st[c], 0x80000000u | (excl + kept));
         }
         s_prefix = excl;
-        if (ce == m) st->mm[(p + 1) & 1] = (int64_t)(excl + kept);
+        if (ce == n) st->mm[0] = (int64_t)(excl + kept);
     }
     __syncthreads();
     off += s_prefix;
@@ -347,8 +364,10 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
         *n_out = 0;
         return CAPT_OK;
     }
-    const size_t wn = (size_t)n + 1;
+    constexpr int NP = 6;
+    const size_t wn = (size_t)n;
     const int64_t nchunk = (n + CC - 1) / CC;
+    const int64_t npub = NP * (2 * nchunk + 64);   // per pass: exits, survivor counts, chunk counter
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -357,12 +376,13 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     };
     const size_t oSt = take(sizeof(FState));
     const size_t oCur = take(sizeof(uint32_t) * wn);
-    const size_t oK0 = take(sizeof(uint64_t) * wn);
-    const size_t oK1 = take(sizeof(uint64_t) * wn);
-    const size_t oV0 = take(sizeof(uint32_t) * wn);
-    const size_t oV1 = take(sizeof(uint32_t) * wn);
-    const size_t oPub = take(sizeof(uint32_t) * (size_t)(2 * nchunk + 64));   // exits, survivor counts, counter
-    const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words((int64_t)wn));
+    const size_t oK0 = take(sizeof(uint64_t) * wn * NP);
+    const size_t oK1 = take(sizeof(uint64_t) * wn * NP);
+    const size_t oV0 = take(sizeof(uint32_t) * wn * NP);
+    const size_t oV1 = take(sizeof(uint32_t) * wn * NP);
+    const size_t oLive = take(wn * (NP + 1));
+    const size_t oPub = take(sizeof(uint32_t) * (size_t)npub);
+    const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words_seg(NP, n));
     Scratch sc;
     if (!sc.alloc(off, s)) {
         set_error("device allocation of %zu filter scratch bytes failed", off);
@@ -375,32 +395,34 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     uint64_t *k1 = reinterpret_cast<uint64_t *>(B + oK1);
     uint32_t *v0 = reinterpret_cast<uint32_t *>(B + oV0);
     uint32_t *v1 = reinterpret_cast<uint32_t *>(B + oV1);
+    uint8_t *live = reinterpret_cast<uint8_t *>(B + oLive);
     uint32_t *pub = reinterpret_cast<uint32_t *>(B + oPub);
     uint32_t *rad = reinterpret_cast<uint32_t *>(B + oRad);
-    uint32_t *exit_pub = pub, *kept_st = pub + nchunk, *chunk_ctr = pub + 2 * nchunk;
-    const int64_t npub = 2 * nchunk + 64;
 
     const float rf2 = r_filter * r_filter;
-    CAPT_HIP(hipMemsetAsync(rad, 0, sizeof(uint32_t) * 64, s));
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, s, rad, (int64_t)64);   // sort error word
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)((npub + 255) / 256)), dim3(256), 0, s, pub, npub);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n)), dim3(TB), 0, s, live, n, (uint8_t)1);
+    CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_fstate_init, dim3(1), dim3(64), 0, s, st, n);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(nblk(n), 16u)), dim3(TB), 0, s, xyz, n, st);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, st);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(TB), 0, s, cur, n);
+    hipLaunchKernelGGL(k_morton6, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, st, k0, v0);
     CAPT_LAUNCH_CHECK();
-    for (int p = 0; p < 6; ++p) {
-        hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, p, k0, v0);
-        CAPT_LAUNCH_CHECK();
-        int where = 0;
-        capt_status e = radix_sort_u64(k0, v0, k1, v1, n, 64, rad, s, &where);
-        if (e) return e;
-        const uint32_t *ord = where ? v1 : v0;
-        hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)((npub + 255) / 256)), dim3(256), 0, s, pub, npub);
-        CAPT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), 0, s, xyz, ord, st, p, rf2, exit_pub,
-                           kept_st, chunk_ctr, cur, rad);
+    int where = 0;
+    capt_status e = radix_sort_u64_seg(k0, v0, k1, v1, NP, n, 63, rad, s, &where);
+    if (e) return e;
+    const uint32_t *ord = where ? v1 : v0;
+    for (int p = 0; p < NP; ++p) {
+        uint32_t *pp = pub + (size_t)p * (2 * nchunk + 64);
+        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), 0, s, xyz, ord + (size_t)p * wn, n,
+                           live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2, (int)(p == NP - 1), pp,
+                           pp + nchunk, pp + 2 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, out_xyz, out_index);

@@ -153,25 +153,34 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Segments: the keys form `nseg` independent lists of `len` items each
+// (segment g at g * len); every segment is sorted on its own.
 template <class K>
-__global__ void k_os_hist(const K *__restrict__ keys, int64_t n, int npass, uint32_t *__restrict__ ghist) {
-    __shared__ uint32_t h[8 * 256];
-    for (int i = threadIdx.x; i < npass * 256; i += TB) h[i] = 0;
+__global__ void k_os_hist(const K *__restrict__ keys, int64_t len, int nseg, int npass, uint32_t *__restrict__ ghist) {
+    extern __shared__ uint32_t h[];   // [nseg][npass][256]
+    const int nh = nseg * npass * 256;
+    for (int i = threadIdx.x; i < nh; i += TB) h[i] = 0;
     __syncthreads();
+    const int64_t n = len * nseg;
     const int64_t stride = (int64_t)gridDim.x * TB;
     for (int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x; j < n; j += stride) {
         const K k = keys[j];
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
+        uint32_t *hs = h + (size_t)(j / len) * npass * 256;
+        for (int p = 0; p < npass; ++p) atomicAdd(&hs[p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < npass * 256; i += TB)
-        if (h[i]) atomicAdd(&ghist[i], h[i]);
+    for (int i = threadIdx.x; i < nh; i += TB) {
+        // ghist layout: [pass][seg][256]
+        const int g = i / (npass * 256), r = i % (npass * 256);
+        const int p = r / 256, d = r % 256;
+        if (h[i]) atomicAdd(&ghist[((size_t)p * nseg + g) * 256 + d], h[i]);
+    }
 }
 
 template <class K>
 __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                   K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
-                                                   int shift, const uint32_t *__restrict__ ghist,
+                                                   K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t len,
+                                                   int64_t tps, int shift, const uint32_t *__restrict__ ghist,
                                                    uint32_t *__restrict__ status, uint32_t *__restrict__ tile_ctr,
                                                    uint32_t *__restrict__ err) {
     __shared__ uint32_t s_tile;
@@ -185,35 +194,39 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t t = s_tile;
-    const int64_t base = (int64_t)t * TILE;
+    const uint32_t t = s_tile;               // global tile id
+    const int64_t g = (int64_t)t / tps;      // its segment
+    const int64_t ts = (int64_t)t - g * tps; // tile within the segment
+    const int64_t seg0 = g * len;
+    const int64_t base = ts * TILE;          // within the segment
     // the tile's items stay in registers for the whole pass (one load round)
     K key[IPT];
     uint32_t val[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        key[r] = j < n ? kin[j] : K(0);
-        val[r] = j < n ? vin[j] : 0u;
+        key[r] = j < len ? kin[seg0 + j] : K(0);
+        val[r] = j < len ? vin[seg0 + j] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        if (j < n) atomicAdd(&cnt[(uint32_t)(key[r] >> shift) & 255u], 1u);
+        if (j < len) atomicAdd(&cnt[(uint32_t)(key[r] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    // publish this tile's digit counts, then look back for the earlier tiles'
+    // publish this tile's digit counts, then look back over the segment's
+    // earlier tiles
     const int d = threadIdx.x;
     const uint32_t c = cnt[d];
     uint32_t excl = 0;
-    if (t == 0) {
-        store_agent(&status[d], ST_PRE | c);
+    if (ts == 0) {
+        store_agent(&status[(size_t)t * 256 + d], ST_PRE | c);
     } else {
         store_agent(&status[(size_t)t * 256 + d], ST_AGG | c);
-        int64_t p = (int64_t)t - 1;
+        int64_t q = (int64_t)t - 1;
         uint32_t spins = 0;
-        while (p >= 0) {
-            const uint32_t v = load_agent(&status[(size_t)p * 256 + d]);
+        while (true) {
+            const uint32_t v = load_agent(&status[(size_t)q * 256 + d]);
             const uint32_t flag = v & ~ST_VAL;
             if (flag == 0) {
                 if (++spins > LOOKBACK_SPINS) {
@@ -224,13 +237,13 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
             }
             excl += v & ST_VAL;
             if (flag == ST_PRE) break;
-            --p;
+            --q;   // a segment's first tile publishes a prefix, so q stays in the segment
         }
         store_agent(&status[(size_t)t * 256 + d], ST_PRE | (excl + c));
     }
-    // global start of every digit: counts of smaller digits over all tiles
+    // start of every digit in the segment: counts of smaller digits
     uint32_t tot;
-    const uint32_t gex = block_excl_scan(ghist[d], lw, &tot);
+    const uint32_t gex = block_excl_scan(ghist[(size_t)g * 256 + d], lw, &tot);
     run[d] = gex + excl;
     __syncthreads();
 #pragma unroll
@@ -239,7 +252,7 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
         for (int q = 0; q < NW; ++q) wc[q][threadIdx.x] = 0;
         __syncthreads();
         const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        const bool valid = j < n;
+        const bool valid = j < len;
         const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t same = __ballot(valid);
 #pragma unroll
@@ -254,8 +267,8 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
             uint32_t pos = run[dg];
             for (int q = 0; q < w; ++q) pos += wc[q][dg];
             pos += rank;
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            kout[seg0 + pos] = key[r];
+            vout[seg0 + pos] = val[r];
         }
         __syncthreads();
         uint32_t add = 0;
@@ -266,36 +279,41 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     }
 }
 
-// tmp layout: [err (64 words)] [ghist npass*256] [tile counters 64] [status npass*ntiles*256].
-// The error word (tmp[0], set if a look-back wait ever exceeds its bound) is
-// not cleared here: callers clear it once and read it at their next sync.
+constexpr int MAX_SEG = 8;
+
+// tmp layout: [err (64 words)] [ghist npass*nseg*256] [tile counters 64]
+// [status npass*nseg*tps*256].  The error word (tmp[0], set if a look-back
+// wait ever exceeds its bound) is not cleared here: callers clear it once and
+// read it at their next sync.
 template <class K>
-capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int bits, uint32_t *tmp, hipStream_t s,
-                       int *where) {
+capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64_t len, int bits, uint32_t *tmp,
+                       hipStream_t s, int *where) {
     *where = 0;
-    if (n <= 1 || bits <= 0) return CAPT_OK;
-    if (n >= ((int64_t)1 << 30)) {
-        set_error("radix sort of %lld keys exceeds 2^30", (long long)n);
+    if (len <= 1 || bits <= 0 || nseg <= 0) return CAPT_OK;
+    if (nseg > MAX_SEG || len * nseg >= ((int64_t)1 << 30)) {
+        set_error("radix sort of %d x %lld keys exceeds the supported size", nseg, (long long)len);
         return CAPT_EUNSUPPORTED;
     }
     const int npass = (bits + 7) / 8;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t tps = (len + TILE - 1) / TILE;
+    const int64_t ntiles = tps * nseg;
     uint32_t *err = tmp;
     uint32_t *ghist = tmp + 64;
-    uint32_t *ctr = ghist + 8 * 256;
+    uint32_t *ctr = ghist + (size_t)npass * nseg * 256;
     uint32_t *status = ctr + 64;
-    const int64_t words = 64 + 8 * 256 + 64 + (int64_t)npass * ntiles * 256;
+    const int64_t words = 64 + (int64_t)npass * nseg * 256 + 64 + (int64_t)npass * ntiles * 256;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 1024)), dim3(256), 0, s,
                        tmp + 64, words - 64, 0u);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(TB), 0, s, k0, n, npass,
-                       ghist);
+    const size_t hl = sizeof(uint32_t) * (size_t)nseg * npass * 256;
+    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(TB), hl, s, k0, len, nseg,
+                       npass, ghist);
     CAPT_LAUNCH_CHECK();
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int p = 0; p < npass; ++p) {
-        hipLaunchKernelGGL(k_os_scatter<K>, dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, n, 8 * p,
-                           ghist + p * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
+        hipLaunchKernelGGL(k_os_scatter<K>, dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, len, tps, 8 * p,
+                           ghist + (size_t)p * nseg * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
         CAPT_LAUNCH_CHECK();
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
@@ -326,19 +344,26 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, con
     return CAPT_OK;
 }
 
-size_t radix_tmp_words(int64_t n) {
-    const int64_t ntiles = (n + TILE - 1) / TILE;
-    return (size_t)(64 + 8 * 256 + 64 + 8 * ntiles * 256 + 64);
+size_t radix_tmp_words(int64_t n) { return radix_tmp_words_seg(1, n); }
+
+size_t radix_tmp_words_seg(int nseg, int64_t len) {
+    const int64_t tps = (len + TILE - 1) / TILE;
+    return (size_t)(64 + 8 * 256 * (int64_t)nseg + 64 + 8 * tps * nseg * 256 + 64);
 }
 
 capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where) {
-    return radix_sort<uint64_t>(k0, v0, k1, v1, n, bits, tmp, s, where);
+    return radix_sort<uint64_t>(k0, v0, k1, v1, 1, n, bits, tmp, s, where);
+}
+
+capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int nseg, int64_t len,
+                               int bits, uint32_t *tmp, hipStream_t s, int *where) {
+    return radix_sort<uint64_t>(k0, v0, k1, v1, nseg, len, bits, tmp, s, where);
 }
 
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where) {
-    return radix_sort<uint32_t>(k0, v0, k1, v1, n, bits, tmp, s, where);
+    return radix_sort<uint32_t>(k0, v0, k1, v1, 1, n, bits, tmp, s, where);
 }
 
 }  // namespace capt

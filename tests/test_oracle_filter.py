@@ -116,3 +116,42 @@ def test_per_pass_and_overall_cover(orc, rf):
     d = np.sqrt(((pts[prev][1:].astype(np.float64) - pts[prev][:-1]) ** 2).sum(-1))
     assert (d > rf * (1 - 1e-5)).all()
     assert len(np.unique(prev)) == len(prev)
+
+
+def test_presorted_passes_equal_iterated_sorts(orc):
+    """Each pass's order is "key of the pass, then original index", whatever
+    the earlier passes did: every permutation's key is a bijection of the grid
+    cell, so a tie under one key is a tie under all of them and the stable
+    sorts keep ties in index order.  The survivors of a pass in that order are
+    the full sorted list with the dead points skipped.  Here the filter is
+    recomputed that way (all six orders fixed up front, liveness flags) and
+    must give the oracle's answer, order and per-pass counts included; the
+    cloud holds exact duplicates and near-duplicates so that ties occur."""
+    rng = np.random.default_rng(77)
+    base = rng.random((600, 3)).astype(np.float32)
+    pts = np.concatenate([base, base[:150], base[:40] + np.float32(1e-7), rng.random((400, 3)).astype(np.float32)])
+    pts = pts[rng.permutation(len(pts))]
+    lo, scale = orc.morton_grid(pts)
+    cells = [orc.morton_cell(p, lo, scale) for p in pts]
+    for rf in (0.0, 0.01, 0.05):
+        rf2 = np.float32(rf) * np.float32(rf)
+        live = np.ones(len(pts), bool)
+        counts = []
+        order = None
+        for p in range(6):
+            keys = [orc.morton_key(c.tolist(), p) for c in cells]
+            order = sorted(range(len(pts)), key=lambda i: (keys[i], i))
+            last = None
+            nxt = np.zeros(len(pts), bool)
+            for i in order:
+                if not live[i]:
+                    continue
+                if last is None or orc.sqdist_f32(pts[last], pts[i]) > rf2:
+                    nxt[i] = True
+                    last = i
+            live = nxt
+            counts.append(int(live.sum()))
+        mine = [i for i in order if live[i]]
+        want, want_counts = orc.filter(pts, rf)
+        assert mine == want.tolist(), rf
+        assert counts == want_counts.tolist(), rf
