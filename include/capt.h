@@ -97,7 +97,9 @@ capt_status capt_filter(const float *xyz, int64_t n, float r_filter,
  * the cell's farthest corner is <= r_min^2 (1 - 2^-18), the set is just the
  * representative (Sec. IV-B).  Each leaf also stores the float32 bounding box of its set.
  * Synchronises on `stream` once (to size the affordance sets).  Non-finite
- * points give CAPT_EINVAL and no forest.
+ * points give CAPT_EINVAL and no forest; a cloud of 2^30 points or more, or
+ * whose sets (each padded to a multiple of 16 entries) reach 2^30 entries,
+ * gives CAPT_EUNSUPPORTED.
  */
 capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                        float r_min, float r_max, uint32_t flags, void *stream,
@@ -238,7 +240,7 @@ capt_status capt_query_chunk_stats(capt_forest f, const float *spheres, const in
  *   groups_per_cu    persistent workgroups per compute unit (1 .. 16)
  *   tile_cfgs        configurations a wavefront takes per queue pop in the
  *                    batched kernel (1 .. 4096)
- *   lds_levels       tree levels kept in LDS (1 .. 14)
+ *   lds_levels       tree levels kept in LDS (1 .. 15; fewer if they do not fit)
  *   scan_unroll      64-lane steps of the entry scan kept in flight, 4 chunks
  *                    per step (1, 2 or 4)
  * Zero fields keep their current value.  Applies to later calls.

@@ -17,10 +17,10 @@ import time
 from . import capt_collides, capt_get_tuning, capt_set_tuning
 
 SPACE = {
-    "waves_per_group": [4, 8, 16],
-    "groups_per_cu": [1, 2, 4],
+    "waves_per_group": [4, 8, 12, 16],
+    "groups_per_cu": [1, 2, 3, 4, 6],
     "tile_cfgs": [16, 64, 256],
-    "lds_levels": [12, 13, 14],
+    "lds_levels": [12, 13, 14, 15],
     "scan_unroll": [1, 2, 4],
 }
 

@@ -217,7 +217,7 @@ capt_status capt_set_tuning(const capt_tuning *t) {
         return CAPT_EINVAL;
     }
     if (t->waves_per_group < 0 || t->waves_per_group > 16 || t->groups_per_cu < 0 || t->groups_per_cu > 16 ||
-        t->tile_cfgs < 0 || t->tile_cfgs > 4096 || t->lds_levels < 0 || t->lds_levels > 14 ||
+        t->tile_cfgs < 0 || t->tile_cfgs > 4096 || t->lds_levels < 0 || t->lds_levels > 15 ||
         !(t->scan_unroll == 0 || t->scan_unroll == 1 || t->scan_unroll == 2 || t->scan_unroll == 4)) {
         set_error("tuning value out of range");
         return CAPT_EINVAL;
@@ -495,7 +495,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
         lf.count = (uint32_t)cnt;
         padded += cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0;
         pruned += pr[l] ? 1 : 0;
-        if (padded >= ((int64_t)1 << 32)) {
+        if (padded >= (int64_t)MAX_SET_ENTRIES) {
             set_error("blob sets too large");
             return CAPT_EUNSUPPORTED;
         }

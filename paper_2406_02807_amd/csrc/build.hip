@@ -785,8 +785,8 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     C.set_total = (int64_t)tot[0];
     C.set_padded = (int64_t)tot[1];
     C.pruned = (int64_t)tot[2];
-    if (tot[1] >= (1ull << 32)) {
-        set_error("affordance sets hold %llu entries, more than 2^32", tot[1]);
+    if (tot[1] >= MAX_SET_ENTRIES) {
+        set_error("affordance sets hold %llu entries, more than 2^30", tot[1]);
         return CAPT_EUNSUPPORTED;
     }
     const size_t E = (size_t)(tot[1] > 0 ? tot[1] : CHUNK);

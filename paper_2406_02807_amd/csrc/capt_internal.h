@@ -46,6 +46,9 @@ struct CloudDev {
 // also the unit of the second-level bounding boxes the query scan tests.
 constexpr uint32_t SET_ALIGN = 16;
 constexpr uint32_t CHUNK = SET_ALIGN;
+// Stored set entries per cloud (with padding) stay below this, so the query
+// kernels address the set arrays with 32-bit byte offsets.
+constexpr unsigned long long MAX_SET_ENTRIES = 1ull << 30;
 
 // ---------------------------------------------------------------------------
 // Host-side error state and helpers (api.hip)

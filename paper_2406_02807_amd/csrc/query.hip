@@ -37,6 +37,14 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
     return v;
 }
 
+// Load at a 32-bit byte offset from a wave-uniform base: the address stays a
+// scalar base plus one 32-bit lane offset (no 64-bit per-lane address math).
+// Used for arrays under 4 GiB: T (fewer than 2^30 nodes), the set arrays and
+// chunk boxes (fewer than 2^30 entries).
+template <class T> __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 __device__ __forceinline__ float axis_of(const float4 &q, int a) {
     return a == 0 ? q.x : (a == 1 ? q.y : q.z);
 }
@@ -59,6 +67,49 @@ __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, in
         a = (a == 2) ? 0 : a + 1;
     }
     return i;
+}
+
+// The same descent, shaped for latency: the LDS levels are taken three per
+// round trip (the node, both children and all four grandchildren are read
+// together, then three comparisons pick the path), and the last two global
+// levels are read together (the node and both children), so the leaf record
+// arrives two memory round trips after the LDS part.  Returns the leaf
+// record; *lf gets its index.
+__device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, int L, const float *__restrict__ Tg,
+                                             const Leaf *__restrict__ leaves, int D, uint32_t *lf) {
+    const float xs[3] = {q.x, q.y, q.z};
+    uint32_t i = 0;
+    int lv = 0;
+    for (; lv + 3 <= L; lv += 3) {   // levels lv, lv+1, lv+2 split axes 0, 1, 2 (lv is a multiple of 3)
+        const float t0 = Tl[i];
+        const float t1a = Tl[2 * i + 1], t1b = Tl[2 * i + 2];
+        const float t2a = Tl[4 * i + 3], t2b = Tl[4 * i + 4], t2c = Tl[4 * i + 5], t2d = Tl[4 * i + 6];
+        const uint32_t b0 = xs[0] > t0 ? 1u : 0u;
+        const uint32_t b1 = xs[1] > (b0 ? t1b : t1a) ? 1u : 0u;
+        const float t2 = b0 ? (b1 ? t2d : t2c) : (b1 ? t2b : t2a);
+        const uint32_t b2 = xs[2] > t2 ? 1u : 0u;
+        i = 8 * i + 7 + 4 * b0 + 2 * b1 + b2;
+    }
+    int a = lv % 3;
+    for (; lv < L; ++lv) {
+        i = 2 * i + 1 + (xs[a] > Tl[i] ? 1u : 0u);
+        a = (a == 2) ? 0 : a + 1;
+    }
+    for (; lv + 2 < D; ++lv) {
+        i = 2 * i + 1 + (xs[a] > ld32(Tg, 4u * i) ? 1u : 0u);
+        a = (a == 2) ? 0 : a + 1;
+    }
+    if (D - lv == 2) {
+        const float t0 = ld32(Tg, 4u * i), t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
+        const int a1 = (a == 2) ? 0 : a + 1;
+        const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
+        const uint32_t b1 = xs[a1] > (b0 ? t1b : t1a) ? 1u : 0u;
+        i = 4 * i + 3 + 2 * b0 + b1;
+    } else if (D - lv == 1) {
+        i = 2 * i + 1 + (xs[a] > ld32(Tg, 4u * i) ? 1u : 0u);
+    }
+    *lf = i - ((1u << D) - 1u);
+    return leaves[*lf];
 }
 
 // Per-wave LDS scratch of the two-level set scan.
@@ -100,28 +151,19 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // entry.  A hit retires its configuration: its spheres' ring chunks are
 // skipped and the level-1 prefix is rebuilt over the spheres still open.
 template <int U>
-__device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L,
-                                          const float4 *__restrict__ sph, int nsph, int g, WaveLds &W) {
+__device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L, float4 q, int nsph, int g,
+                                          WaveLds &W) {
     const int lane = lane_id();
     const bool valid = lane < nsph;
-    float4 q = valid ? sph[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float r2 = __fmul_rn(q.w, q.w);
-    const int64_t N = (int64_t)1 << C.D;
-    const uint32_t node = descend(q, Tl, L, C.T, C.D);
-    const uint32_t lf = node - (uint32_t)(N - 1);
     Leaf leaf;
-    if (valid) {
-        leaf = C.leaf[lf];
-    } else {
-        leaf.count = 0;
-        leaf.start = 0;
-    }
-    bool alive = valid && leaf.count > 0;
+    uint32_t lf;
+    leaf = descend_leaf(q, Tl, L, C.T, C.leaf, C.D, &lf);
+    if (!valid) leaf.count = 0;
+    bool alive = leaf.count > 0;
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
     wave_lds_sync();   // the previous tile's readers of W are done
     W.sph[lane] = make_float4(q.x, q.y, q.z, r2);
-    wave_lds_sync();
-
     const int gg = g > WAVE ? WAVE : g;
     const int cfg = g > WAVE ? 0 : lane / gg;
     const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
@@ -130,7 +172,17 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     uint64_t dead = 0;                                    // lanes whose configuration is hit
     uint32_t rem = alive ? (leaf.count + CHUNK - 1) / CHUNK : 0u;   // chunks not yet box-tested
     uint32_t cpos = leaf.start / CHUNK;                   // the first of them
-    uint32_t head = 0, tail = 0;                          // ring [head, tail), wave-uniform
+    // A one-chunk set's chunk box is its leaf AABB, already passed: straight
+    // to the entry scan.
+    const bool direct = rem == 1u;
+    const uint64_t dm = __ballot(direct);
+    if (direct) {
+        const uint32_t at = lanes_below(dm);
+        W.chunk[at] = cpos;
+        W.owner[at] = (uint8_t)lane;
+        rem = 0u;
+    }
+    uint32_t head = 0, tail = (uint32_t)__popcll(dm);     // ring [head, tail), wave-uniform
     const float4 *__restrict__ CB = C.cbox;
     const float *__restrict__ PX = C.px;
     const float *__restrict__ PY = C.py;
@@ -158,9 +210,9 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             own[u] = o;
             s[u] = W.sph[o];
             const uint32_t e = ch * CHUNK + ((uint32_t)lane & (CHUNK - 1));
-            px[u] = in[u] ? PX[e] : 0.f;
-            py[u] = in[u] ? PY[e] : 0.f;
-            pz[u] = in[u] ? PZ[e] : 0.f;
+            px[u] = in[u] ? ld32(PX, 4u * e) : 0.f;
+            py[u] = in[u] ? ld32(PY, 4u * e) : 0.f;
+            pz[u] = in[u] ? ld32(PZ, 4u * e) : 0.f;
         }
         uint64_t om = 0;   // owners hit by this lane's entries
 #pragma unroll
@@ -179,6 +231,10 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
         return true;
     };
 
+    wave_lds_sync();
+    while (tail - head >= (uint32_t)U * CPS) {
+        if (entry_round((uint32_t)U * CPS) && single) return done;
+    }
     while (true) {
         if (done) rem = 0;
         const uint32_t incl = wave_incl_scan(rem, lane);
@@ -201,8 +257,8 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             const float4 so = W.sph[o];
             bool surv = false;
             if (in) {
-                const float4 a = CB[2 * (size_t)ch];
-                const float4 b = CB[2 * (size_t)ch + 1];
+                const float4 a = ld32(CB, 32u * ch);
+                const float4 b = ld32(CB, 32u * ch + 16u);
                 const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
                 surv = box_sqdist(so.x, so.y, so.z, lo, hi) <= so.w;
             }
@@ -264,17 +320,29 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
         const int64_t ta = t0 + (int64_t)c;
         if (ta >= t1) break;
         const int64_t tb = min<int64_t>(ta + chunk, t1);
-        for (int64_t t = ta; t < tb; ++t) {
-            if (g <= WAVE) {
+        if (g <= WAVE) {
+            // the next tile's spheres are loaded while this one is processed
+            auto load = [&](int64_t t) {
                 const int64_t c0 = t * cpt;
                 const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-                const bool hit = wave_tile<U>(C, Tl, L, sph + c0 * g, nc * g, g, W);
+                return lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            };
+            float4 qn = load(ta);
+            for (int64_t t = ta; t < tb; ++t) {
+                const float4 q = qn;
+                if (t + 1 < tb) qn = load(t + 1);
+                const int64_t c0 = t * cpt;
+                const int nc = (int)min<int64_t>(cpt, ncfg - c0);
+                const bool hit = wave_tile<U>(C, Tl, L, q, nc * g, g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
-            } else {
+            }
+        } else {
+            for (int64_t t = ta; t < tb; ++t) {
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile<U>(C, Tl, L, sph + t * g + s0, ns, g, W);
+                    const float4 q = lane < ns ? sph[t * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    hit = wave_tile<U>(C, Tl, L, q, ns, g, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[t] = (uint8_t)hit;
@@ -318,7 +386,8 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
-                const bool hit = wave_tile<U>(C, nullptr, 0, sph + c0 * g, nc * g, g, W);
+                const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const bool hit = wave_tile<U>(C, nullptr, 0, q, nc * g, g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -327,7 +396,8 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 bool hit = false;
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
-                    hit = wave_tile<U>(C, nullptr, 0, sph + cc * g + s0, ns, g, W);
+                    const float4 q = lane < ns ? sph[cc * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    hit = wave_tile<U>(C, nullptr, 0, q, ns, g, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[cc] = (uint8_t)hit;
@@ -468,7 +538,7 @@ __global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r
 }  // namespace
 
 capt_tuning &tuning() {
-    static capt_tuning t = {16, 4, 16, 14, 4};
+    static capt_tuning t = {12, 2, 16, 13, 2};
     return t;
 }
 
@@ -501,7 +571,7 @@ namespace {
 
 // Tree levels kept in LDS beside `extra` bytes of per-wave scratch.
 int lds_levels_for(int D, size_t extra) {
-    int L = std::min(D, std::max(0, std::min(14, (int)tuning().lds_levels)));
+    int L = std::min(D, std::max(0, std::min(15, (int)tuning().lds_levels)));
     const size_t cap = (size_t)device_info().lds_per_block;
     while (L > 0 && extra + sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
     return L;
