@@ -49,12 +49,16 @@ __global__ void k_count_nonfinite(const float *__restrict__ xyz, int64_t cnt, ui
     if (b) atomicAdd(bad, b);
 }
 
-__global__ void k_presort_keys(const float *__restrict__ xyz, int64_t n, int64_t N, int a,
-                               uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+// Sort keys of all three axes: segment a of keys / vals holds axis a.
+__global__ void k_presort_keys(const float *__restrict__ xyz, int64_t n, int64_t N, uint32_t *__restrict__ keys,
+                               uint32_t *__restrict__ vals) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    keys[j] = j < n ? ord_key(xyz[3 * j + a]) : 0xFFFFFFFFu;
-    vals[j] = (uint32_t)j;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        keys[a * N + j] = j < n ? ord_key(xyz[3 * j + a]) : 0xFFFFFFFFu;
+        vals[a * N + j] = (uint32_t)j;
+    }
 }
 
 // Global level: split values and "goes left" flags from the list on axis a.
@@ -456,16 +460,22 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         for (int a = 0; a < 3; ++a) {
             cl[a] = (double)c[a];
             ch[a] = (double)c[3 + a];
-            const double lo_b = fmax(cl[a] - A.R, g.lo[a]);
-            const double hi_b = fmin(ch[a] + A.R, g.hi[a]);
+            // A point that passes the float64 test below lies within R of the
+            // cell on every axis up to rounding (about 1e-16 relative); the
+            // slack covers that, and bin_of is monotone, so the bins from
+            // bin_of(lo_b) to bin_of(hi_b) hold every such point.
+            const double slack =
+                1e-9 * (A.R + 1.0 + (isfinite(cl[a]) ? fabs(cl[a]) : 0.0) + (isfinite(ch[a]) ? fabs(ch[a]) : 0.0));
+            const double lo_b = fmax(cl[a] - A.R - slack, g.lo[a]);
+            const double hi_b = fmin(ch[a] + A.R + slack, g.hi[a]);
             if (!(lo_b <= hi_b)) {
                 empty = true;
                 b0[a] = 0;
                 b1[a] = -1;
                 continue;
             }
-            b0[a] = max(bin_of(lo_b, g.origin[a], g.g, g.dims[a]) - 1, 0);
-            b1[a] = min(bin_of(hi_b, g.origin[a], g.g, g.dims[a]) + 1, g.dims[a] - 1);
+            b0[a] = bin_of(lo_b, g.origin[a], g.g, g.dims[a]);
+            b1[a] = bin_of(hi_b, g.origin[a], g.g, g.dims[a]);
         }
         if (!empty) {
             const int64_t ny = b1[1] - b0[1] + 1;
@@ -633,12 +643,13 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         return o;
     };
     const size_t oL = take(sizeof(uint32_t) * 6 * wN);     // 3 lists x 2 buffers
-    const size_t oK = take(sizeof(uint32_t) * 2 * std::max(wN, wn));   // sort keys x 2
+    const size_t oK = take(sizeof(uint32_t) * 2 * std::max(3 * wN, wn));   // sort keys x 2
     const size_t oV = take(sizeof(uint32_t) * 2 * wn);     // grid sort values x 2
     const size_t oInv = take(sizeof(uint32_t) * wN);
     const size_t oLeft = take(wN);
     const size_t oSums = take(sizeof(uint32_t) * (2 * ntile + 16));
-    const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words(std::max<int64_t>(N, n)));
+    const size_t oRad = take(sizeof(uint32_t) * std::max(radix_tmp_words(std::max<int64_t>(N, n)),
+                                                         radix_tmp_words_seg(3, N)));
     const size_t oCells = take(sizeof(float) * 6 * wN);
     const size_t oCnt = take(sizeof(uint32_t) * (wN + 1));
     const size_t oPs = take(sizeof(uint32_t) * (wN + 1));
@@ -678,18 +689,19 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         CAPT_LAUNCH_CHECK();
     }
 
-    // 1. presort on each axis: L[a] (buffer 0) sorted by (coordinate, id)
+    // 1. presort: list a sorted by (coordinate a, id), the three lists in
+    //    one segmented sort (buffer b holds the three lists back to back)
     uint32_t *L[3][2];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 2; ++b) L[a][b] = Lbuf + (size_t)(2 * a + b) * wN;
+        for (int b = 0; b < 2; ++b) L[a][b] = Lbuf + (size_t)(3 * b + a) * wN;
     int cur[3] = {0, 0, 0};
-    for (int a = 0; a < 3; ++a) {
-        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, a, keys, L[a][0]);
+    {
+        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, keys, L[0][0]);
         CAPT_LAUNCH_CHECK();
         int where = 0;
-        capt_status st = radix_sort_u32(keys, L[a][0], keys + wN, L[a][1], N, 32, rad, s, &where);
+        capt_status st = radix_sort_u32_seg(keys, L[0][0], keys + 3 * wN, L[0][1], 3, N, 32, rad, s, &where);
         if (st) return st;
-        cur[a] = where;
+        cur[0] = cur[1] = cur[2] = where;
     }
 
     // 2. splits: global levels while segments exceed LMAX, then LDS levels

@@ -119,6 +119,8 @@ capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v
 size_t radix_tmp_words_seg(int nseg, int64_t len);
 capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int nseg, int64_t len,
                                int bits, uint32_t *tmp, hipStream_t s, int *where);
+capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int nseg, int64_t len,
+                               int bits, uint32_t *tmp, hipStream_t s, int *where);
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where);
 

@@ -290,7 +290,7 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
                        hipStream_t s, int *where) {
     *where = 0;
     if (len <= 1 || bits <= 0 || nseg <= 0) return CAPT_OK;
-    if (nseg > MAX_SEG || len * nseg >= ((int64_t)1 << 30)) {
+    if (nseg > MAX_SEG || len >= ((int64_t)1 << 30)) {   // 30-bit counts per segment
         set_error("radix sort of %d x %lld keys exceeds the supported size", nseg, (long long)len);
         return CAPT_EUNSUPPORTED;
     }
@@ -364,6 +364,11 @@ capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                            int bits, uint32_t *tmp, hipStream_t s, int *where) {
     return radix_sort<uint32_t>(k0, v0, k1, v1, 1, n, bits, tmp, s, where);
+}
+
+capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int nseg, int64_t len,
+                               int bits, uint32_t *tmp, hipStream_t s, int *where) {
+    return radix_sort<uint32_t>(k0, v0, k1, v1, nseg, len, bits, tmp, s, where);
 }
 
 }  // namespace capt
