@@ -29,6 +29,7 @@ namespace {
 
 constexpr int TB = 256;
 constexpr int LMAX = 2048;   // subtree size finished in LDS
+constexpr int LMAX_LOG2 = 11;
 constexpr int GTILE = 2048;  // tile of the global partition passes
 
 __device__ __forceinline__ uint32_t ord_key(float v) {
@@ -39,6 +40,18 @@ __device__ __forceinline__ uint32_t ord_key(float v) {
 
 __device__ __forceinline__ float coord_of(const float *xyz, int64_t n, uint32_t id, int a) {
     return (int64_t)id < n ? xyz[3 * (int64_t)id + a] : INFINITY;
+}
+
+__global__ void k_fill_u32_b(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_count_nonfinite(const float *__restrict__ xyz, int64_t cnt, uint32_t *bad) {
@@ -97,52 +110,37 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lw, ui
     return off + inc - v;
 }
 
-// Global partition, pass 1: per tile count of left-going points, for the two
-// lists given by blockIdx.y.
-__global__ void k_gpart_count(const uint32_t *__restrict__ Lb0, const uint32_t *__restrict__ Lb1,
-                              const uint8_t *__restrict__ left, int64_t N,
-                              uint32_t *__restrict__ sums, int64_t ntile) {
-    __shared__ uint32_t lw[TB / WAVE];
-    const uint32_t *L = blockIdx.y ? Lb1 : Lb0;
-    const int64_t base = (int64_t)blockIdx.x * GTILE + (int64_t)threadIdx.x * 8;
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) c += left[L[base + i]];
-    uint32_t tot;
-    block_excl_scan(c, lw, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.y * ntile + blockIdx.x] = tot;
-}
+// One global level d in one launch: the two lists not on the split axis are
+// stably partitioned inside every segment of s = N >> d positions ("goes
+// left" first), tiles of GTILE finding their offset inside the segment by
+// decoupled look-back over the segment's earlier tiles (a segment's first
+// tile publishes a prefix at once, so every wait ends; waits are also
+// bounded).  The first of the two lists is on the axis of level d + 1, and
+// its new order fixes that level: while scattering it the kernel writes level
+// d + 1's split values and "goes left" flags (when `next` is set).
+constexpr uint32_t LB_AGG = 1u << 30;
+constexpr uint32_t LB_PRE = 2u << 30;
+constexpr uint32_t LB_VAL = (1u << 30) - 1u;
+constexpr uint32_t LB_SPINS = 1u << 20;
 
-// Pass 2: exclusive scan of the tile counts of each list (one block per list).
-__global__ void k_gpart_scan(uint32_t *__restrict__ sums, int64_t ntile) {
+__global__ void __launch_bounds__(TB) k_glevel(const uint32_t *__restrict__ Lb1, const uint32_t *__restrict__ Lb2,
+                                               uint32_t *__restrict__ Ob1, uint32_t *__restrict__ Ob2,
+                                               const uint8_t *__restrict__ left, uint8_t *__restrict__ left_next,
+                                               const float *__restrict__ xyz, int64_t n, int64_t N, int d, int next,
+                                               float *__restrict__ T, uint32_t *__restrict__ status,
+                                               uint32_t *__restrict__ ctr, int64_t ntile, uint32_t *__restrict__ err) {
     __shared__ uint32_t lw[TB / WAVE];
-    __shared__ uint32_t carry;
-    uint32_t *S = sums + blockIdx.x * ntile;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ uint32_t s_tile, s_excl;
+    const int y = blockIdx.y;
+    const uint32_t *L = y ? Lb2 : Lb1;
+    uint32_t *O = y ? Ob2 : Ob1;
+    uint32_t *St = status + (size_t)y * ntile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&ctr[y], 1u);
     __syncthreads();
-    for (int64_t c0 = 0; c0 < ntile; c0 += TB) {
-        int64_t j = c0 + threadIdx.x;
-        uint32_t v = j < ntile ? S[j] : 0u;
-        uint32_t tot;
-        uint32_t e = block_excl_scan(v, lw, &tot) + carry;
-        if (j < ntile) S[j] = e;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
-    }
-}
-
-// Pass 3: stable scatter within each segment of size s = N >> d.
-__global__ void k_gpart_scatter(const uint32_t *__restrict__ Lb0, const uint32_t *__restrict__ Lb1,
-                                uint32_t *__restrict__ Ob0, uint32_t *__restrict__ Ob1,
-                                const uint8_t *__restrict__ left, int64_t N, int d,
-                                const uint32_t *__restrict__ sums, int64_t ntile) {
-    __shared__ uint32_t lw[TB / WAVE];
-    const uint32_t *L = blockIdx.y ? Lb1 : Lb0;
-    uint32_t *O = blockIdx.y ? Ob1 : Ob0;
-    const uint32_t *S = sums + blockIdx.y * ntile;
+    const int64_t t = s_tile;
     const int64_t s = N >> d, h = s >> 1;
-    const int64_t base = (int64_t)blockIdx.x * GTILE + (int64_t)threadIdx.x * 8;
+    const int64_t tps = s / GTILE;   // >= 2 on a global level
+    const int64_t base = t * GTILE + (int64_t)threadIdx.x * 8;
     uint32_t p[8], f[8], c = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -151,16 +149,52 @@ __global__ void k_gpart_scatter(const uint32_t *__restrict__ Lb0, const uint32_t
         c += f[i];
     }
     uint32_t tot;
-    uint32_t e = block_excl_scan(c, lw, &tot) + S[blockIdx.x];
+    uint32_t e = block_excl_scan(c, lw, &tot);
+    if (threadIdx.x == 0) {
+        const int64_t t0 = t & ~(tps - 1);   // the segment's first tile
+        uint32_t ex = 0;
+        if (t == t0) {
+            st_agent(&St[t], LB_PRE | tot);
+        } else {
+            st_agent(&St[t], LB_AGG | tot);
+            int64_t q = t - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t v = ld_agent(&St[q]);
+                const uint32_t flag = v & ~LB_VAL;
+                if (flag == 0) {
+                    if (++spins > LB_SPINS) {
+                        atomicOr(err, 8u);
+                        break;
+                    }
+                    continue;
+                }
+                ex += v & LB_VAL;
+                if (flag == LB_PRE) break;
+                --q;
+            }
+            st_agent(&St[t], LB_PRE | (ex + tot));
+        }
+        s_excl = ex;
+    }
+    __syncthreads();
+    e += s_excl;   // left-goers of the segment before this thread's items
     const int64_t seg = base & ~(s - 1);
-    const uint32_t eseg = S[seg / GTILE];
+    const int64_t s2 = s >> 1, h2 = s2 >> 1;
+    const int lg2 = 62 - __builtin_clzll((unsigned long long)s);   // log2(s / 2)
+    const int an = (d + 1) % 3;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int64_t q = base + i;
-        const int64_t lc = (int64_t)(e - eseg);
+        const int64_t lc = (int64_t)e;
         const int64_t np = f[i] ? seg + lc : seg + h + (q - seg - lc);
         O[np] = p[i];
         e += f[i];
+        if (y == 0 && next) {
+            const int64_t k2 = np & (s2 - 1);
+            left_next[p[i]] = (uint8_t)(k2 < h2);
+            if (k2 == h2 - 1) T[((int64_t)1 << (d + 1)) - 1 + (np >> lg2)] = coord_of(xyz, n, p[i], an);
+        }
     }
 }
 
@@ -646,8 +680,10 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     const size_t oK = take(sizeof(uint32_t) * 2 * std::max(3 * wN, wn));   // sort keys x 2
     const size_t oV = take(sizeof(uint32_t) * 2 * wn);     // grid sort values x 2
     const size_t oInv = take(sizeof(uint32_t) * wN);
-    const size_t oLeft = take(wN);
-    const size_t oSums = take(sizeof(uint32_t) * (2 * ntile + 16));
+    const size_t oLeft = take(2 * wN);   // "goes left" flags, two levels
+    const int nglob = std::max(0, D - LMAX_LOG2);   // global levels (segments above LMAX)
+    const size_t lvl_words = 2 * ntile + 64;          // per global level: two status lists, two counters
+    const size_t oSums = take(sizeof(uint32_t) * (lvl_words * (size_t)std::max(nglob, 1) + 64));
     const size_t oRad = take(sizeof(uint32_t) * std::max(radix_tmp_words(std::max<int64_t>(N, n)),
                                                          radix_tmp_words_seg(3, N)));
     const size_t oCells = take(sizeof(float) * 6 * wN);
@@ -706,23 +742,28 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
 
     // 2. splits: global levels while segments exceed LMAX, then LDS levels
     int d = 0;
+    if ((N >> d) > LMAX) {
+        const size_t words = lvl_words * (size_t)nglob;
+        hipLaunchKernelGGL(k_fill_u32_b, dim3((unsigned)std::min<size_t>((words + TB - 1) / TB, 1024)), dim3(TB), 0,
+                           s, sums, (int64_t)words, 0u);
+        CAPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], xyz, n, N, 0, 0, T, left);
+        CAPT_LAUNCH_CHECK();
+    }
+    uint8_t *lf_cur = left, *lf_next = left + wN;
     for (; d < D && (N >> d) > LMAX; ++d) {
         const int a = d % 3;
         const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
-        hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[a][cur[a]], xyz, n, N, d, a, T,
-                           left);
-        CAPT_LAUNCH_CHECK();
         const int64_t nt = N / GTILE;
-        hipLaunchKernelGGL(k_gpart_count, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]],
-                           L[b2][cur[b2]], left, N, sums, nt);
-        CAPT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gpart_scan, dim3(2), dim3(TB), 0, s, sums, nt);
-        CAPT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gpart_scatter, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]],
-                           L[b2][cur[b2]], L[b1][cur[b1] ^ 1], L[b2][cur[b2] ^ 1], left, N, d, sums, nt);
+        uint32_t *lv = sums + lvl_words * (size_t)d;
+        const int next = (N >> (d + 1)) > LMAX ? 1 : 0;
+        hipLaunchKernelGGL(k_glevel, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]], L[b2][cur[b2]],
+                           L[b1][cur[b1] ^ 1], L[b2][cur[b2] ^ 1], lf_cur, lf_next, xyz, n, N, d, next, T, lv,
+                           lv + 2 * nt, nt, rad);
         CAPT_LAUNCH_CHECK();
         cur[b1] ^= 1;
         cur[b2] ^= 1;
+        std::swap(lf_cur, lf_next);
     }
     hipLaunchKernelGGL(k_inverse, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], N, inv);
     CAPT_LAUNCH_CHECK();

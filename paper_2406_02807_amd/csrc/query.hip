@@ -134,10 +134,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Process one tile of up to 64 spheres against one cloud.  Lane l holds
-// sphere l of the tile (valid if l < nsph); lanes of configuration c are
-// c*g .. c*g+g-1 (g <= 64), or all lanes belong to one configuration (g > 64).
-// Returns, per lane, whether that lane's configuration was hit.
+// Process one tile of up to 64 spheres against one cloud.  Lane l holds a
+// sphere if `valid`; the lanes form groups of gg (lanes c*gg .. c*gg+gg-1),
+// each group a part of one configuration, or the whole wave is one
+// configuration (`single`).  Returns, per lane, whether a sphere of its group
+// (its configuration when single) was hit.
 //
 // A surviving sphere's set is stored as 16-entry chunks, each with a float32
 // bounding box.  Level 1 box-tests the (sphere, chunk) pairs of all surviving
@@ -151,10 +152,9 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // entry.  A hit retires its configuration: its spheres' ring chunks are
 // skipped and the level-1 prefix is rebuilt over the spheres still open.
 template <int U>
-__device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L, float4 q, int nsph, int g,
-                                          WaveLds &W) {
+__device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L, float4 q, bool valid, int gg,
+                                          bool single, WaveLds &W) {
     const int lane = lane_id();
-    const bool valid = lane < nsph;
     const float r2 = __fmul_rn(q.w, q.w);
     Leaf leaf;
     uint32_t lf;
@@ -164,10 +164,8 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
     wave_lds_sync();   // the previous tile's readers of W are done
     W.sph[lane] = make_float4(q.x, q.y, q.z, r2);
-    const int gg = g > WAVE ? WAVE : g;
-    const int cfg = g > WAVE ? 0 : lane / gg;
+    const int cfg = lane / gg;
     const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
-    const bool single = (g > WAVE) || (2 * g > nsph);   // one configuration in this tile
     bool done = false;
     uint64_t dead = 0;                                    // lanes whose configuration is hit
     uint32_t rem = alive ? (leaf.count + CHUNK - 1) / CHUNK : 0u;   // chunks not yet box-tested
@@ -333,7 +331,7 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
                 if (t + 1 < tb) qn = load(t + 1);
                 const int64_t c0 = t * cpt;
                 const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-                const bool hit = wave_tile<U>(C, Tl, L, q, nc * g, g, W);
+                const bool hit = wave_tile<U>(C, Tl, L, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -342,10 +340,82 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
                     const float4 q = lane < ns ? sph[t * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    hit = wave_tile<U>(C, Tl, L, q, ns, g, W);
+                    hit = wave_tile<U>(C, Tl, L, q, lane < ns, WAVE, true, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[t] = (uint8_t)hit;
+            }
+        }
+    }
+}
+
+// Configurations of more than SLOT spheres, with early exit inside a
+// configuration: the wave's 64 lanes form NSLOT slots of SLOT lanes; a slot
+// holds one configuration and tests its spheres SLOT at a time, in order,
+// stopping at the first piece with a hit (as a sequential scan of the
+// configuration would); a slot that finishes takes the next configuration
+// from the wave's popped range (per-XCD queues as above).  The slots of a
+// wave run together through the two-level scan, each slot a group.
+constexpr int SLOT = 16;
+
+template <int U>
+__global__ void k_collide_slots(CloudDev C, const float4 *__restrict__ sph, int64_t ncfg, int g,
+                                uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
+    extern __shared__ float4 lds4[];
+    WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
+    float *Tl = reinterpret_cast<float *>(reinterpret_cast<WaveLds *>(lds4) + blockDim.x / WAVE);
+    const int nT = (1 << L) - 1;
+    for (int i = threadIdx.x; i < nT; i += blockDim.x) Tl[i] = C.T[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const int j = lane & (SLOT - 1);
+    const int lead = lane & ~(SLOT - 1);   // first lane of this lane's slot
+    const int nq = (int)min<int64_t>(NXCD, (int64_t)gridDim.x);
+    const int xq = (int)(blockIdx.x % (unsigned)nq);
+    const int64_t t0 = ncfg * xq / nq, t1 = ncfg * (xq + 1) / nq;
+    int64_t ra = 0, rb = 0;   // popped configurations not yet started (wave-uniform)
+    bool drained = false;
+    int64_t cfg = -1;         // the configuration in this lane's slot, -1 = free
+    int s0 = 0;               // its next piece starts at sphere s0
+    while (true) {
+        // fill free slots in slot order, popping more configurations as needed
+        while (true) {
+            const uint64_t freem = __ballot(j == 0 && cfg < 0);
+            if (freem == 0) break;
+            if (ra >= rb) {
+                if (drained) break;
+                unsigned int c = 0;
+                if (lane == 0) c = atomicAdd(&ctr[xq * CTR_STRIDE], (unsigned int)chunk);
+                c = __shfl(c, 0, WAVE);
+                const int64_t a = t0 + (int64_t)c;
+                if (a >= t1) {
+                    drained = true;
+                    break;
+                }
+                ra = a;
+                rb = min<int64_t>(a + chunk, t1);
+            }
+            const bool myfree = (freem >> lead) & 1ull;
+            const int64_t rank = __popcll(freem & ((1ull << lead) - 1ull));   // free slots before this one
+            if (myfree && rank < rb - ra) {
+                cfg = ra + rank;
+                s0 = 0;
+            }
+            ra = min<int64_t>(ra + __popcll(freem), rb);
+        }
+        const bool active = cfg >= 0;
+        if (__ballot(active) == 0) break;   // range drained and every slot finished
+        const int si = s0 + j;
+        const bool valid = active && si < g;
+        const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
+        bool hit = wave_tile<U>(C, Tl, L, q, valid, SLOT, false, W);
+        hit = __shfl(hit, lead, WAVE);   // the slot's first lane always holds a sphere
+        if (active) {
+            if (hit || s0 + SLOT >= g) {
+                if (j == 0) out[cfg] = (uint8_t)hit;
+                cfg = -1;
+            } else {
+                s0 += SLOT;
             }
         }
     }
@@ -387,7 +457,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const bool hit = wave_tile<U>(C, nullptr, 0, q, nc * g, g, W);
+                const bool hit = wave_tile<U>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -397,7 +467,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
                     const float4 q = lane < ns ? sph[cc * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    hit = wave_tile<U>(C, nullptr, 0, q, ns, g, W);
+                    hit = wave_tile<U>(C, nullptr, 0, q, lane < ns, WAVE, true, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[cc] = (uint8_t)hit;
@@ -602,7 +672,8 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_wave / 8));
     const size_t lds = wl + sizeof(float) * (size_t)((1 << L) - 1);
     static const bool lds_ok = allow_lds(k_collide_cloud<4>) == CAPT_OK && allow_lds(k_collide_cloud<2>) == CAPT_OK &&
-                               allow_lds(k_collide_cloud<1>) == CAPT_OK;
+                               allow_lds(k_collide_cloud<1>) == CAPT_OK && allow_lds(k_collide_slots<4>) == CAPT_OK &&
+                               allow_lds(k_collide_slots<2>) == CAPT_OK && allow_lds(k_collide_slots<1>) == CAPT_OK;
     if (!lds_ok) {
         set_error("raising the dynamic LDS limit of the collision kernel failed");
         return CAPT_EHIP;
@@ -610,6 +681,27 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
     CAPT_LAUNCH_CHECK();
     const float4 *sp = reinterpret_cast<const float4 *>(spheres);
+    if (g > SLOT) {
+        // slots: the queue holds configurations
+        const int64_t per_cfg_wave = ncfg / std::max<int64_t>(1, blocks * wpb);
+        const int cchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_cfg_wave / 8));
+        switch (t.scan_unroll) {
+            case 4:
+                hipLaunchKernelGGL(k_collide_slots<4>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
+                                   out, L, ctr, cchunk);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_collide_slots<2>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
+                                   out, L, ctr, cchunk);
+                break;
+            default:
+                hipLaunchKernelGGL(k_collide_slots<1>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
+                                   out, L, ctr, cchunk);
+                break;
+        }
+        CAPT_LAUNCH_CHECK();
+        return CAPT_OK;
+    }
     switch (t.scan_unroll) {
         case 4:
             hipLaunchKernelGGL(k_collide_cloud<4>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
