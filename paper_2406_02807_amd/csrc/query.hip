@@ -437,6 +437,46 @@ __global__ void k_reset_counter(unsigned int *ctr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = 0u;
 }
 
+// The slot scheme of k_collide_slots over one fixed range of configurations
+// [c0, c1) of one cloud (no LDS tree levels); returns when all are answered.
+template <int U>
+__device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ sph, int g, int64_t c0, int64_t c1,
+                                 uint8_t *__restrict__ out, WaveLds &W) {
+    const int lane = lane_id();
+    const int j = lane & (SLOT - 1);
+    const int lead = lane & ~(SLOT - 1);
+    int64_t ra = c0;
+    int64_t cfg = -1;
+    int s0 = 0;
+    while (true) {
+        const uint64_t freem = __ballot(j == 0 && cfg < 0);
+        if (freem != 0 && ra < c1) {
+            const bool myfree = (freem >> lead) & 1ull;
+            const int64_t rank = __popcll(freem & ((1ull << lead) - 1ull));
+            if (myfree && rank < c1 - ra) {
+                cfg = ra + rank;
+                s0 = 0;
+            }
+            ra = min<int64_t>(ra + __popcll(freem), c1);
+        }
+        const bool active = cfg >= 0;
+        if (__ballot(active) == 0) break;
+        const int si = s0 + j;
+        const bool valid = active && si < g;
+        const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
+        bool hit = wave_tile<U>(C, nullptr, 0, q, valid, SLOT, false, W);
+        hit = __shfl(hit, lead, WAVE);
+        if (active) {
+            if (hit || s0 + SLOT >= g) {
+                if (j == 0) out[cfg] = (uint8_t)hit;
+                cfg = -1;
+            } else {
+                s0 += SLOT;
+            }
+        }
+    }
+}
+
 template <int U>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
@@ -451,7 +491,9 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
         if ((int64_t)t >= ntiles) break;
         const Tile tile = tiles[t];
         const CloudDev C = clouds[tile.cloud];
-        if (g <= WAVE) {
+        if (g > SLOT) {
+            slots_over_range<U>(C, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
+        } else {
             const int cpt = WAVE / g;
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
@@ -459,18 +501,6 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
                 const bool hit = wave_tile<U>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
-            }
-        } else {
-            for (int c = 0; c < tile.ncfg; ++c) {
-                const int64_t cc = tile.cfg0 + c;
-                bool hit = false;
-                for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
-                    const int ns = min(WAVE, g - s0);
-                    const float4 q = lane < ns ? sph[cc * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    hit = wave_tile<U>(C, nullptr, 0, q, lane < ns, WAVE, true, W);
-                    hit = __shfl(hit, 0, WAVE);
-                }
-                if (lane == 0) out[cc] = (uint8_t)hit;
             }
         }
     }
