@@ -82,10 +82,16 @@ def algorithmic_bytes(capt, forest, spheres_dev, group):
     }
 
 
-def traffic_from_profiles(kernel_src_hash):
+def query_kernel(group):
+    """The kernel capt_collides launches for one cloud: configurations above 16
+    spheres run in 16-lane slots."""
+    return "k_collide_slots" if group > 16 else "k_collide_cloud"
+
+
+def traffic_from_profiles(kernel, kernel_src_hash):
     """HBM bytes per launch measured with rocprofv3 counters (committed under
     profiles/), or None when missing or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", "k_collide_cloud_tabletop_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"{kernel}_tabletop_traffic.json")
     try:
         d = json.load(open(p))
     except Exception:
@@ -304,7 +310,7 @@ def main():
     alg_bytes, alg = algorithmic_bytes(capt, forest, sph, G)
     q_ms = float(query.mean())
     achieved = alg_bytes / (q_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(src_hash())
+    traffic = traffic_from_profiles(query_kernel(G), src_hash())
     result = {
         "metric": METRIC,
         "value": value,
@@ -335,7 +341,7 @@ def main():
         "collision_rate": float(out.float().mean().item()),
         "tuning": tuned,
         "roofline": {
-            "kernel": "k_collide_cloud",
+            "kernel": query_kernel(G),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
