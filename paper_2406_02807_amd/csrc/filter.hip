@@ -159,12 +159,17 @@ __global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
     if (i < n) p[i] = v;
 }
 
-constexpr int CT = 1024;             // threads of the chain kernel
-constexpr int CI = 2;                // positions per thread
+constexpr int CT = 256;              // threads of the chain kernel
+constexpr int CI = 1;                // positions per thread
 constexpr int CC = CT * CI;          // chunk length
-constexpr int CR = 11;               // log2(CC): jump tables J_0 .. J_10
+constexpr int CR = 8;                // log2(CC): jump tables J_0 .. J_7
+// dynamic LDS of the chain kernel: J [CR][CC] u16, Nx [CC] u32, Ex [CC] u32, mark [CC] i8
+constexpr size_t CHAIN_LDS = sizeof(uint16_t) * CR * CC + 2 * sizeof(uint32_t) * CC + CC;
 constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"
 constexpr uint32_t PUB = 0x80000000u;
+constexpr uint32_t MX_AGG = 0x40000000u;   // farthest reach: this chunk's own (positions < 2^30)
+constexpr uint32_t MX_PRE = 0x80000000u;   // farthest reach of chunks 0 .. c
+constexpr uint32_t MX_FLAGS = 0xC0000000u;
 constexpr uint32_t SPIN_LIMIT = 1u << 20;
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
@@ -205,14 +210,20 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
                                                     int64_t n, const uint8_t *__restrict__ live_in,
                                                     uint8_t *__restrict__ live_out, FState *__restrict__ st,
                                                     float rf2, int last, uint32_t *__restrict__ exit_pub,
-                                                    uint32_t *__restrict__ kept_st, uint32_t *__restrict__ chunk_ctr,
-                                                    uint32_t *__restrict__ out, uint32_t *__restrict__ err) {
-    __shared__ uint16_t J[CR][CC];
-    __shared__ uint32_t Nx[CC];
-    __shared__ int8_t mark[CC];
-    __shared__ uint32_t s_chunk, s_entry, s_prefix;
+                                                    uint32_t *__restrict__ kept_st, uint32_t *__restrict__ max_pub,
+                                                    uint32_t *__restrict__ chunk_ctr, uint32_t *__restrict__ out,
+                                                    uint32_t *__restrict__ err) {
+    extern __shared__ uint32_t chain_lds[];
+    auto J = reinterpret_cast<uint16_t(*)[CC]>(chain_lds);
+    uint32_t *Nx = chain_lds + CR * CC / 2;
+    uint32_t *Ex = Nx + CC;
+    int8_t *mark = reinterpret_cast<int8_t *>(Ex + CC);
+    __shared__ uint32_t s_chunk, s_entry, s_prefix, s_max;
     __shared__ uint32_t lw[CT / WAVE];
-    if (threadIdx.x == 0) s_chunk = atomicAdd(chunk_ctr, 1u);
+    if (threadIdx.x == 0) {
+        s_chunk = atomicAdd(chunk_ctr, 1u);
+        s_max = 0u;
+    }
     __syncthreads();
     const int64_t c = s_chunk;
     const int64_t cs = c * CC;
@@ -238,11 +249,17 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
             }
             Nx[i] = (uint32_t)k;
             J[0][i] = k < ce ? (uint16_t)(k - cs) : OUTL;
+            atomicMax(&s_max, (uint32_t)k);
         } else {
             J[0][i] = OUTL;
         }
     }
     __syncthreads();
+    // the farthest position a next pointer of this chunk reaches bounds where
+    // the chain can enter later chunks: published at once as this chunk's own
+    // value (MX_AGG), later as the running maximum over chunks 0 .. c (MX_PRE)
+    const uint32_t own_max = s_max;
+    if (threadIdx.x == 0) st_agent(&max_pub[c], (c == 0 ? MX_PRE : MX_AGG) | own_max);
     // 2. jump tables J_t = next^(2^t) inside the chunk
     for (int t = 1; t < CR; ++t) {
         for (int i = threadIdx.x; i < CC; i += CT) {
@@ -251,8 +268,56 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
         }
         __syncthreads();
     }
-    // 3. where the chain enters this chunk, where it leaves; publish the exit
+    // 3. where the chain leaves the chunk from every entry position
+    for (int i = threadIdx.x; i < len; i += CT) {
+        int cur = i;
+        for (int t = CR - 1; t >= 0; --t)
+            if (J[t][cur] != OUTL) cur = J[t][cur];
+        Ex[i] = Nx[cur];
+    }
+    // The chain enters this chunk at a position no later than M, the farthest
+    // next pointer of the earlier chunks.  When every entry up to M leaves at
+    // the same position (chains merge after a few nodes), that is the exit
+    // whatever the earlier chunks do: publish it without waiting for them.
+    // Otherwise wait for the previous chunk's exit.
+    if (c > 0 && threadIdx.x < WAVE) {
+        // decoupled look-back over the earlier chunks' maxima, 64 at a time
+        const int lane = threadIdx.x;
+        uint32_t m = 0;
+        int64_t hi = c;   // chunks [0, hi) still to look at
+        while (hi > 0) {
+            const int64_t q = hi - 1 - lane;
+            uint32_t v = MX_PRE;   // lanes past chunk 0: an empty inclusive maximum
+            if (q >= 0) {
+                uint32_t spins = 0;
+                while (((v = ld_agent(&max_pub[q])) & MX_FLAGS) == 0) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(err, 2u);
+                        v = MX_PRE;
+                        break;
+                    }
+                }
+            }
+            const uint64_t pre = __ballot((v & MX_FLAGS) == MX_PRE);
+            const int stop = pre ? __builtin_ctzll(pre) : WAVE;   // nearest inclusive maximum
+            if (lane <= stop) m = max(m, v & ~MX_FLAGS);
+            if (pre) break;
+            hi -= WAVE;
+        }
+        for (int off = WAVE / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, WAVE));
+        if (lane == 0) {
+            st_agent(&max_pub[c], MX_PRE | max(m, own_max));
+            s_max = m;
+        }
+    }
+    __syncthreads();
+    const int64_t M = c > 0 ? (int64_t)s_max : cs;
+    bool same = M < ce;
+    if (same)
+        for (int i = threadIdx.x; i <= (int)(M - cs); i += CT) same = same && Ex[i] == Ex[0];
+    const bool merged = __syncthreads_and(same) != 0;
     if (threadIdx.x == 0) {
+        if (merged) st_agent(&exit_pub[c], PUB | Ex[0]);
         uint32_t X = 0;
         if (c > 0) {
             uint32_t v = 0, spins = 0;
@@ -264,14 +329,7 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
             }
             X = v & ~PUB;
         }
-        uint32_t ex = X;
-        if ((int64_t)X < ce) {
-            int cur = (int)(X - cs);
-            for (int t = CR - 1; t >= 0; --t)
-                if (J[t][cur] != OUTL) cur = J[t][cur];
-            ex = Nx[cur];
-        }
-        st_agent(&exit_pub[c], PUB | ex);
+        if (!merged) st_agent(&exit_pub[c], PUB | ((int64_t)X < ce ? Ex[X - cs] : X));
         s_entry = X;
     }
     for (int i = threadIdx.x; i < CC; i += CT) mark[i] = -1;
@@ -367,7 +425,7 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     constexpr int NP = 6;
     const size_t wn = (size_t)n;
     const int64_t nchunk = (n + CC - 1) / CC;
-    const int64_t npub = NP * (2 * nchunk + 64);   // per pass: exits, survivor counts, chunk counter
+    const int64_t npub = NP * (3 * nchunk + 64);   // per pass: exits, survivor counts, farthest reaches, counter
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -399,6 +457,9 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     uint32_t *pub = reinterpret_cast<uint32_t *>(B + oPub);
     uint32_t *rad = reinterpret_cast<uint32_t *>(B + oRad);
 
+    static const hipError_t lds_attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_filter_chain), hipFuncAttributeMaxDynamicSharedMemorySize, (int)CHAIN_LDS);
+    if (lds_attr != hipSuccess) return hip_fail(lds_attr, "hipFuncSetAttribute(k_filter_chain)", __FILE__, __LINE__);
     const float rf2 = r_filter * r_filter;
     hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, s, rad, (int64_t)64);   // sort error word
     CAPT_LAUNCH_CHECK();
@@ -419,10 +480,10 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     if (e) return e;
     const uint32_t *ord = where ? v1 : v0;
     for (int p = 0; p < NP; ++p) {
-        uint32_t *pp = pub + (size_t)p * (2 * nchunk + 64);
-        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), 0, s, xyz, ord + (size_t)p * wn, n,
+        uint32_t *pp = pub + (size_t)p * (3 * nchunk + 64);
+        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), CHAIN_LDS, s, xyz, ord + (size_t)p * wn, n,
                            live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2, (int)(p == NP - 1), pp,
-                           pp + nchunk, pp + 2 * nchunk, cur, rad);
+                           pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, out_xyz, out_index);
