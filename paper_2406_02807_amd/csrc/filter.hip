@@ -44,35 +44,28 @@ struct FState {
     double scale;
     int64_t mm[2];      // mm[0]: survivors of the last pass (n until it ends)
     unsigned int bad;   // non-finite coordinates
+    unsigned int err;   // copy of the internal wait-bound error word
 };
 
-__global__ void k_fstate_init(FState *st, int64_t n) {
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) {
-            st->lo[a] = INFINITY;
-            st->hi[a] = -INFINITY;
-        }
-        st->mm[0] = n;
-        st->mm[1] = 0;
-        st->bad = 0;
-        st->scale = 0.0;
-    }
+constexpr int BB_BLOCKS = 64;   // partial bounding boxes
+
+// Scratch that must start at zero or one: the publication words of the six
+// chain passes, the sort's error words, the liveness flags before pass 0.
+__global__ void k_finit(uint32_t *__restrict__ pub, int64_t npub, uint32_t *__restrict__ errw,
+                        uint8_t *__restrict__ live, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < npub; i += stride) pub[i] = 0u;
+    for (int64_t i = t; i < 64; i += stride) errw[i] = 0u;
+    for (int64_t i = t; i < n; i += stride) live[i] = 1u;
 }
 
-__device__ __forceinline__ void atomic_min_f(float *a, float v) {
-    // order-preserving integer view of a float (no NaN here)
-    int iv = __float_as_int(v);
-    if (iv >= 0) atomicMin(reinterpret_cast<int *>(a), iv);
-    else atomicMax(reinterpret_cast<unsigned int *>(a), (unsigned int)iv);
-}
-
-__device__ __forceinline__ void atomic_max_f(float *a, float v) {
-    int iv = __float_as_int(v);
-    if (iv >= 0) atomicMax(reinterpret_cast<int *>(a), iv);
-    else atomicMin(reinterpret_cast<unsigned int *>(a), (unsigned int)iv);
-}
-
-__global__ void k_bbox(const float *__restrict__ xyz, int64_t n, FState *st) {
+// Per-block bounding box of the finite coordinates and count of non-finite
+// ones; part[b] = {lo[3], hi[3]}, bad[b].
+__global__ void k_bbox(const float *__restrict__ xyz, int64_t n, float *__restrict__ part,
+                       unsigned int *__restrict__ badp) {
+    __shared__ float sl[TB / WAVE][6];
+    __shared__ unsigned int sb[TB / WAVE];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     unsigned int bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -87,35 +80,68 @@ __global__ void k_bbox(const float *__restrict__ xyz, int64_t n, FState *st) {
             hi[a] = fmaxf(hi[a], v);
         }
     }
-    for (int a = 0; a < 3; ++a) {
-        for (int off = WAVE / 2; off >= 1; off >>= 1) {
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
             lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
             hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
         }
+        bad += (unsigned int)__shfl_xor((int)bad, off, WAVE);
     }
+    const int w = threadIdx.x / WAVE;
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         for (int a = 0; a < 3; ++a) {
-            // the sign of a zero minimum does not change any cell coordinate
-            atomic_min_f(&st->lo[a], lo[a]);
-            atomic_max_f(&st->hi[a], hi[a]);
+            sl[w][a] = lo[a];
+            sl[w][3 + a] = hi[a];
         }
+        sb[w] = bad;
     }
-    if (bad) atomicAdd(&st->bad, bad);
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float v = sl[0][threadIdx.x];
+        for (int i = 1; i < TB / WAVE; ++i) v = threadIdx.x < 3 ? fminf(v, sl[i][threadIdx.x]) : fmaxf(v, sl[i][threadIdx.x]);
+        part[6 * blockIdx.x + threadIdx.x] = v;
+    }
+    if (threadIdx.x == 0) {
+        unsigned int t = 0;
+        for (int i = 0; i < TB / WAVE; ++i) t += sb[i];
+        badp[blockIdx.x] = t;
+    }
 }
 
-__global__ void k_grid(FState *st) {
-    if (threadIdx.x != 0) return;
+// Reduce the partial boxes; set the grid (cell = largest extent / 2^21) and
+// the rest of the state.  One wave.
+__global__ void k_grid(const float *__restrict__ part, const unsigned int *__restrict__ badp, int nb, int64_t n,
+                       FState *st) {
+    const int lane = threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    unsigned int bad = 0;
+    if (lane < nb) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = part[6 * lane + a];
+            hi[a] = part[6 * lane + 3 + a];
+        }
+        bad = badp[lane];
+    }
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
+        }
+        bad += (unsigned int)__shfl_xor((int)bad, off, WAVE);
+    }
+    if (lane != 0) return;
     double E = 0.0;
     for (int a = 0; a < 3; ++a) {
-        double e = __dsub_rn((double)st->hi[a], (double)st->lo[a]);
+        st->lo[a] = lo[a];   // the sign of a zero minimum does not change any cell coordinate
+        st->hi[a] = hi[a];
+        const double e = __dsub_rn((double)hi[a], (double)lo[a]);
         if (e > E) E = e;
     }
     st->scale = E > 0.0 ? 2097152.0 / E : 0.0;
-}
-
-__global__ void k_clear_u32(uint32_t *__restrict__ p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    st->mm[0] = n;
+    st->mm[1] = 0;
+    st->bad = bad;
+    st->err = 0;
 }
 
 // Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
@@ -152,11 +178,6 @@ __global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState
         keys[p * n + j] = (sp[c_perm[p][0]] << 2) | (sp[c_perm[p][1]] << 1) | sp[c_perm[p][2]];
         vals[p * n + j] = (uint32_t)j;
     }
-}
-
-__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
 }
 
 constexpr int CT = 256;              // threads of the chain kernel
@@ -403,9 +424,10 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
 }
 
 __global__ void k_output(const float *__restrict__ xyz, const uint32_t *__restrict__ cur, int64_t n,
-                         const FState *__restrict__ st, float *__restrict__ out_xyz,
+                         FState *__restrict__ st, const uint32_t *__restrict__ errw, float *__restrict__ out_xyz,
                          int32_t *__restrict__ out_index) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) st->err = *errw;   // one copy to the host carries everything
     if (j >= n || j >= st->mm[0]) return;
     const uint32_t id = cur[j];
     out_xyz[3 * j] = xyz[3 * (int64_t)id];
@@ -441,6 +463,7 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     const size_t oLive = take(wn * (NP + 1));
     const size_t oPub = take(sizeof(uint32_t) * (size_t)npub);
     const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words_seg(NP, n));
+    const size_t oBB = take(sizeof(float) * 6 * BB_BLOCKS + sizeof(unsigned int) * BB_BLOCKS);
     Scratch sc;
     if (!sc.alloc(off, s)) {
         set_error("device allocation of %zu filter scratch bytes failed", off);
@@ -456,22 +479,20 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     uint8_t *live = reinterpret_cast<uint8_t *>(B + oLive);
     uint32_t *pub = reinterpret_cast<uint32_t *>(B + oPub);
     uint32_t *rad = reinterpret_cast<uint32_t *>(B + oRad);
+    float *bbp = reinterpret_cast<float *>(B + oBB);
+    unsigned int *bbbad = reinterpret_cast<unsigned int *>(bbp + 6 * BB_BLOCKS);
 
     static const hipError_t lds_attr = hipFuncSetAttribute(
         reinterpret_cast<const void *>(k_filter_chain), hipFuncAttributeMaxDynamicSharedMemorySize, (int)CHAIN_LDS);
     if (lds_attr != hipSuccess) return hip_fail(lds_attr, "hipFuncSetAttribute(k_filter_chain)", __FILE__, __LINE__);
     const float rf2 = r_filter * r_filter;
-    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, s, rad, (int64_t)64);   // sort error word
+    hipLaunchKernelGGL(k_finit, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(npub, n) / TB + 1, 1024)), dim3(TB),
+                       0, s, pub, npub, rad, live, n);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)((npub + 255) / 256)), dim3(256), 0, s, pub, npub);
+    const int nbb = (int)std::min<int64_t>(nblk(n), BB_BLOCKS);
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)nbb), dim3(TB), 0, s, xyz, n, bbp, bbbad);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n)), dim3(TB), 0, s, live, n, (uint8_t)1);
-    CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fstate_init, dim3(1), dim3(64), 0, s, st, n);
-    CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bbox, dim3(std::min<unsigned>(nblk(n), 16u)), dim3(TB), 0, s, xyz, n, st);
-    CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(WAVE), 0, s, bbp, bbbad, nbb, n, st);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_morton6, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, st, k0, v0);
     CAPT_LAUNCH_CHECK();
@@ -486,15 +507,13 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
                            pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, out_xyz, out_index);
+    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index);
     CAPT_LAUNCH_CHECK();
     FState h;
-    uint32_t sort_err = 0;
     CAPT_HIP(hipMemcpyAsync(&h, st, sizeof(FState), hipMemcpyDeviceToHost, s));
-    CAPT_HIP(hipMemcpyAsync(&sort_err, rad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     CAPT_HIP(hipStreamSynchronize(s));
-    if (sort_err) {
-        set_error("internal: a look-back wait bound was exceeded in the filter (code %u)", sort_err);
+    if (h.err) {
+        set_error("internal: a look-back wait bound was exceeded in the filter (code %u)", h.err);
         return CAPT_EHIP;
     }
     if (h.bad) {

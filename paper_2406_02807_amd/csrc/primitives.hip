@@ -306,7 +306,7 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
                        tmp + 64, words - 64, 0u);
     CAPT_LAUNCH_CHECK();
     const size_t hl = sizeof(uint32_t) * (size_t)nseg * npass * 256;
-    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(TB), hl, s, k0, len, nseg,
+    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 64)), dim3(TB), hl, s, k0, len, nseg,
                        npass, ghist);
     CAPT_LAUNCH_CHECK();
     K *ki = k0, *ko = k1;
