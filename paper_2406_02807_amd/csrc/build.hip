@@ -30,6 +30,7 @@ namespace {
 constexpr int TB = 256;
 constexpr int LMAX = 2048;   // subtree size finished in LDS
 constexpr int LMAX_LOG2 = 11;
+constexpr int LTB = 1024;    // threads of the LDS levels kernel
 constexpr int GTILE = 2048;  // tile of the global partition passes
 
 __device__ __forceinline__ uint32_t ord_key(float v) {
@@ -206,7 +207,7 @@ __global__ void k_inverse(const uint32_t *__restrict__ L, int64_t N, uint32_t *_
 // The remaining levels d0 .. D-1 of one subtree of S0 = N >> d0 <= LMAX
 // points, in LDS.  Lists hold local indices (positions in the axis-0 list of
 // the subtree).
-__global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict__ L0,
+__global__ void __launch_bounds__(LTB) k_local_levels(const uint32_t *__restrict__ L0,
                                                      const uint32_t *__restrict__ L1,
                                                      const uint32_t *__restrict__ L2,
                                                      const uint32_t *__restrict__ inv,
@@ -220,10 +221,10 @@ __global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict_
     __shared__ uint16_t tmp[LMAX];
     __shared__ uint16_t escan[LMAX];
     __shared__ uint8_t flag[LMAX];
-    __shared__ uint32_t lw[TB / WAVE];
+    __shared__ uint32_t lw[LTB / WAVE];
     const int S0 = (int)(N >> d0);
     const int64_t seg = (int64_t)blockIdx.x * S0;
-    for (int k = threadIdx.x; k < S0; k += TB) {
+    for (int k = threadIdx.x; k < S0; k += LTB) {
         uint32_t id = L0[seg + k];
         ids[k] = id;
         for (int a = 0; a < 3; ++a) cx[a][k] = coord_of(xyz, n, id, a);
@@ -235,13 +236,13 @@ __global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict_
     for (int d = d0; d < D; ++d) {
         const int s = (int)(N >> d), h = s >> 1, a = d % 3;
         const int64_t node0 = ((int64_t)1 << d) - 1 + (int64_t)blockIdx.x * (S0 / s);
-        for (int j = threadIdx.x; j < S0 / s; j += TB) T[node0 + j] = cx[a][lst[a][j * s + h - 1]];
-        for (int k = threadIdx.x; k < S0; k += TB) flag[lst[a][k]] = (uint8_t)((k & (s - 1)) < h);
+        for (int j = threadIdx.x; j < S0 / s; j += LTB) T[node0 + j] = cx[a][lst[a][j * s + h - 1]];
+        for (int k = threadIdx.x; k < S0; k += LTB) flag[lst[a][k]] = (uint8_t)((k & (s - 1)) < h);
         __syncthreads();
         for (int b = 1; b <= 2; ++b) {
             uint16_t *lb = lst[(a + b) % 3];
             // exclusive scan of flags over the S0 positions (8 per thread)
-            const int per = (S0 + TB - 1) / TB;
+            const int per = (S0 + LTB - 1) / LTB;
             const int k0 = threadIdx.x * per;
             uint32_t c = 0;
             for (int i = 0; i < per; ++i) {
@@ -258,7 +259,7 @@ __global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict_
                 }
             }
             __syncthreads();
-            for (int k = threadIdx.x; k < S0; k += TB) {
+            for (int k = threadIdx.x; k < S0; k += LTB) {
                 const int sg = k & ~(s - 1);
                 const int lc = (int)escan[k] - (int)escan[sg];
                 const uint16_t v = lb[k];
@@ -266,11 +267,11 @@ __global__ void __launch_bounds__(TB) k_local_levels(const uint32_t *__restrict_
                 tmp[np] = v;
             }
             __syncthreads();
-            for (int k = threadIdx.x; k < S0; k += TB) lb[k] = tmp[k];
+            for (int k = threadIdx.x; k < S0; k += LTB) lb[k] = tmp[k];
             __syncthreads();
         }
     }
-    for (int k = threadIdx.x; k < S0; k += TB) rep[seg + k] = (int32_t)ids[lst[0][k]];
+    for (int k = threadIdx.x; k < S0; k += LTB) rep[seg + k] = (int32_t)ids[lst[0][k]];
 }
 
 // Leaf cells from the split values of the ancestors (Alg. 1: the left child
@@ -382,7 +383,7 @@ __global__ void k_grid_setup(const float *__restrict__ bb, double R, int64_t cap
         g.origin[a] = g.lo[a];
         ext = fmax(ext, g.hi[a] - g.lo[a]);
     }
-    double step = R;
+    double step = R * 0.5;   // bins of half the reach: fewer candidates per leaf
     if (ext / step > 1000.0) step = ext / 1000.0;
     int64_t total = 0;
     for (int it = 0; it < 64; ++it) {
@@ -767,7 +768,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     }
     hipLaunchKernelGGL(k_inverse, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], N, inv);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(TB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]],
+    hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(LTB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]],
                        inv, xyz, n, N, D, d, T, C.rep);
     CAPT_LAUNCH_CHECK();
 
@@ -780,7 +781,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
                        C.pruned_flag, W.totals);
     CAPT_LAUNCH_CHECK();
 
-    // 4. grid of the points: bins of side >= R, points sorted by bin
+    // 4. grid of the points: bins of side >= R / 2, points sorted by bin
     const double R = (double)r_max * (1.0 + 0x1p-20);
     hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bb);
     CAPT_LAUNCH_CHECK();
