@@ -31,6 +31,7 @@ constexpr int TB = 256;
 constexpr int LMAX = 2048;   // subtree size finished in LDS
 constexpr int LMAX_LOG2 = 11;
 constexpr int LTB = 1024;    // threads of the LDS levels kernel
+constexpr int AU = 2;        // 64-candidate steps in flight in the affordance kernels
 constexpr int GTILE = 2048;  // tile of the global partition passes
 
 __device__ __forceinline__ uint32_t ord_key(float v) {
@@ -432,12 +433,15 @@ __global__ void k_grid_gather(const float *__restrict__ xyz, const uint32_t *__r
     sz[k] = xyz[3 * id + 2];
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_b(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, WAVE);
-        if (lane >= d) v += t;
-    }
+// Inclusive scan over the 64 lanes with DPP adds (row shifts, then the row
+// totals through row_bcast:15 and row_bcast:31).
+__device__ __forceinline__ uint32_t wave_incl_scan_b(uint32_t v, int) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
     return v;
 }
 
@@ -524,44 +528,55 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                     s = A.cstart[row + b0[0]];
                     e = A.cstart[row + b1[0] + 1];
                 }
-                uint32_t rem = e - s, pos = s;
-                while (true) {
-                    const uint32_t incl = wave_incl_scan_b(rem, lane);
-                    const uint32_t excl = incl - rem;
-                    const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-                    if (total == 0) break;
-                    int o = 0;
+                // the rows' candidates as one flattened list, AU steps of 64
+                // in flight (all loads first, then tests and emits in order)
+                const uint32_t rem = e - s;
+                const uint32_t incl = wave_incl_scan_b(rem, lane);
+                const uint32_t excl = incl - rem;
+                const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+                const uint32_t base_l = s - excl;   // sorted index of list slot t of this row = base_l + t
+                for (uint32_t k0 = 0; k0 < total; k0 += AU * WAVE) {
+                    float x[AU], y[AU], z[AU];
+                    int32_t id[AU];
+                    bool in[AU];
 #pragma unroll
-                    for (int step = 32; step >= 1; step >>= 1) {
-                        const uint32_t ev = __shfl(excl, o + step, WAVE);
-                        if (ev <= (uint32_t)lane) o += step;
-                    }
-                    const uint32_t base = __shfl(pos - excl, o, WAVE);
-                    bool ok = false;
-                    float x = 0.f, y = 0.f, z = 0.f;
-                    int32_t id = -1;
-                    if ((uint32_t)lane < total) {
-                        const uint32_t k = base + (uint32_t)lane;
-                        x = A.sx[k];
-                        y = A.sy[k];
-                        z = A.sz[k];
-                        id = (int32_t)A.sid[k];
-                        const double pp[3] = {(double)x, (double)y, (double)z};
-                        double d2 = 0.0;
+                    for (int u = 0; u < AU; ++u) {
+                        const uint32_t slot = k0 + (uint32_t)(u * WAVE + lane);
+                        in[u] = slot < total;
+                        int o = 0;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const double below = dsub(cl[a], pp[a]);
-                            const double above = dsub(pp[a], ch[a]);
-                            double gg = below > above ? below : above;
-                            if (gg < 0.0) gg = 0.0;
-                            d2 = dadd(d2, dmul(gg, gg));
+                        for (int step = 32; step >= 1; step >>= 1) {
+                            const uint32_t ev = __shfl(excl, o + step, WAVE);
+                            if (ev <= slot) o += step;
                         }
-                        ok = d2 <= A.R2;
+                        const uint32_t k = __shfl(base_l, o, WAVE) + slot;
+                        x[u] = y[u] = z[u] = 0.f;
+                        id[u] = -1;
+                        if (in[u]) {
+                            x[u] = A.sx[k];
+                            y[u] = A.sy[k];
+                            z[u] = A.sz[k];
+                            if (FILL) id[u] = (int32_t)A.sid[k];
+                        }
                     }
-                    emit(ok, x, y, z, id);
-                    const uint32_t take = excl >= WAVE ? 0u : min(rem, (uint32_t)WAVE - excl);
-                    rem -= take;
-                    pos += take;
+#pragma unroll
+                    for (int u = 0; u < AU; ++u) {
+                        bool ok = false;
+                        if (in[u]) {
+                            const double pp[3] = {(double)x[u], (double)y[u], (double)z[u]};
+                            double d2 = 0.0;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const double below = dsub(cl[a], pp[a]);
+                                const double above = dsub(pp[a], ch[a]);
+                                double gg = below > above ? below : above;
+                                if (gg < 0.0) gg = 0.0;
+                                d2 = dadd(d2, dmul(gg, gg));
+                            }
+                            ok = d2 <= A.R2;
+                        }
+                        emit(ok, x[u], y[u], z[u], id[u]);
+                    }
                 }
             }
         }
