@@ -369,3 +369,92 @@ def test_autotuned_shapes_give_identical_answers(capt, orc):
         assert np.array_equal(got, orc.brute_f32(pts, sph, 60))
     finally:
         capt.capt_set_tuning(**before)
+
+
+def test_full_size_room_1e8_spheres(capt, orc):
+    """Room scene at full size: 1.2M points filtered at 5 mm, 10^8 single-sphere
+    queries.  Filter against the oracle exactly; answers against the oracle on a
+    sample and against the GPU brute force on a larger sample."""
+    w = synth.workload(5)
+    _say(f"case: full room {len(w.cloud)} points, {len(w.spheres)} spheres")
+    xyz = dev(w.cloud)
+    fx, fidx = capt.capt_filter(xyz, w.r_filter)
+    keep, _ = orc.filter(w.cloud, w.r_filter)
+    assert np.array_equal(fidx.cpu().numpy(), keep)
+    pts = w.cloud[keep]
+    f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+    info = f.info()
+    _say(f"  built n={info['n']} D={info['D']} set entries={info['set_total']}")
+    sph = dev(w.spheres)
+    got = capt.capt_collides(f, sph, 1)
+    f.close()
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(len(w.spheres), 20_000, replace=False))
+    assert np.array_equal(got[torch.from_numpy(idx).cuda()].cpu().numpy(), orc.brute_f32(pts, w.spheres[idx]))
+    idx2 = torch.from_numpy(np.sort(rng.choice(len(w.spheres), 200_000, replace=False))).cuda()
+    br = capt.capt_bruteforce_collides(fx.contiguous(), sph[idx2].contiguous(), 1)
+    assert torch.equal(got[idx2], br)
+    rate = got.float().mean().item()
+    assert 0.2 < rate < 0.9
+
+
+def test_full_size_clearance_1M(capt, orc):
+    """Clearance workload at full size: every clearance and gradient against its
+    witness in float64, a sample against the oracle's exact minimum."""
+    w = synth.workload(4)
+    _say(f"case: full clearance {len(w.spheres)} spheres")
+    keep, _ = orc.filter(w.cloud, w.r_filter)
+    pts = w.cloud[keep]
+    f = capt.capt_build(dev(pts), 0.0, w.r_max)
+    s = dev(w.spheres).requires_grad_(True)
+    clr, wit = capt.clearance(f, s)
+    clr.sum().backward()
+    P = torch.from_numpy(pts.astype(np.float64)).cuda()
+    x = s.detach().double()
+    wl = wit.long()
+    has = wl >= 0
+    d = torch.full_like(clr, w.r_max, dtype=torch.float64)
+    diff = x[has, :3] - P[wl[has]]
+    d[has] = diff.norm(dim=1)
+    # every clearance equals the distance to its witness (clamped at r_max) minus r
+    ref = torch.clamp(d, max=w.r_max) - x[:, 3]
+    assert (torch.abs(clr.double() - ref) <= 1e-4 * torch.clamp(torch.abs(ref), min=w.r_max)).all()
+    # the gradient of sum(clr): unit vector from the witness, -1 for the radius
+    g = s.grad.double()
+    gref = torch.zeros_like(g)
+    inside = has & (d > 0)   # a witness within r_max; zero distance has no direction
+    gref[inside, :3] = (x[inside, :3] - P[wl[inside]]) / d[inside, None]
+    gref[:, 3] = -1.0
+    assert (torch.linalg.norm(g - gref, dim=1) <= 1e-4 * torch.linalg.norm(gref, dim=1) + 1e-6).all()
+    # a sample against the exact minimum over all points
+    rng = np.random.default_rng(4)
+    idx = np.sort(rng.choice(len(w.spheres), 3000, replace=False))
+    clr_o, wit_o, _ = orc.clearance_f64(pts, w.spheres[idx], w.r_max)
+    c = clr.detach().cpu().numpy()[idx].astype(np.float64)
+    assert (np.abs(c - clr_o) <= 1e-4 * np.maximum(np.abs(clr_o), w.r_max)).all()
+
+
+def test_full_size_batched_64_clouds(capt, orc):
+    """Batched workload at full size: 64 clouds, ragged query ranges, one graph
+    launch; every answer against the GPU brute force, a sample against the
+    oracle."""
+    w = synth.workload(3)
+    cloud_off = np.concatenate([[0], np.cumsum([len(c) for c in w.cloud])])
+    query_off = np.concatenate([[0], np.cumsum([len(s) for s in w.spheres])])
+    _say(f"case: full batched {len(w.cloud)} clouds, {query_off[-1]} spheres")
+    xyz = dev(np.concatenate(w.cloud))
+    sph = dev(np.concatenate(w.spheres))
+    f = capt.capt_build(xyz, w.r_min, w.r_max, cloud_off=cloud_off)
+    got = capt.capt_collides(f, sph, 60, query_off=query_off)
+    again = capt.capt_collides(f, sph, 60, query_off=query_off)   # graph replay
+    br = capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off, query_off=query_off)
+    f.close()
+    assert torch.equal(got, br) and torch.equal(again, got)
+    got = got.cpu().numpy()
+    rng = np.random.default_rng(3)
+    for c in rng.choice(len(w.cloud), 4, replace=False):
+        nc = len(w.spheres[c]) // 60
+        pick = np.sort(rng.choice(nc, min(nc, 300), replace=False))
+        sub = w.spheres[c].reshape(-1, 60, 4)[pick].reshape(-1, 4)
+        want = orc.brute_f32(w.cloud[c], sub, 60)
+        assert np.array_equal(got[query_off[c] // 60 + pick], want), c
