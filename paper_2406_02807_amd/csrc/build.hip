@@ -2,23 +2,27 @@
 //
 // Alg. 1 recurses with a cell c and an afforded set z; on a GPU the same tree
 // is produced level-synchronously:
-//  1. presort: three stable sorts of the padded point ids by (coordinate,
-//     id), one per axis (pad points sit at +inf);
+//  1. presort: the padded point ids sorted by (coordinate, id) on each axis,
+//     the three lists in one segmented radix sort (pad points sit at +inf);
 //  2. splits: at depth d every node is a contiguous, aligned segment of the
 //     three lists.  The node's split value is the coordinate of the last
 //     element of the lower half of the list sorted on axis d mod 3 (the lower
 //     median under (coordinate, id)); the other two lists are stably
 //     partitioned by "goes left", which keeps every half sorted on every
-//     axis.  Levels whose segments exceed one tile run as global passes; the
-//     remaining levels of each 2048-point subtree run in LDS in one launch.
+//     axis.  Levels whose segments exceed LMAX run as one kernel each (the
+//     partition finds offsets by decoupled look-back and already emits the
+//     next level's split values and flags); the remaining levels of each
+//     LMAX-point subtree run in LDS in one launch.
 //  3. leaf cells from the split values of each leaf's ancestors;
 //  4. affordance sets: instead of carrying z down the recursion, each leaf
-//     collects {p : dist(p, cell) <= R} directly, by a near-first walk of the
-//     tree that skips subtrees whose point bounding box is farther than R.
-//     Both constructions give the same set (Lemma 1, case 1); the float64
-//     distance test is monotone under cell shrinking, so they agree exactly.
-//     A count pass sizes the sets, a scan places them (each set starts at a
-//     multiple of SET_ALIGN entries), a fill pass writes them SoA.
+//     collects {p : dist(p, cell) <= R} directly from a uniform grid of the
+//     points (bins of side R / 2, points sorted by bin), scanning the exact
+//     bin range around its cell.  Both constructions give the same set
+//     (Lemma 1, case 1); the float64 distance test is monotone under cell
+//     shrinking, so they agree exactly.  A count pass sizes the sets, a scan
+//     places them (each set starts at a multiple of SET_ALIGN entries), a fill
+//     pass writes them SoA with each leaf's AABB, and a last pass writes the
+//     box of every 16-entry chunk.
 #include <cmath>
 
 #include "capt_internal.h"

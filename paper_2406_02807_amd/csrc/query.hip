@@ -1,22 +1,27 @@
 // Collision queries against CAPTs (Alg. 3, Sec. IV-D) on wave64 CDNA4.
 //
-// Mapping.  One wavefront owns a tile of up to 64 spheres: one sphere per lane
-// (64 / g whole configurations of g spheres, or a 64-sphere slice of a larger
-// configuration).  Each lane descends the tree branch-free (the top levels of
-// T sit in LDS) and tests its leaf's AABB.  The surviving spheres' affordance
-// sets are then scanned as ONE flattened list of (sphere, set entry) pairs:
-// an exclusive wave scan of the remaining set lengths places every sphere's
-// pairs, each of the 64 lanes takes one pair per step (binary search over the
-// scan finds its sphere), loads the entry from the SoA set arrays - runs of
-// consecutive lanes read consecutive addresses of one set - and tests it.  A
-// ballot after every step marks the configurations that were hit; their
-// spheres drop out of the next scan (early exit, Sec. I and IV-D).  This keeps
-// every lane busy whatever the mix of set sizes, which the paper's CPU layout
-// (lanes across one set at a time) does not.
+// Mapping.  A wavefront holds up to 64 spheres, one per lane: 64 / g whole
+// configurations of g <= 16 spheres (k_collide_cloud), or four 16-lane slots,
+// each holding the next 16 spheres of one larger configuration
+// (k_collide_slots; a slot moves on to the configuration's next 16 spheres
+// only if the current ones missed, so a configuration stops at its first
+// colliding piece, as Alg. 3's sequential loop stops at its first colliding
+// sphere).  Each lane descends the tree branch-free (the top levels of T sit
+// in LDS) and tests its leaf's AABB.  The surviving spheres' sets are stored
+// as 16-entry chunks with a float32 box each and are scanned in two levels:
+// the (sphere, chunk) pairs of all surviving spheres form one flattened list
+// (an exclusive wave scan of the chunk counts places each sphere's pairs;
+// every lane takes one pair per step), chunks whose box lies within reach go
+// to a per-wave ring in LDS, and the entries of four ring chunks are tested
+// per 64-lane step.  A ballot after every step marks the configurations that
+// were hit; their spheres drop out (early exit, Sec. I and IV-D).  Every lane
+// stays busy whatever the mix of set sizes, which the paper's CPU layout
+// (lanes across one set at a time) does not give.
 //
-// Kernels: k_collide_cloud (one cloud, persistent, static tile stride),
-// k_collide_batched (many clouds, persistent, tiles popped from a queue sorted
-// by descending cost), k_brute (baseline), k_query_stats (work accounting).
+// Kernels: k_collide_cloud / k_collide_slots (one cloud, persistent, per-XCD
+// work queues), k_collide_batched (many clouds, persistent, tiles popped from a
+// queue sorted by descending cost), k_brute (baseline), k_query_stats and
+// k_chunk_stats (work accounting).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
