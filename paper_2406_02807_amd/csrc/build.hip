@@ -60,23 +60,74 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_count_nonfinite(const float *__restrict__ xyz, int64_t cnt, uint32_t *bad) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    uint32_t b = 0;
-    for (; i < cnt; i += stride) b += !isfinite(xyz[i]);
-    if (b) atomicAdd(bad, b);
+
+// Zero the phase's counters and bins in one launch.
+__global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__restrict__ errw,
+                        uint32_t *__restrict__ cstart, int64_t ncs) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 4) totals[t] = 0ull;
+    if (t < 64) errw[t] = 0u;
+    for (int64_t i = t; i < ncs; i += stride) cstart[i] = 0u;
 }
 
-// Sort keys of all three axes: segment a of keys / vals holds axis a.
-__global__ void k_presort_keys(const float *__restrict__ xyz, int64_t n, int64_t N, uint32_t *__restrict__ keys,
-                               uint32_t *__restrict__ vals) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// One read of the cloud: sort keys of all three axes (segment a of keys /
+// vals holds axis a), the forest's copy of the points, the count of
+// non-finite coordinates and the bounding box of the finite ones, both as
+// per-block partials (bbp[6 b ..], badp[b]).
+__global__ void __launch_bounds__(TB) k_presort_keys(const float *__restrict__ xyz, int64_t n, int64_t N,
+                                                     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                     float *__restrict__ pts, float *__restrict__ bbp,
+                                                     uint32_t *__restrict__ badp) {
+    __shared__ float sl[TB / WAVE][6];
+    __shared__ uint32_t sb[TB / WAVE];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t bad = 0;
+    if (j < N) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        keys[a * N + j] = j < n ? ord_key(xyz[3 * j + a]) : 0xFFFFFFFFu;
-        vals[a * N + j] = (uint32_t)j;
+        for (int a = 0; a < 3; ++a) {
+            float v = INFINITY;
+            if (j < n) {
+                v = xyz[3 * j + a];
+                pts[3 * j + a] = v;
+                if (isfinite(v)) {
+                    lo[a] = v;
+                    hi[a] = v;
+                } else {
+                    ++bad;
+                }
+            }
+            keys[a * N + j] = j < n ? ord_key(v) : 0xFFFFFFFFu;
+            vals[a * N + j] = (uint32_t)j;
+        }
+    }
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
+        }
+        bad += (uint32_t)__shfl_xor((int)bad, off, WAVE);
+    }
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            sl[w][a] = lo[a];
+            sl[w][3 + a] = hi[a];
+        }
+        sb[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float v = sl[0][threadIdx.x];
+        for (int i = 1; i < TB / WAVE; ++i) v = threadIdx.x < 3 ? fminf(v, sl[i][threadIdx.x]) : fmaxf(v, sl[i][threadIdx.x]);
+        bbp[6 * blockIdx.x + threadIdx.x] = v;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < TB / WAVE; ++i) t += sb[i];
+        badp[blockIdx.x] = t;
     }
 }
 
@@ -281,51 +332,58 @@ __global__ void __launch_bounds__(LTB) k_local_levels(const uint32_t *__restrict
 
 // Leaf cells from the split values of the ancestors (Alg. 1: the left child
 // takes hi = T_i, the right child lo = T_i on the node's axis).
-__global__ void k_leaf_cells(const float *__restrict__ T, int64_t N, int D,
-                             float *__restrict__ cells) {
-    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= N) return;
-    float c[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
-    int64_t i = 0;
-    for (int d = 0; d < D; ++d) {
-        int a = d % 3;
-        int bit = (int)((l >> (D - 1 - d)) & 1);
-        if (bit) c[a] = T[i];
-        else c[3 + a] = T[i];
-        i = 2 * i + 1 + bit;
-    }
-    for (int k = 0; k < 6; ++k) cells[6 * l + k] = c[k];
-}
-
 // float64 helpers, every operation rounded on its own
 __device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
 __device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
 
-// r_min pruning of one leaf (Sec. IV-B): bounded cell whose farthest corner is
-// within r_min of the representative (float64, margin 2^-18).
-__global__ void k_prune(const float *__restrict__ cells, const int32_t *__restrict__ rep,
-                        const float *__restrict__ xyz, int64_t n, int64_t N, int prune, double thr,
-                        uint8_t *__restrict__ pruned, unsigned long long *__restrict__ totals) {
+// Cell of every leaf from its ancestors' split values (upper bound from a
+// left descent, lower bound from a right one, +-inf where unbounded), then the
+// r_min pruning of the leaf (Sec. IV-B): a bounded cell whose farthest corner
+// is within r_min of the representative (float64, margin 2^-18).  Pruned
+// leaves are counted per block (prp[b]).
+__global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T, int64_t N, int D,
+                                                    float *__restrict__ cells, const int32_t *__restrict__ rep,
+                                                    const float *__restrict__ xyz, int64_t n, int prune, double thr,
+                                                    uint8_t *__restrict__ pruned, uint32_t *__restrict__ prp) {
+    __shared__ uint32_t sc[TB / WAVE];
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= N) return;
-    const int64_t id = rep[l];
-    bool pr = prune && id < n;
-    const float *c = cells + 6 * l;
-    for (int k = 0; k < 6 && pr; ++k) pr = isfinite(c[k]);
-    if (pr) {
-        double far2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double t = (double)xyz[3 * id + a];
-            const double lo = dsub(t, (double)c[a]);
-            const double hi = dsub((double)c[3 + a], t);
-            const double l2 = dmul(lo, lo), h2 = dmul(hi, hi);
-            far2 = dadd(far2, l2 > h2 ? l2 : h2);
+    bool pr = false;
+    if (l < N) {
+        float c[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+        int64_t i = 0;
+        for (int d = 0; d < D; ++d) {
+            const int a = d % 3;
+            const int bit = (int)((l >> (D - 1 - d)) & 1);
+            if (bit) c[a] = T[i];
+            else c[3 + a] = T[i];
+            i = 2 * i + 1 + bit;
         }
-        pr = far2 <= thr;
+        for (int k = 0; k < 6; ++k) cells[6 * l + k] = c[k];
+        const int64_t id = rep[l];
+        pr = prune && id < n;
+        for (int k = 0; k < 6 && pr; ++k) pr = isfinite(c[k]);
+        if (pr) {
+            double far2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double t = (double)xyz[3 * id + a];
+                const double lo = dsub(t, (double)c[a]);
+                const double hi = dsub((double)c[3 + a], t);
+                const double l2 = dmul(lo, lo), h2 = dmul(hi, hi);
+                far2 = dadd(far2, l2 > h2 ? l2 : h2);
+            }
+            pr = far2 <= thr;
+        }
+        pruned[l] = (uint8_t)pr;
     }
-    pruned[l] = (uint8_t)pr;
-    if (pr) atomicAdd(&totals[2], 1ull);
+    const uint32_t cnt = (uint32_t)__popcll(__ballot(pr));
+    if ((threadIdx.x & (WAVE - 1)) == 0) sc[threadIdx.x / WAVE] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < TB / WAVE; ++i) t += sc[i];
+        prp[blockIdx.x] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -345,45 +403,60 @@ struct Grid {
     int64_t ncells;
 };
 
-__global__ void k_grid_bbox(const float *__restrict__ xyz, int64_t n, float *__restrict__ bb) {
+
+
+// Reduce the bounding-box partials (one block), store the non-finite count in
+// totals[3], and lay the grid over the box.
+__global__ void __launch_bounds__(TB) k_grid_setup(const float *__restrict__ bbp, const uint32_t *__restrict__ badp,
+                                                   int64_t nb, double R, int64_t cap, Grid *G,
+                                                   unsigned long long *__restrict__ totals) {
+    __shared__ float sl[TB / WAVE][6];
+    __shared__ uint32_t sb[TB / WAVE];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+    uint32_t bad = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += TB) {
         for (int a = 0; a < 3; ++a) {
-            const float v = xyz[3 * j + a];
-            lo[a] = fminf(lo[a], v);
-            hi[a] = fmaxf(hi[a], v);
+            lo[a] = fminf(lo[a], bbp[6 * b + a]);
+            hi[a] = fmaxf(hi[a], bbp[6 * b + 3 + a]);
         }
-    for (int a = 0; a < 3; ++a)
-        for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        bad += badp[b];
+    }
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
             lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
             hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
         }
-    if ((threadIdx.x & (WAVE - 1)) == 0)
-        for (int a = 0; a < 3; ++a) {
-            // order-preserving integer views (finite values; signed zeros tie)
-            const int il = __float_as_int(lo[a]), ih = __float_as_int(hi[a]);
-            if (il >= 0) atomicMin(reinterpret_cast<int *>(&bb[a]), il);
-            else atomicMax(reinterpret_cast<unsigned int *>(&bb[a]), (unsigned int)il);
-            if (ih >= 0) atomicMax(reinterpret_cast<int *>(&bb[3 + a]), ih);
-            else atomicMin(reinterpret_cast<unsigned int *>(&bb[3 + a]), (unsigned int)ih);
-        }
-}
-
-__global__ void k_grid_init(float *bb) {
-    if (threadIdx.x < 3) {
-        bb[threadIdx.x] = INFINITY;
-        bb[3 + threadIdx.x] = -INFINITY;
+        bad += (uint32_t)__shfl_xor((int)bad, off, WAVE);
     }
-}
-
-__global__ void k_grid_setup(const float *__restrict__ bb, double R, int64_t cap, Grid *G) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            sl[w][a] = lo[a];
+            sl[w][3 + a] = hi[a];
+        }
+        sb[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < TB / WAVE; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(sl[0][a], sl[i][a]);
+            sl[0][a] = lo[a];
+            hi[a] = fmaxf(sl[0][3 + a], sl[i][3 + a]);
+            sl[0][3 + a] = hi[a];
+        }
+        sb[0] += sb[i];
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = sl[0][a];
+        hi[a] = sl[0][3 + a];
+    }
+    totals[3] = sb[0];
     Grid g;
     double ext = 0.0;
     for (int a = 0; a < 3; ++a) {
-        g.lo[a] = (double)bb[a];
-        g.hi[a] = (double)bb[3 + a];
+        g.lo[a] = (double)lo[a];
+        g.hi[a] = (double)hi[a];
         if (!(g.lo[a] <= g.hi[a]) || !isfinite(g.lo[a]) || !isfinite(g.hi[a])) g.lo[a] = g.hi[a] = 0.0;   // empty cloud
         g.origin[a] = g.lo[a];
         ext = fmax(ext, g.hi[a] - g.lo[a]);
@@ -614,16 +687,68 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
     }
 }
 
-__global__ void k_pad_counts(const uint32_t *__restrict__ cnt, int64_t N, uint32_t *__restrict__ out,
-                             unsigned long long *__restrict__ totals) {
-    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= N) return;
-    uint32_t c = cnt[l];
-    uint32_t p = c ? ((c + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
-    out[l] = p;
-    if (c) {
-        atomicAdd(&totals[0], (unsigned long long)c);
-        atomicAdd(&totals[1], (unsigned long long)p);
+// Padded set sizes, and per-block sums of the set sizes and padded sizes
+// (pp[2 b], pp[2 b + 1]).
+__global__ void __launch_bounds__(TB) k_pad_counts(const uint32_t *__restrict__ cnt, int64_t N,
+                                                   uint32_t *__restrict__ out, unsigned long long *__restrict__ pp) {
+    __shared__ unsigned long long sc[TB / WAVE][2];
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c = 0, p = 0;
+    if (l < N) {
+        const uint32_t v = cnt[l];
+        const uint32_t q = v ? ((v + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+        out[l] = q;
+        c = v;
+        p = q;
+    }
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        c += __shfl_xor(c, off, WAVE);
+        p += __shfl_xor(p, off, WAVE);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        sc[threadIdx.x / WAVE][0] = c;
+        sc[threadIdx.x / WAVE][1] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tc = 0, tp = 0;
+        for (int i = 0; i < TB / WAVE; ++i) {
+            tc += sc[i][0];
+            tp += sc[i][1];
+        }
+        pp[2 * blockIdx.x] = tc;
+        pp[2 * blockIdx.x + 1] = tp;
+    }
+}
+
+// totals[0..2] = set entries, padded entries, pruned leaves, from the
+// per-block partials (one block).
+__global__ void __launch_bounds__(TB) k_sum_partials(const unsigned long long *__restrict__ pp,
+                                                     const uint32_t *__restrict__ prp, int64_t nb,
+                                                     unsigned long long *__restrict__ totals) {
+    __shared__ unsigned long long sc[TB / WAVE][3];
+    unsigned long long c = 0, p = 0, r = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += TB) {
+        c += pp[2 * b];
+        p += pp[2 * b + 1];
+        r += prp[b];
+    }
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+        c += __shfl_xor(c, off, WAVE);
+        p += __shfl_xor(p, off, WAVE);
+        r += __shfl_xor(r, off, WAVE);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        sc[threadIdx.x / WAVE][0] = c;
+        sc[threadIdx.x / WAVE][1] = p;
+        sc[threadIdx.x / WAVE][2] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t[3] = {0, 0, 0};
+        for (int i = 0; i < TB / WAVE; ++i)
+            for (int k = 0; k < 3; ++k) t[k] += sc[i][k];
+        for (int k = 0; k < 3; ++k) totals[k] = t[k];
     }
 }
 
@@ -681,7 +806,6 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     C.dev.n = n;
     C.dev.D = D;
     C.dev.flags = flags;
-    if (n > 0) CAPT_HIP(hipMemcpyAsync(pts, xyz, sizeof(float) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s));
 
     // scratch
     const size_t wN = (size_t)N;
@@ -710,6 +834,8 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     const size_t oCnt = take(sizeof(uint32_t) * (wN + 1));
     const size_t oPs = take(sizeof(uint32_t) * (wN + 1));
     const size_t oTot = take(sizeof(unsigned long long) * 4);
+    const int64_t nbN = (int64_t)nblk(N);   // blocks of the per-point / per-leaf kernels
+    const size_t oPart = take((sizeof(float) * 6 + sizeof(uint32_t) * 2 + sizeof(unsigned long long) * 2) * nbN);
     const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words(std::max<int64_t>(N, cell_cap) + 1));
     const size_t oGrid = take(sizeof(Grid) + 64);
     const size_t oCs = take(sizeof(uint32_t) * ((size_t)cell_cap + 1));
@@ -733,17 +859,15 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     W.totals = reinterpret_cast<unsigned long long *>(Sb + oTot);
     W.scan_tmp = reinterpret_cast<uint32_t *>(Sb + oScan);
     Grid *grid = reinterpret_cast<Grid *>(Sb + oGrid);
-    float *bb = reinterpret_cast<float *>(Sb + oGrid + sizeof(Grid));
     uint32_t *cstart = reinterpret_cast<uint32_t *>(Sb + oCs);
     float *sxyz = reinterpret_cast<float *>(Sb + oS);
-    uint32_t *bad = reinterpret_cast<uint32_t *>(W.totals + 3);
-    CAPT_HIP(hipMemsetAsync(W.totals, 0, sizeof(unsigned long long) * 4, s));
-    CAPT_HIP(hipMemsetAsync(rad, 0, sizeof(uint32_t) * 64, s));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_count_nonfinite, dim3(std::min<int64_t>(nblk(3 * n), 4096)), dim3(TB), 0, s,
-                           xyz, 3 * n, bad);
-        CAPT_LAUNCH_CHECK();
-    }
+    unsigned long long *pad_part = reinterpret_cast<unsigned long long *>(Sb + oPart);   // [nbN][2]
+    float *bbp = reinterpret_cast<float *>(pad_part + 2 * nbN);                          // [nbN][6]
+    uint32_t *badp = reinterpret_cast<uint32_t *>(bbp + 6 * nbN);                         // [nbN]
+    uint32_t *prp = badp + nbN;                                                           // [nbN]
+    hipLaunchKernelGGL(k_binit, dim3((unsigned)std::min<int64_t>((cell_cap + TB) / TB + 1, 1024)), dim3(TB), 0, s,
+                       W.totals, rad, cstart, cell_cap + 1);
+    CAPT_LAUNCH_CHECK();
 
     // 1. presort: list a sorted by (coordinate a, id), the three lists in
     //    one segmented sort (buffer b holds the three lists back to back)
@@ -752,7 +876,8 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         for (int b = 0; b < 2; ++b) L[a][b] = Lbuf + (size_t)(3 * b + a) * wN;
     int cur[3] = {0, 0, 0};
     {
-        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, keys, L[0][0]);
+        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, keys, L[0][0], pts, bbp,
+                           badp);
         CAPT_LAUNCH_CHECK();
         int where = 0;
         capt_status st = radix_sort_u32_seg(keys, L[0][0], keys + 3 * wN, L[0][1], 3, N, 32, rad, s, &where);
@@ -792,25 +917,16 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     CAPT_LAUNCH_CHECK();
 
     // 3. leaf cells and pruning
-    hipLaunchKernelGGL(k_leaf_cells, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, cells);
-    CAPT_LAUNCH_CHECK();
     const int prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
     const double thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
-    hipLaunchKernelGGL(k_prune, dim3(nblk(N)), dim3(TB), 0, s, cells, C.rep, xyz, n, N, prune, thr,
-                       C.pruned_flag, W.totals);
+    hipLaunchKernelGGL(k_cells_prune, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, cells, C.rep, xyz, n, prune, thr,
+                       C.pruned_flag, prp);
     CAPT_LAUNCH_CHECK();
 
     // 4. grid of the points: bins of side >= R / 2, points sorted by bin
     const double R = (double)r_max * (1.0 + 0x1p-20);
-    hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bb);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(TB), 0, s, bbp, badp, nbN, R, cell_cap, grid, W.totals);
     CAPT_LAUNCH_CHECK();
-    if (n > 0) {
-        hipLaunchKernelGGL(k_grid_bbox, dim3(std::min<unsigned>(nblk(n), 16u)), dim3(TB), 0, s, xyz, n, bb);
-        CAPT_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, bb, R, cell_cap, grid);
-    CAPT_LAUNCH_CHECK();
-    CAPT_HIP(hipMemsetAsync(cstart, 0, sizeof(uint32_t) * ((size_t)cell_cap + 1), s));
     if (n > 0) {
         hipLaunchKernelGGL(k_grid_keys, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, grid, keys, gval, cstart);
         CAPT_LAUNCH_CHECK();
@@ -849,7 +965,9 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
                        nullptr, nullptr, nullptr, nullptr);
     CAPT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, W.totals);
+    hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, pad_part);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(TB), 0, s, pad_part, prp, nbN, W.totals);
     CAPT_LAUNCH_CHECK();
     return scan_exclusive_u32(W.pstart, W.pstart, N, nullptr, nullptr, W.scan_tmp, s);
 }
