@@ -63,12 +63,13 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 
 // Zero the phase's counters and bins in one launch.
 __global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__restrict__ errw,
-                        uint32_t *__restrict__ cstart, int64_t ncs) {
+                        uint32_t *__restrict__ cstart, int64_t ncs, uint32_t *__restrict__ scan_st, int64_t nss) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 4) totals[t] = 0ull;
     if (t < 64) errw[t] = 0u;
     for (int64_t i = t; i < ncs; i += stride) cstart[i] = 0u;
+    for (int64_t i = t; i < nss; i += stride) scan_st[i] = 0u;
 }
 
 // One read of the cloud: sort keys of all three axes (segment a of keys /
@@ -836,7 +837,8 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     const size_t oTot = take(sizeof(unsigned long long) * 4);
     const int64_t nbN = (int64_t)nblk(N);   // blocks of the per-point / per-leaf kernels
     const size_t oPart = take((sizeof(float) * 6 + sizeof(uint32_t) * 2 + sizeof(unsigned long long) * 2) * nbN);
-    const size_t oScan = take(sizeof(uint32_t) * scan_tmp_words(std::max<int64_t>(N, cell_cap) + 1));
+    const size_t nscan_cs = scan_lb_words(cell_cap + 1), nscan_ps = scan_lb_words(N);
+    const size_t oScan = take(sizeof(uint32_t) * (nscan_cs + nscan_ps));   // look-back words of the two scans
     const size_t oGrid = take(sizeof(Grid) + 64);
     const size_t oCs = take(sizeof(uint32_t) * ((size_t)cell_cap + 1));
     const size_t oS = take(sizeof(float) * 3 * wn);
@@ -866,7 +868,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     uint32_t *badp = reinterpret_cast<uint32_t *>(bbp + 6 * nbN);                         // [nbN]
     uint32_t *prp = badp + nbN;                                                           // [nbN]
     hipLaunchKernelGGL(k_binit, dim3((unsigned)std::min<int64_t>((cell_cap + TB) / TB + 1, 1024)), dim3(TB), 0, s,
-                       W.totals, rad, cstart, cell_cap + 1);
+                       W.totals, rad, cstart, cell_cap + 1, W.scan_tmp, (int64_t)(nscan_cs + nscan_ps));
     CAPT_LAUNCH_CHECK();
 
     // 1. presort: list a sorted by (coordinate a, id), the three lists in
@@ -932,7 +934,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         CAPT_LAUNCH_CHECK();
     }
     // bin starts: exclusive scan over the cap; cstart[ncells .. cap] = n
-    capt_status st = scan_exclusive_u32(cstart, cstart, cell_cap + 1, nullptr, nullptr, W.scan_tmp, s);
+    capt_status st = scan_exclusive_u32_lb(cstart, cstart, cell_cap + 1, W.scan_tmp, rad, s);
     if (st) return st;
     int where = 0;
     if (n > 1) {
@@ -969,7 +971,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(TB), 0, s, pad_part, prp, nbN, W.totals);
     CAPT_LAUNCH_CHECK();
-    return scan_exclusive_u32(W.pstart, W.pstart, N, nullptr, nullptr, W.scan_tmp, s);
+    return scan_exclusive_u32_lb(W.pstart, W.pstart, N, W.scan_tmp + nscan_cs, rad, s);
 }
 
 capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsigned long long tot[4]) {

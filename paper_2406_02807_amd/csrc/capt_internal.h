@@ -106,6 +106,13 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
                                const int64_t *n_dev, uint32_t *total, uint32_t *tmp,
                                hipStream_t s);
 
+// One-pass exclusive scan by decoupled look-back (sums below 2^30): status
+// holds scan_lb_words(n) words the caller zeroed; err is an error word (bit 16
+// set if an internal wait bound was hit).
+size_t scan_lb_words(int64_t n);
+capt_status scan_exclusive_u32_lb(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *status, uint32_t *err,
+                                  hipStream_t s);
+
 // Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
 // key (n < 2^30).  Keys/values ping-pong between the two buffers; *where tells
 // whether the result is in (k0, v0) (0) or (k1, v1) (1).  tmp must hold

@@ -153,6 +153,66 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// One-pass exclusive scan: tiles take ids from a counter (status[ntiles]) and
+// find their offset by decoupled look-back over the earlier tiles' published
+// sums (bits 30-31 = aggregate / inclusive prefix, bits 0-29 = value, so the
+// total stays below 2^30).  status must hold ntiles + 1 zeroed words.
+__global__ void __launch_bounds__(TB) k_scan_lb(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                int64_t n, uint32_t *__restrict__ status, int64_t ntiles,
+                                                uint32_t *__restrict__ err) {
+    __shared__ uint32_t lw[NW];
+    __shared__ uint32_t s_tile, s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&status[ntiles], 1u);
+    __syncthreads();
+    const int64_t t = s_tile;
+    const int64_t base = t * TILE + (int64_t)threadIdx.x * IPT;
+    uint32_t v[IPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = base + i;
+        v[i] = j < n ? in[j] : 0u;
+        sum += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(sum, lw, &tot);
+    if (threadIdx.x == 0) {
+        uint32_t ex = 0;
+        if (t == 0) {
+            store_agent(&status[0], ST_PRE | tot);
+        } else {
+            store_agent(&status[t], ST_AGG | tot);
+            int64_t q = t - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t w = load_agent(&status[q]);
+                const uint32_t flag = w & ~ST_VAL;
+                if (flag == 0) {
+                    if (++spins > LOOKBACK_SPINS) {
+                        atomicOr(err, 16u);
+                        break;
+                    }
+                    continue;
+                }
+                ex += w & ST_VAL;
+                if (flag == ST_PRE) break;
+                --q;
+            }
+            store_agent(&status[t], ST_PRE | (ex + tot));
+        }
+        s_excl = ex;
+    }
+    __syncthreads();
+    off += s_excl;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = base + i;
+        if (j < n) out[j] = off;
+        off += v[i];
+    }
+}
+
+
 // Segments: the keys form `nseg` independent lists of `len` items each
 // (segment g at g * len); every segment is sorted on its own.
 template <class K>
@@ -340,6 +400,21 @@ capt_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, con
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(TB), 0, s, tmp, nb, total);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(TB), 0, s, in, out, n, n_dev, tmp);
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
+}
+
+size_t scan_lb_words(int64_t n) { return (size_t)((n + TILE - 1) / TILE + 1); }
+
+capt_status scan_exclusive_u32_lb(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *status, uint32_t *err,
+                                  hipStream_t s) {
+    if (n <= 0) return CAPT_OK;
+    if (n >= ((int64_t)1 << 30)) {
+        set_error("one-pass scan of %lld values exceeds 2^30", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    const int64_t nt = (n + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)nt), dim3(TB), 0, s, in, out, n, status, nt, err);
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }
