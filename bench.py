@@ -18,8 +18,9 @@ step (60,000,000 spheres / step time).  Printed as one JSON line, with:
                 exit per configuration) on the same workload
   brute         the GPU brute force on the same spheres (answers compared)
 and, unless --no-extras, the batched ragged workload (64 clouds, one
-persistent launch vs one launch per cloud vs GPU brute force) and the
-clearance forward/backward workload.
+persistent launch vs one launch per cloud vs GPU brute force), the
+clearance forward/backward workload, and the per-frame rebuild latency
+(filter -> build) of a 307,200-point synthetic depth frame.
 """
 from __future__ import annotations
 
@@ -216,6 +217,43 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
     }
 
 
+def bench_frame(capt, torch, reps=10):
+    """Per-frame rebuild latency: filter -> build on one 640 x 480 synthetic
+    depth frame (307,200 points) at r_filter = 1, 1.5 and 2 cm, r_min = 1.5 cm,
+    r_max = 8 cm, against the 16.7 ms budget of a 60 Hz camera."""
+    import synth
+    frame = synth.depth_frame()
+    xyz = torch.from_numpy(frame).cuda()
+    rows = []
+    for rf in (0.01, 0.015, 0.02):
+        for _ in range(2):
+            fx, _ = capt.capt_filter(xyz, rf)
+            capt.capt_build(fx.contiguous(), 0.015, 0.08).close()
+        torch.cuda.synchronize()
+        tf, tb, tw = [], [], []
+        for _ in range(reps):
+            a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            t0 = time.perf_counter()
+            a.record()
+            fx, _ = capt.capt_filter(xyz, rf)
+            b.record()
+            f = capt.capt_build(fx.contiguous(), 0.015, 0.08)
+            c.record()
+            torch.cuda.synchronize()
+            tw.append((time.perf_counter() - t0) * 1e3)
+            tf.append(a.elapsed_time(b))
+            tb.append(b.elapsed_time(c))
+            info = f.info()
+            f.close()
+        rows.append({"r_filter": rf, "points_after_filter": int(fx.shape[0]),
+                     "set_entries": info["set_total"], "filter_ms": float(np.median(tf)),
+                     "build_ms": float(np.median(tb)), "frame_ms_wall": float(np.median(tw)),
+                     "budget_60hz_ms": 1000.0 / 60.0})
+    return {"workload": "one 640 x 480 synthetic depth frame of the tabletop scene in a 6 x 6 x 3 m room "
+                        "(307,200 points, depth noise 0.001 m x depth^2), r_min = 0.015, r_max = 0.08",
+            "points": int(len(frame)), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,6 +416,8 @@ def main():
         log(f"batched: {result['batched']}")
         result["clearance"] = bench_clearance(capt, torch, fx.contiguous())
         log(f"clearance: {result['clearance']}")
+        result["frame"] = bench_frame(capt, torch)
+        log(f"frame: {result['frame']}")
 
     if not args.no_cpu:
         cb, ref = cpu_baseline(w, G, min(args.cpu_sample, m // G))

@@ -164,6 +164,66 @@ def tabletop_cloud(n: int, seed: int, n_boxes: int = 24, n_cyl: int = 8,
     return pts.astype(np.float32)
 
 
+def depth_frame(seed: int = 7001, width: int = 640, height: int = 480, hfov_deg: float = 87.0,
+                vfov_deg: float = 58.0, scene_seed: int = 2001) -> np.ndarray:
+    """One synthetic depth-camera frame of the tabletop scene (the boxes and
+    cylinders of `tabletop_cloud(.., scene_seed)`) inside a 6 x 6 x 3 m room:
+    one point per pixel (width x height), where the pixel's ray first meets a
+    surface, with depth noise N(0, (0.001 m * depth^2)) along the ray.  The
+    camera stands at a seeded point 1.8-2.4 m from the workspace centre at
+    1.0-1.6 m height and looks at it, with the field of view of a common
+    stereo depth camera (87 x 58 degrees).  float32 [width * height, 3]."""
+    gs = _rng(scene_seed)
+    boxes = _random_boxes(gs, 24, WORKSPACE, 0.05, 0.6)
+    cyls = _random_cylinders(gs, 8, WORKSPACE, 0.05, 0.6)
+    g = _rng(seed)
+    ang = g.uniform(0.0, 2.0 * math.pi)
+    dist = g.uniform(1.8, 2.4)
+    cam = np.array([dist * math.cos(ang), dist * math.sin(ang), g.uniform(1.0, 1.6)])
+    look = np.array([0.0, 0.0, 0.5]) - cam
+    fwd = look / np.linalg.norm(look)
+    right = np.cross(fwd, np.array([0.0, 0.0, 1.0]))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    u = (np.arange(width) + 0.5) / width * 2.0 - 1.0
+    v = 1.0 - (np.arange(height) + 0.5) / height * 2.0
+    uu, vv = np.meshgrid(u * math.tan(math.radians(hfov_deg) / 2), v * math.tan(math.radians(vfov_deg) / 2))
+    d = fwd[None, :] + uu.reshape(-1, 1) * right[None, :] + vv.reshape(-1, 1) * up[None, :]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = cam
+    best = np.full(len(d), np.inf)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        for b in boxes:
+            t1 = (b.lo - o) * inv
+            t2 = (b.lo + b.size - o) * inv
+            tn = np.nanmax(np.minimum(t1, t2), axis=1)
+            tf = np.nanmin(np.maximum(t1, t2), axis=1)
+            hit = (tf >= np.maximum(tn, 0.0)) & (tn > 0.0)
+            best = np.where(hit & (tn < best), tn, best)
+        for c in cyls:
+            ox, oy = o[0] - c.cx, o[1] - c.cy
+            a = d[:, 0] ** 2 + d[:, 1] ** 2
+            bq = 2.0 * (ox * d[:, 0] + oy * d[:, 1])
+            cq = ox * ox + oy * oy - c.radius ** 2
+            disc = bq * bq - 4.0 * a * cq
+            t = (-bq - np.sqrt(np.maximum(disc, 0.0))) / (2.0 * a)
+            z = o[2] + t * d[:, 2]
+            hit = (disc >= 0.0) & (t > 0.0) & (z >= c.z0) & (z <= c.z0 + c.height)
+            best = np.where(hit & (t < best), t, best)
+            for zc in (c.z0, c.z0 + c.height):
+                t = (zc - o[2]) * inv[:, 2]
+                x = o[0] + t * d[:, 0] - c.cx
+                y = o[1] + t * d[:, 1] - c.cy
+                hit = (t > 0.0) & (x * x + y * y <= c.radius ** 2)
+                best = np.where(hit & (t < best), t, best)
+        for axis, value in ((2, 0.0), (2, 3.0), (0, -3.0), (0, 3.0), (1, -3.0), (1, 3.0)):
+            t = (value - o[axis]) * inv[:, axis]
+            best = np.where((t > 0.0) & (t < best), t, best)
+    best = best + g.normal(0.0, 1.0, len(best)) * 0.001 * best ** 2
+    return (o[None, :] + best[:, None] * d).astype(np.float32)
+
+
 def room_cloud(n_surface: int, n_outliers: int, seed: int, n_boxes: int = 20,
                n_cyl: int = 20, size=(0.05, 0.6), noise: float = 0.003) -> np.ndarray:
     """A 6 x 6 x 3 m room: floor and four walls plus `n_boxes` boxes and

@@ -458,3 +458,22 @@ def test_full_size_batched_64_clouds(capt, orc):
         sub = w.spheres[c].reshape(-1, 60, 4)[pick].reshape(-1, 4)
         want = orc.brute_f32(w.cloud[c], sub, 60)
         assert np.array_equal(got[query_off[c] // 60 + pick], want), c
+
+
+def test_depth_frame_filter_and_build(capt, orc):
+    """A 640 x 480 synthetic depth frame (307,200 points): the filter at the three
+    radii of the per-frame experiment against the oracle, and the tree built
+    from the 2 cm frame against the oracle build, then queried."""
+    frame = synth.depth_frame()
+    xyz = dev(frame)
+    for rf in (0.01, 0.015, 0.02):
+        _say(f"case: depth frame filter r_filter={rf}")
+        fx, fidx = capt.capt_filter(xyz, rf)
+        keep, _ = orc.filter(frame, rf)
+        assert np.array_equal(fidx.cpu().numpy(), keep)
+    pts = frame[keep]
+    _say(f"case: depth frame build n={len(pts)}")
+    f, b, t = compare_build(capt, orc, pts, 0.015, 0.08)
+    sph = synth.uniform_spheres(60 * 2000, np.array([[-3.0, 3.0], [-3.0, 3.0], [0.0, 2.2]]), 0.015, 0.08, 7002)
+    got = capt.capt_collides(f, dev(sph), 60).cpu().numpy()
+    assert np.array_equal(got, orc.brute_f32(pts, sph, 60))
