@@ -180,12 +180,12 @@ __global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState
     }
 }
 
-constexpr int CT = 256;              // threads of the chain kernel
+// The chain kernel takes one position per thread; a chunk is CT positions
+// (256, or 1024 for large clouds, where fewer chunks shorten the look-back).
 constexpr int CI = 1;                // positions per thread
-constexpr int CC = CT * CI;          // chunk length
-constexpr int CR = 8;                // log2(CC): jump tables J_0 .. J_7
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 // dynamic LDS of the chain kernel: J [CR][CC] u16, Nx [CC] u32, Ex [CC] u32, mark [CC] i8
-constexpr size_t CHAIN_LDS = sizeof(uint16_t) * CR * CC + 2 * sizeof(uint32_t) * CC + CC;
+constexpr size_t chain_lds(int CC) { return sizeof(uint16_t) * ilog2c(CC) * CC + 2 * sizeof(uint32_t) * CC + CC; }
 constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"
 constexpr uint32_t PUB = 0x80000000u;
 constexpr uint32_t MX_AGG = 0x40000000u;   // farthest reach: this chunk's own (positions < 2^30)
@@ -200,6 +200,7 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <int CT>
 __device__ __forceinline__ uint32_t block_excl_scan_c(uint32_t v, uint32_t *lw, uint32_t *total) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
@@ -227,6 +228,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_c(uint32_t v, uint32_t *lw, 
 // curve order (original ids); live_in / live_out: liveness per original id
 // before / after the pass.  With `last`, the survivors also go to out in
 // order and their count to st->mm[0].
+template <int CT>
 __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ xyz, const uint32_t *__restrict__ ord,
                                                     int64_t n, const uint8_t *__restrict__ live_in,
                                                     uint8_t *__restrict__ live_out, FState *__restrict__ st,
@@ -234,9 +236,11 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
                                                     uint32_t *__restrict__ kept_st, uint32_t *__restrict__ max_pub,
                                                     uint32_t *__restrict__ chunk_ctr, uint32_t *__restrict__ out,
                                                     uint32_t *__restrict__ err) {
-    extern __shared__ uint32_t chain_lds[];
-    auto J = reinterpret_cast<uint16_t(*)[CC]>(chain_lds);
-    uint32_t *Nx = chain_lds + CR * CC / 2;
+    constexpr int CC = CT * CI;          // chunk length
+    constexpr int CR = ilog2c(CC);       // jump tables J_0 .. J_{CR-1}
+    extern __shared__ uint32_t chain_mem[];
+    auto J = reinterpret_cast<uint16_t(*)[CC]>(chain_mem);
+    uint32_t *Nx = chain_mem + CR * CC / 2;
     uint32_t *Ex = Nx + CC;
     int8_t *mark = reinterpret_cast<int8_t *>(Ex + CC);
     __shared__ uint32_t s_chunk, s_entry, s_prefix, s_max;
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     }
     if (!last) return;
     uint32_t kept;
-    uint32_t off = block_excl_scan_c(cnt, lw, &kept);
+    uint32_t off = block_excl_scan_c<CT>(cnt, lw, &kept);
     // 6. offset of the chunk's survivors: look back over earlier chunks
     if (threadIdx.x == 0) {
         uint32_t excl = 0;
@@ -446,7 +450,9 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     }
     constexpr int NP = 6;
     const size_t wn = (size_t)n;
-    const int64_t nchunk = (n + CC - 1) / CC;
+    // chunk length: 256 positions, or 1024 once that would make more than 256 chunks
+    const int CT = (n + 255) / 256 > 256 ? 1024 : 256;
+    const int64_t nchunk = (n + CT - 1) / CT;
     const int64_t npub = NP * (3 * nchunk + 64);   // per pass: exits, survivor counts, farthest reaches, counter
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -482,9 +488,6 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     float *bbp = reinterpret_cast<float *>(B + oBB);
     unsigned int *bbbad = reinterpret_cast<unsigned int *>(bbp + 6 * BB_BLOCKS);
 
-    static const hipError_t lds_attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(k_filter_chain), hipFuncAttributeMaxDynamicSharedMemorySize, (int)CHAIN_LDS);
-    if (lds_attr != hipSuccess) return hip_fail(lds_attr, "hipFuncSetAttribute(k_filter_chain)", __FILE__, __LINE__);
     const float rf2 = r_filter * r_filter;
     hipLaunchKernelGGL(k_finit, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(npub, n) / TB + 1, 1024)), dim3(TB),
                        0, s, pub, npub, rad, live, n);
@@ -502,9 +505,14 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     const uint32_t *ord = where ? v1 : v0;
     for (int p = 0; p < NP; ++p) {
         uint32_t *pp = pub + (size_t)p * (3 * nchunk + 64);
-        hipLaunchKernelGGL(k_filter_chain, dim3((unsigned)nchunk), dim3(CT), CHAIN_LDS, s, xyz, ord + (size_t)p * wn, n,
-                           live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2, (int)(p == NP - 1), pp,
-                           pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
+        if (CT == 1024)
+            hipLaunchKernelGGL(k_filter_chain<1024>, dim3((unsigned)nchunk), dim3(1024), chain_lds(1024), s, xyz,
+                               ord + (size_t)p * wn, n, live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2,
+                               (int)(p == NP - 1), pp, pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
+        else
+            hipLaunchKernelGGL(k_filter_chain<256>, dim3((unsigned)nchunk), dim3(256), chain_lds(256), s, xyz,
+                               ord + (size_t)p * wn, n, live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2,
+                               (int)(p == NP - 1), pp, pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index);

@@ -215,8 +215,11 @@ __global__ void __launch_bounds__(TB) k_scan_lb(const uint32_t *__restrict__ in,
 
 // Segments: the keys form `nseg` independent lists of `len` items each
 // (segment g at g * len); every segment is sorted on its own.
-template <class K>
-__global__ void k_os_hist(const K *__restrict__ keys, int64_t len, int nseg, int npass, uint32_t *__restrict__ ghist) {
+// Histograms of every digit of every pass.  ATOMIC: blocks add theirs to
+// ghist[pass][seg][256] (few blocks, small inputs); otherwise every block
+// writes its own to part[block][seg][pass][256] and k_os_hist_sum adds them.
+template <class K, bool ATOMIC>
+__global__ void k_os_hist(const K *__restrict__ keys, int64_t len, int nseg, int npass, uint32_t *__restrict__ part) {
     extern __shared__ uint32_t h[];   // [nseg][npass][256]
     const int nh = nseg * npass * 256;
     for (int i = threadIdx.x; i < nh; i += TB) h[i] = 0;
@@ -229,12 +232,29 @@ __global__ void k_os_hist(const K *__restrict__ keys, int64_t len, int nseg, int
         for (int p = 0; p < npass; ++p) atomicAdd(&hs[p * 256 + ((uint32_t)(k >> (8 * p)) & 255u)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nh; i += TB) {
-        // ghist layout: [pass][seg][256]
-        const int g = i / (npass * 256), r = i % (npass * 256);
-        const int p = r / 256, d = r % 256;
-        if (h[i]) atomicAdd(&ghist[((size_t)p * nseg + g) * 256 + d], h[i]);
+    if (ATOMIC) {
+        for (int i = threadIdx.x; i < nh; i += TB) {
+            const int g = i / (npass * 256), r = i % (npass * 256);
+            const int p = r / 256, d = r % 256;
+            if (h[i]) atomicAdd(&part[((size_t)p * nseg + g) * 256 + d], h[i]);
+        }
+        return;
     }
+    uint32_t *out = part + (size_t)blockIdx.x * nh;
+    for (int i = threadIdx.x; i < nh; i += TB) out[i] = h[i];
+}
+
+// ghist[pass][seg][256] = sum over blocks of part[block][seg][pass][256].
+__global__ void k_os_hist_sum(const uint32_t *__restrict__ part, int nblocks, int nseg, int npass,
+                              uint32_t *__restrict__ ghist) {
+    const int nh = nseg * npass * 256;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nh) return;
+    uint32_t t = 0;
+    for (int b = 0; b < nblocks; ++b) t += part[(size_t)b * nh + i];
+    const int g = i / (npass * 256), r = i % (npass * 256);
+    const int p = r / 256, d = r % 256;
+    ghist[((size_t)p * nseg + g) * 256 + d] = t;
 }
 
 template <class K>
@@ -340,9 +360,11 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
 }
 
 constexpr int MAX_SEG = 8;
+constexpr int HIST_BLOCKS = 256;          // blocks of the histogram pass (per-block partials)
+constexpr int ATOMIC_HIST_BLOCKS = 64;    // blocks of the histogram pass (atomics, small inputs)
 
 // tmp layout: [err (64 words)] [ghist npass*nseg*256] [tile counters 64]
-// [status npass*nseg*tps*256].  The error word (tmp[0], set if a look-back
+// [status npass*nseg*tps*256] [per-block histograms HIST_BLOCKS*nseg*npass*256].  The error word (tmp[0], set if a look-back
 // wait ever exceeds its bound) is not cleared here: callers clear it once and
 // read it at their next sync.
 template <class K>
@@ -366,9 +388,23 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
                        tmp + 64, words - 64, 0u);
     CAPT_LAUNCH_CHECK();
     const size_t hl = sizeof(uint32_t) * (size_t)nseg * npass * 256;
-    hipLaunchKernelGGL(k_os_hist<K>, dim3((unsigned)std::min<int64_t>(ntiles, 64)), dim3(TB), hl, s, k0, len, nseg,
-                       npass, ghist);
-    CAPT_LAUNCH_CHECK();
+    if (ntiles <= 4 * ATOMIC_HIST_BLOCKS) {
+        // small inputs: one kernel, block histograms added with atomics
+        hipLaunchKernelGGL((k_os_hist<K, true>), dim3((unsigned)std::min<int64_t>(ntiles, ATOMIC_HIST_BLOCKS)),
+                           dim3(TB), hl, s, k0, len, nseg, npass, ghist);
+        CAPT_LAUNCH_CHECK();
+    } else {
+        // large inputs: per-block histograms, then one add per bin
+        const int hblocks = (int)std::min<int64_t>(HIST_BLOCKS, ntiles / 4);
+        uint32_t *hpart = status + (size_t)npass * ntiles * 256;
+        hipLaunchKernelGGL((k_os_hist<K, false>), dim3((unsigned)hblocks), dim3(TB), hl, s, k0, len, nseg, npass,
+                           hpart);
+        CAPT_LAUNCH_CHECK();
+        const int nh = nseg * npass * 256;
+        hipLaunchKernelGGL(k_os_hist_sum, dim3((unsigned)((nh + TB - 1) / TB)), dim3(TB), 0, s, hpart, hblocks, nseg,
+                           npass, ghist);
+        CAPT_LAUNCH_CHECK();
+    }
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int p = 0; p < npass; ++p) {
@@ -423,7 +459,8 @@ size_t radix_tmp_words(int64_t n) { return radix_tmp_words_seg(1, n); }
 
 size_t radix_tmp_words_seg(int nseg, int64_t len) {
     const int64_t tps = (len + TILE - 1) / TILE;
-    return (size_t)(64 + 8 * 256 * (int64_t)nseg + 64 + 8 * tps * nseg * 256 + 64);
+    return (size_t)(64 + 8 * 256 * (int64_t)nseg + 64 + 8 * tps * nseg * 256 +
+                    (int64_t)HIST_BLOCKS * nseg * 8 * 256 + 64);
 }
 
 capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
