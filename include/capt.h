@@ -112,7 +112,7 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
  *              spheres[query_off[c] .. query_off[c+1])
  *   query_off  host [ncloud + 1], non-decreasing, each range a multiple of
  *              `group`
- *   group      1 .. 1024 spheres per configuration
+ *   group      1 .. 2^20 spheres per configuration
  *   out        [M / group] bytes; out[k] = 1 iff some sphere of configuration
  *              k touches its cloud, else 0
  *   flags      CAPT_CHECK_RADII, CAPT_PER_CLOUD, CAPT_NO_GRAPH
@@ -124,6 +124,34 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
  */
 capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *query_off,
                           int32_t group, uint8_t *out, uint32_t flags, void *stream);
+
+/*
+ * CollisionCheck (Alg. 3) on robot configurations given as rigid poses of one
+ * sphere template, grouped into edges (runs of consecutive configurations, as
+ * a planner validates a motion) with early exit at the first colliding sphere
+ * of an edge in order (configurations in order, spheres in template order).
+ * Reading the template and a 48-byte pose per configuration replaces reading
+ * g materialised spheres.
+ *   tmpl      [g][4] template spheres (x, y, z, r) in the robot frame;
+ *             1 <= g <= 1024
+ *   poses     [P][12] per configuration: rotation R row-major (9 floats), then
+ *             translation t (3 floats); sphere k of configuration c is centred
+ *             at ((R0 x + R1 y) + R2 z) + t0, ((R3 x + R4 y) + R5 z) + t1,
+ *             ((R6 x + R7 y) + R8 z) + t2, every product and sum rounded to
+ *             float32 on its own, radius r
+ *   pose_off  host [ncloud + 1]: the poses of cloud c are
+ *             poses[pose_off[c] .. pose_off[c+1]), each range a multiple of edge
+ *   edge      configurations per edge (edge * g <= 2^20)
+ *   out       [P / edge] bytes; out[k] = 1 iff some sphere of some configuration
+ *             of edge k touches its cloud (the float32 predicate of
+ *             capt_collides), else 0
+ *   flags     CAPT_CHECK_RADII (template radii against [r_min, r_max]) or 0
+ * Asynchronous on `stream`; CAPT_EINVAL on bad arguments.  The answers equal
+ * capt_collides on the materialised spheres with group = edge * g.
+ */
+capt_status capt_collides_posed(capt_forest f, const float *tmpl, int32_t g, const float *poses,
+                                const int64_t *pose_off, int32_t edge, uint8_t *out, uint32_t flags,
+                                void *stream);
 
 /*
  * Clearance of each sphere: c = min(d, r_max) - r, with d the float32

@@ -59,6 +59,7 @@ def _load():
         sig = {
             "orc_sqdist_f32": (f32, [P, P]),
             "orc_brute_f32": (None, [P, i64, P, i64, i32, P]),
+            "orc_pose_spheres": (None, [P, i32, P, i64, P]),
             "orc_brute_f64": (None, [P, i64, P, i64, P, P]),
             "orc_clearance_f64": (None, [P, i64, P, i64, f32, P, P, P]),
             "orc_build": (P, [P, i64, f32, f32, C.c_int]),
@@ -101,6 +102,17 @@ def brute_f32(points, spheres, group: int = 1) -> np.ndarray:
     assert len(sph) % group == 0
     out = np.zeros(len(sph) // group, dtype=np.uint8)
     _load().orc_brute_f32(_p(pts), len(pts), _p(sph), len(sph), group, _p(out))
+    return out
+
+
+def pose_spheres(template, poses) -> np.ndarray:
+    """Template spheres [g, 4] under rigid poses [P, 12] (row-major rotation,
+    then translation), float32 arithmetic in the posed query's order:
+    float32 [P * g, 4], configuration-major."""
+    tm = _f32(template, 4)
+    ps = _f32(poses, 12)
+    out = np.zeros((len(ps) * len(tm), 4), dtype=np.float32)
+    _load().orc_pose_spheres(_p(tm), len(tm), _p(ps), len(ps), _p(out))
     return out
 
 

@@ -69,6 +69,32 @@ ORC_API float orc_sqdist_f32(const float *a, const float *b) { return sqdist_f32
 
 /* O1: brute force, float32 predicate.  out[c] = 1 iff some sphere of group c
  * (spheres c*g .. c*g+g-1) touches some point.  m must be a multiple of g. */
+/* Spheres of a template under rigid poses (the posed query's definition):
+ * sphere k of configuration c is template sphere k with centre
+ * ((R0 x + R1 y) + R2 z) + t0, ((R3 x + R4 y) + R5 z) + t1,
+ * ((R6 x + R7 y) + R8 z) + t2, every product and sum in float32, radius kept;
+ * pose c = R row-major (9 floats), then t (3 floats).  out [P * g][4],
+ * configuration-major. */
+ORC_API void orc_pose_spheres(const float *tmpl, int32_t g, const float *poses, int64_t P, float *out)
+{
+    for (int64_t c = 0; c < P; ++c) {
+        const float *R = poses + 12 * c;
+        for (int32_t k = 0; k < g; ++k) {
+            const float x = tmpl[4 * k], y = tmpl[4 * k + 1], z = tmpl[4 * k + 2];
+            float *o = out + 4 * (c * g + k);
+            for (int i = 0; i < 3; ++i) {
+                float a = R[3 * i] * x;
+                float b = R[3 * i + 1] * y;
+                float s = a + b;
+                float d = R[3 * i + 2] * z;
+                s = s + d;
+                o[i] = s + R[9 + i];
+            }
+            o[3] = tmpl[4 * k + 3];
+        }
+    }
+}
+
 ORC_API void orc_brute_f32(const float *pts, int64_t n, const float *sph, int64_t m,
                            int32_t g, uint8_t *out)
 {

@@ -28,7 +28,7 @@ CAPT_NO_GRAPH = 0x8
 EXPORTS = [
     "capt_filter", "capt_build", "capt_collides", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
-    "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning",
+    "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
     "capt_get_tuning",
 ]
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH):
         "capt_bruteforce_collides": [P, P, i32, P, P, i32, P, P],
         "capt_query_stats": [P, P, P, P, P, P, P, P],
         "capt_query_chunk_stats": [P, P, P, P, P, P],
+        "capt_collides_posed": [P, P, i32, P, P, i32, P, u32, P],
         "capt_set_tuning": [P],
         "capt_get_tuning": [P],
     }
@@ -210,6 +211,28 @@ def capt_collides(forest: Forest, spheres, group: int = 1, query_off=None, flags
         out = torch.empty((M // group,), dtype=torch.uint8, device=spheres.device)
     _check(lib.capt_collides(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
                              _ptr(out), flags, _stream(stream)))
+    return out
+
+
+def capt_collides_posed(forest: Forest, template, poses, edge: int = 1, pose_off=None, flags: int = 0,
+                        out=None, stream=None):
+    """CollisionCheck on posed template spheres, grouped into edges of `edge`
+    configurations: uint8 [P / edge].  template [g, 4]; poses [P, 12]
+    (row-major rotation, then translation)."""
+    import torch
+    lib = load_library()
+    template = _dev(template, torch.float32, 4, "template")
+    poses = _dev(poses, torch.float32, 12, "poses")
+    P = poses.shape[0]
+    if pose_off is None:
+        if forest.ncloud != 1:
+            raise ValueError("pose_off is required for a forest of several clouds")
+        pose_off = [0, P]
+    off = _offsets(pose_off, forest.ncloud)
+    if out is None:
+        out = torch.empty((P // edge,), dtype=torch.uint8, device=poses.device)
+    _check(lib.capt_collides_posed(forest.handle, _ptr(template), template.shape[0], _ptr(poses),
+                                   off.ctypes.data_as(C.c_void_p), edge, _ptr(out), flags, _stream(stream)))
     return out
 
 

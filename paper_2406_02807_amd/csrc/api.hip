@@ -127,8 +127,8 @@ capt_status check_queries(capt_forest f, const float *spheres, const int64_t *qo
     const int32_t nc = (int32_t)f->clouds.size();
     capt_status st = check_offsets(qoff, nc, "query_off");
     if (st) return st;
-    if (group < 1 || group > 1024) {
-        set_error("group = %d outside 1 .. 1024", group);
+    if (group < 1 || group > MAX_GROUP) {
+        set_error("group = %d outside 1 .. 2^20", group);
         return CAPT_EINVAL;
     }
     for (int32_t c = 0; c < nc; ++c)
@@ -320,6 +320,36 @@ capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *qu
     }
     if (M == 0) return CAPT_OK;
     return collides(f, spheres, query_off, group, out, flags, (hipStream_t)stream);
+}
+
+capt_status capt_collides_posed(capt_forest f, const float *tmpl, int32_t g, const float *poses,
+                                const int64_t *pose_off, int32_t edge, uint8_t *out, uint32_t flags, void *stream) {
+    ApiGuard guard;
+    if (g < 1 || g > 1024) {
+        set_error("template size g = %d outside 1 .. 1024", g);
+        return CAPT_EINVAL;
+    }
+    if (!tmpl) {
+        set_error("template is NULL");
+        return CAPT_EINVAL;
+    }
+    if (edge < 1 || (int64_t)edge * g > MAX_GROUP) {
+        set_error("edge = %d outside 1 .. 2^20 / g", edge);
+        return CAPT_EINVAL;
+    }
+    capt_status st = check_queries(f, poses, pose_off, edge);   // pose ranges in whole edges
+    if (st) return st;
+    if (flags & ~CAPT_CHECK_RADII) {
+        set_error("unknown posed query flags 0x%x", flags);
+        return CAPT_EINVAL;
+    }
+    const int64_t P = pose_off[f->clouds.size()];
+    if (P > 0 && !out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (P == 0) return CAPT_OK;
+    return collides_posed(f, tmpl, g, poses, pose_off, edge, out, flags, (hipStream_t)stream);
 }
 
 capt_status capt_clearance(capt_forest f, const float *spheres, const int64_t *query_off, float *clearance,
@@ -601,8 +631,8 @@ capt_status capt_bruteforce_collides(const float *xyz, const int64_t *cloud_off,
     capt_status st = check_offsets(cloud_off, ncloud, "cloud_off");
     if (!st) st = check_offsets(query_off, ncloud, "query_off");
     if (st) return st;
-    if (group < 1 || group > 1024) {
-        set_error("group = %d outside 1 .. 1024", group);
+    if (group < 1 || group > MAX_GROUP) {
+        set_error("group = %d outside 1 .. 2^20", group);
         return CAPT_EINVAL;
     }
     for (int32_t c = 0; c < ncloud; ++c)

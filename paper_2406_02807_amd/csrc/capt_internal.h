@@ -49,6 +49,8 @@ constexpr uint32_t CHUNK = SET_ALIGN;
 // Stored set entries per cloud (with padding) stay below this, so the query
 // kernels address the set arrays with 32-bit byte offsets.
 constexpr unsigned long long MAX_SET_ENTRIES = 1ull << 30;
+// Largest configuration (spheres per group) a query accepts.
+constexpr int32_t MAX_GROUP = 1 << 20;
 
 // ---------------------------------------------------------------------------
 // Host-side error state and helpers (api.hip)
@@ -182,6 +184,8 @@ void sets_layout(void *base, size_t entries, float **px, float **py, float **pz,
 // query.hip
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                      int32_t group, uint8_t *out, uint32_t flags, hipStream_t s);
+capt_status collides_posed(capt_forest_s *f, const float *tmpl, int32_t g, const float *poses, const int64_t *pose_off,
+                           int32_t edge, uint8_t *out, uint32_t flags, hipStream_t s);
 capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                         int32_t *leaf, uint8_t *rejected, int32_t *scanned, uint8_t *hit, hipStream_t s);
 capt_status chunk_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off, int32_t *boxes,

@@ -358,17 +358,51 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
     }
 }
 
-// Configurations of more than SLOT spheres, with early exit inside a
-// configuration: the wave's 64 lanes form NSLOT slots of SLOT lanes; a slot
-// holds one configuration and tests its spheres SLOT at a time, in order,
-// stopping at the first piece with a hit (as a sequential scan of the
-// configuration would); a slot that finishes takes the next configuration
-// from the wave's popped range (per-XCD queues as above).  The slots of a
-// wave run together through the two-level scan, each slot a group.
 constexpr int SLOT = 16;
 
-template <int U>
-__global__ void k_collide_slots(CloudDev C, const float4 *__restrict__ sph, int64_t ncfg, int g,
+// Sphere sources of the slot kernel: item i has `len` spheres in test order.
+// Materialised spheres: item = configuration, sphere k = spheres[i * g + k].
+struct SphereSrc {
+    const float4 *sph;
+    __device__ __forceinline__ float4 operator()(int64_t item, int k, int len) const {
+        return sph[item * len + k];
+    }
+};
+// Posed template: item = edge of `edge` configurations, each a rigid pose
+// (row-major rotation R, then translation t: 12 floats) of the g template
+// spheres; sphere k is template sphere k % g under pose item * edge + k / g:
+// centre ((R0 x + R1 y) + R2 z) + t0 (and likewise), every operation rounded
+// to float32 on its own, radius unchanged.
+struct PosedSrc {
+    const float *poses;
+    const float4 *tmpl;
+    int g;
+    __device__ __forceinline__ float4 operator()(int64_t item, int k, int len) const {
+        const int edge = len / g;
+        const int c = k / g;
+        const float4 t = tmpl[k - c * g];
+        const float *P = poses + 12 * (item * edge + c);
+        const float4 a = *reinterpret_cast<const float4 *>(P);       // R0 R1 R2 R3
+        const float4 b = *reinterpret_cast<const float4 *>(P + 4);   // R4 R5 R6 R7
+        const float4 d = *reinterpret_cast<const float4 *>(P + 8);   // R8 t0 t1 t2
+        float4 q;
+        q.x = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(a.x, t.x), __fmul_rn(a.y, t.y)), __fmul_rn(a.z, t.z)), d.y);
+        q.y = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(a.w, t.x), __fmul_rn(b.x, t.y)), __fmul_rn(b.y, t.z)), d.z);
+        q.z = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(b.z, t.x), __fmul_rn(b.w, t.y)), __fmul_rn(d.x, t.z)), d.w);
+        q.w = t.w;
+        return q;
+    }
+};
+
+// Items (configurations, or edges of posed configurations) of `len` spheres,
+// with early exit inside an item: the wave's 64 lanes form four slots of
+// SLOT lanes; a slot holds one item and tests its spheres SLOT at a time, in
+// order, stopping at the first piece with a hit (as a sequential scan of the
+// item would); a slot that finishes takes the next item from the wave's
+// popped range (per-XCD queues as above).  The slots of a wave run together
+// through the two-level scan, each slot a group.
+template <int U, class Src>
+__global__ void k_collide_slots(CloudDev C, Src src, int64_t ncfg, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float4 lds4[];
     WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
@@ -416,7 +450,7 @@ __global__ void k_collide_slots(CloudDev C, const float4 *__restrict__ sph, int6
         if (__ballot(active) == 0) break;   // range drained and every slot finished
         const int si = s0 + j;
         const bool valid = active && si < g;
-        const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 q = valid ? src(cfg, si, g) : make_float4(0.f, 0.f, 0.f, 0.f);
         bool hit = wave_tile<U>(C, Tl, L, q, valid, SLOT, false, W);
         hit = __shfl(hit, lead, WAVE);   // the slot's first lane always holds a sphere
         if (active) {
@@ -693,66 +727,98 @@ template <class K> capt_status allow_lds(K kernel) {
     return CAPT_OK;
 }
 
-capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
-                         unsigned int *ctr, hipStream_t s) {
-    if (nsph <= 0) return CAPT_OK;
+// Launch shape shared by the single-cloud kernels.
+struct CloudShape {
+    int threads = 0, L = 0;
+    int64_t blocks = 0;
+    size_t lds = 0;
+};
+
+CloudShape cloud_shape(const CloudDev &C, int64_t units) {
     const capt_tuning &t = tuning();
-    const int threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
-    const size_t wl = sizeof(WaveLds) * (size_t)(threads / WAVE);
-    const int L = lds_levels_for(C.D, wl);
-    const int64_t ncfg = nsph / g;
-    const int cpt = g <= WAVE ? WAVE / g : 1;
-    const int64_t ntiles = (ncfg + cpt - 1) / cpt;
-    const int64_t wpb = threads / WAVE;
-    int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
-    blocks = std::max<int64_t>(1, std::min(blocks, (ntiles + wpb - 1) / wpb));
-    // queue chunk: about 8 pops per wave over the whole launch, 1 .. 64 tiles
-    const int64_t per_wave = ntiles / std::max<int64_t>(1, blocks * wpb);
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_wave / 8));
-    const size_t lds = wl + sizeof(float) * (size_t)((1 << L) - 1);
-    static const bool lds_ok = allow_lds(k_collide_cloud<4>) == CAPT_OK && allow_lds(k_collide_cloud<2>) == CAPT_OK &&
-                               allow_lds(k_collide_cloud<1>) == CAPT_OK && allow_lds(k_collide_slots<4>) == CAPT_OK &&
-                               allow_lds(k_collide_slots<2>) == CAPT_OK && allow_lds(k_collide_slots<1>) == CAPT_OK;
+    CloudShape sh;
+    sh.threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
+    const size_t wl = sizeof(WaveLds) * (size_t)(sh.threads / WAVE);
+    sh.L = lds_levels_for(C.D, wl);
+    const int64_t wpb = sh.threads / WAVE;
+    sh.blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
+    sh.blocks = std::max<int64_t>(1, std::min(sh.blocks, (units + wpb - 1) / wpb));
+    sh.lds = wl + sizeof(float) * (size_t)((1 << sh.L) - 1);
+    return sh;
+}
+
+// queue chunk: about 8 pops per wave over the whole launch, 1 .. 64 units
+int queue_chunk(const CloudShape &sh, int64_t units) {
+    const int64_t per_wave = units / std::max<int64_t>(1, sh.blocks * (sh.threads / WAVE));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(64, per_wave / 8));
+}
+
+template <class K> bool allow_lds_once(K k) {
+    return allow_lds(k) == CAPT_OK;
+}
+
+// Slot kernel over `nitem` items of `len` spheres each.
+template <class Src>
+capt_status launch_slots(const CloudDev &C, Src src, int64_t nitem, int len, uint8_t *out, unsigned int *ctr,
+                         hipStream_t s) {
+    if (nitem <= 0) return CAPT_OK;
+    static const bool lds_ok = allow_lds_once(k_collide_slots<4, Src>) && allow_lds_once(k_collide_slots<2, Src>) &&
+                               allow_lds_once(k_collide_slots<1, Src>);
     if (!lds_ok) {
         set_error("raising the dynamic LDS limit of the collision kernel failed");
         return CAPT_EHIP;
     }
+    const CloudShape sh = cloud_shape(C, nitem);
+    const int chunk = queue_chunk(sh, nitem);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
     CAPT_LAUNCH_CHECK();
-    const float4 *sp = reinterpret_cast<const float4 *>(spheres);
-    if (g > SLOT) {
-        // slots: the queue holds configurations
-        const int64_t per_cfg_wave = ncfg / std::max<int64_t>(1, blocks * wpb);
-        const int cchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, per_cfg_wave / 8));
-        switch (t.scan_unroll) {
-            case 4:
-                hipLaunchKernelGGL(k_collide_slots<4>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
-                                   out, L, ctr, cchunk);
-                break;
-            case 2:
-                hipLaunchKernelGGL(k_collide_slots<2>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
-                                   out, L, ctr, cchunk);
-                break;
-            default:
-                hipLaunchKernelGGL(k_collide_slots<1>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, ncfg, g,
-                                   out, L, ctr, cchunk);
-                break;
-        }
-        CAPT_LAUNCH_CHECK();
-        return CAPT_OK;
-    }
-    switch (t.scan_unroll) {
+    const dim3 grid((unsigned)sh.blocks), block(sh.threads);
+    switch (tuning().scan_unroll) {
         case 4:
-            hipLaunchKernelGGL(k_collide_cloud<4>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
-                               ctr, chunk);
+            hipLaunchKernelGGL((k_collide_slots<4, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+                               chunk);
             break;
         case 2:
-            hipLaunchKernelGGL(k_collide_cloud<2>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
-                               ctr, chunk);
+            hipLaunchKernelGGL((k_collide_slots<2, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+                               chunk);
             break;
         default:
-            hipLaunchKernelGGL(k_collide_cloud<1>, dim3((unsigned)blocks), dim3(threads), lds, s, C, sp, nsph, g, out, L,
-                               ctr, chunk);
+            hipLaunchKernelGGL((k_collide_slots<1, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+                               chunk);
+            break;
+    }
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
+}
+
+capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
+                         unsigned int *ctr, hipStream_t s) {
+    if (nsph <= 0) return CAPT_OK;
+    const int64_t ncfg = nsph / g;
+    const float4 *sp = reinterpret_cast<const float4 *>(spheres);
+    if (g > SLOT) return launch_slots(C, SphereSrc{sp}, ncfg, g, out, ctr, s);   // slots: the queue holds configurations
+    static const bool lds_ok = allow_lds_once(k_collide_cloud<4>) && allow_lds_once(k_collide_cloud<2>) &&
+                               allow_lds_once(k_collide_cloud<1>);
+    if (!lds_ok) {
+        set_error("raising the dynamic LDS limit of the collision kernel failed");
+        return CAPT_EHIP;
+    }
+    const int cpt = WAVE / g;
+    const int64_t ntiles = (ncfg + cpt - 1) / cpt;
+    const CloudShape sh = cloud_shape(C, ntiles);
+    const int chunk = queue_chunk(sh, ntiles);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NXCD * CTR_STRIDE), 0, s, ctr, NXCD * CTR_STRIDE);
+    CAPT_LAUNCH_CHECK();
+    const dim3 grid((unsigned)sh.blocks), block(sh.threads);
+    switch (tuning().scan_unroll) {
+        case 4:
+            hipLaunchKernelGGL(k_collide_cloud<4>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_collide_cloud<2>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
+            break;
+        default:
+            hipLaunchKernelGGL(k_collide_cloud<1>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
             break;
     }
     CAPT_LAUNCH_CHECK();
@@ -915,6 +981,29 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
         CAPT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     }
     CAPT_HIP(hipGraphLaunch(p->exec, s));
+    return CAPT_OK;
+}
+
+capt_status collides_posed(capt_forest_s *f, const float *tmpl, int32_t g, const float *poses, const int64_t *poff,
+                           int32_t edge, uint8_t *out, uint32_t flags, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    if (flags & CAPT_CHECK_RADII) {
+        capt_status st = check_radii(tmpl, g, f->r_min, f->r_max, s);
+        if (st) return st;
+    }
+    Scratch ctr;
+    if (!ctr.alloc(sizeof(unsigned int) * NXCD * CTR_STRIDE * (size_t)nc, s)) {
+        set_error("device allocation for queue counters failed");
+        return CAPT_ENOMEM;
+    }
+    for (int c = 0; c < nc; ++c) {
+        const int64_t np = poff[c + 1] - poff[c];
+        if (np <= 0) continue;
+        PosedSrc src{poses + 12 * poff[c], reinterpret_cast<const float4 *>(tmpl), g};
+        capt_status st = launch_slots(f->clouds[c].dev, src, np / edge, edge * g, out + poff[c] / edge,
+                                      ctr.as<unsigned int>() + (size_t)c * NXCD * CTR_STRIDE, s);
+        if (st) return st;
+    }
     return CAPT_OK;
 }
 

@@ -316,6 +316,43 @@ def posed_spheres(template: np.ndarray, n_cfg: int, box, seed: int,
     return out
 
 
+def _slerp(q0: np.ndarray, q1: np.ndarray, u: np.ndarray) -> np.ndarray:
+    d = np.sum(q0 * q1, axis=1, keepdims=True)
+    q1 = np.where(d < 0, -q1, q1)
+    d = np.abs(d)
+    th = np.arccos(np.clip(d, -1.0, 1.0))
+    s = np.sin(th)
+    small = s < 1e-9
+    a = np.where(small, 1.0 - u, np.sin((1.0 - u) * th) / np.where(small, 1.0, s))
+    b = np.where(small, u, np.sin(u * th) / np.where(small, 1.0, s))
+    q = a * q0 + b * q1
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def pose_edges(n_edges: int, steps: int, box, seed: int, reach: float = 0.4) -> np.ndarray:
+    """Motion edges of a rigid body: each edge runs from a pose (translation
+    uniform in `box`, rotation uniform) to a second pose whose translation is
+    within `reach` of the first and whose rotation is uniform, in `steps`
+    configurations (translation interpolated linearly, rotation by slerp,
+    endpoints included when steps > 1).  float64 arithmetic, rounded to float32
+    once.  float32 [n_edges * steps, 12]: rotation row-major, then translation."""
+    box = np.asarray(box, dtype=np.float64)
+    g = _rng(seed)
+    q0 = g.normal(size=(n_edges, 4))
+    q0 /= np.linalg.norm(q0, axis=1, keepdims=True)
+    q1 = g.normal(size=(n_edges, 4))
+    q1 /= np.linalg.norm(q1, axis=1, keepdims=True)
+    t0 = box[:, 0] + g.random((n_edges, 3)) * (box[:, 1] - box[:, 0])
+    t1 = np.clip(t0 + g.uniform(-reach, reach, (n_edges, 3)), box[:, 0], box[:, 1])
+    u = (np.arange(steps) / max(steps - 1, 1))[None, :, None]            # [1, steps, 1]
+    q = _slerp(np.repeat(q0, steps, 0), np.repeat(q1, steps, 0), np.tile(u[0], (n_edges, 1)))
+    t = (t0[:, None, :] * (1.0 - u) + t1[:, None, :] * u).reshape(-1, 3)
+    out = np.empty((n_edges * steps, 12), dtype=np.float32)
+    out[:, :9] = _quat_to_matrix(q).reshape(-1, 9)
+    out[:, 9:] = t
+    return out
+
+
 # ----------------------------------------------------------------------------
 # The five workloads
 # ----------------------------------------------------------------------------

@@ -477,3 +477,20 @@ def test_depth_frame_filter_and_build(capt, orc):
     sph = synth.uniform_spheres(60 * 2000, np.array([[-3.0, 3.0], [-3.0, 3.0], [0.0, 2.2]]), 0.015, 0.08, 7002)
     got = capt.capt_collides(f, dev(sph), 60).cpu().numpy()
     assert np.array_equal(got, orc.brute_f32(pts, sph, 60))
+
+
+@pytest.mark.parametrize("edge", [1, 4, 25])
+def test_posed_edges_match_oracle(capt, orc, edge):
+    """Posed template queries with edge-level early exit against the oracle's
+    posed spheres, and against capt_collides on the same spheres."""
+    pts = synth.tabletop_cloud(20_000, 71)
+    tmpl = synth.chain_template(2003).astype(np.float32)
+    poses = synth.pose_edges(3000 // edge, edge, synth.WORKSPACE, 72)
+    _say(f"case: posed edges edge={edge}")
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    got = capt.capt_collides_posed(f, dev(tmpl), dev(poses), edge).cpu().numpy()
+    sph = orc.pose_spheres(tmpl, poses)
+    want = orc.brute_f32(pts, sph, edge * len(tmpl))
+    assert np.array_equal(got, want)
+    assert np.array_equal(capt.capt_collides(f, dev(sph), edge * len(tmpl)).cpu().numpy(), want)
+    assert 0 < want.sum() < len(want) or edge > 1
