@@ -19,8 +19,9 @@ step (60,000,000 spheres / step time).  Printed as one JSON line, with:
   brute         the GPU brute force on the same spheres (answers compared)
 and, unless --no-extras, the batched ragged workload (64 clouds, one
 persistent launch vs one launch per cloud vs GPU brute force), the
-clearance forward/backward workload, and the per-frame rebuild latency
-(filter -> build) of a 307,200-point synthetic depth frame.
+clearance forward/backward workload, the per-frame rebuild latency
+(filter -> build) of a 307,200-point synthetic depth frame, and motion-edge
+validation with posed template spheres.
 """
 from __future__ import annotations
 
@@ -215,6 +216,43 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
         "forward_queries_per_s": m / (np.median(tf) * 1e-3),
         "backward_bytes_per_s": 48 * m / (np.median(tb) * 1e-3),
     }
+
+
+def bench_posed(capt, torch, forest, reps=5):
+    """Motion-edge validation: 100,000 edges of 10 rigid poses of the 60-sphere
+    template (translation within 0.4 m, rotation by slerp) on the tabletop
+    forest, posed on the fly (48 B per configuration), against the same
+    spheres materialised (960 B per configuration), answers compared."""
+    import oracle
+    import synth
+    tmpl = synth.chain_template(2003).astype(np.float32)
+    steps, n_edges = 10, 100_000
+    poses = synth.pose_edges(n_edges, steps, synth.WORKSPACE, 8002)
+    sph = torch.from_numpy(oracle.pose_spheres(tmpl, poses)).cuda()
+    pd, td = torch.from_numpy(poses).cuda(), torch.from_numpy(tmpl).cuda()
+    G = steps * len(tmpl)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    t_posed = timed(lambda: capt.capt_collides_posed(forest, td, pd, steps))
+    t_mat = timed(lambda: capt.capt_collides(forest, sph, G))
+    same = bool(torch.equal(capt.capt_collides_posed(forest, td, pd, steps), capt.capt_collides(forest, sph, G)))
+    hit = capt.capt_collides_posed(forest, td, pd, steps).float().mean().item()
+    return {"workload": "tabletop forest; 100,000 motion edges x 10 rigid poses of the 60-sphere template",
+            "edges": n_edges, "configurations": n_edges * steps, "edge_collision_rate": hit,
+            "posed_ms": t_posed, "materialised_ms": t_mat, "input_bytes_posed": int(poses.nbytes + tmpl.nbytes),
+            "input_bytes_materialised": int(sph.numel() * 4), "same_answers": same}
 
 
 def bench_frame(capt, torch, reps=10):
@@ -418,6 +456,10 @@ def main():
         log(f"clearance: {result['clearance']}")
         result["frame"] = bench_frame(capt, torch)
         log(f"frame: {result['frame']}")
+        f_posed = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+        result["posed"] = bench_posed(capt, torch, f_posed)
+        f_posed.close()
+        log(f"posed: {result['posed']}")
 
     if not args.no_cpu:
         cb, ref = cpu_baseline(w, G, min(args.cpu_sample, m // G))
