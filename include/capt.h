@@ -183,6 +183,14 @@ capt_status capt_clearance_backward(capt_forest f, const float *spheres,
 /* Release a forest's device memory (waits for the device first).  NULL is a no-op. */
 void capt_destroy(capt_forest f);
 
+/* Release a forest's device memory in stream order on `stream`, without
+ * waiting: the caller has ordered every use of the forest (its build, every
+ * query, clearance and stats call) on `stream` before this call, or made
+ * `stream` wait for them.  The handle is invalid on return.  A forest that
+ * holds a captured batched launch (a capt_collides call over several clouds)
+ * waits for the device first, as capt_destroy does.  NULL is a no-op. */
+void capt_destroy_async(capt_forest f, void *stream);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char *capt_last_error(void);
 

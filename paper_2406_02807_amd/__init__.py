@@ -27,7 +27,7 @@ CAPT_NO_GRAPH = 0x8
 
 EXPORTS = [
     "capt_filter", "capt_build", "capt_collides", "capt_clearance", "capt_clearance_backward",
-    "capt_destroy", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
+    "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
     "capt_get_tuning",
 ]
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
         fn.restype = C.c_int32
     lib.capt_destroy.argtypes = [P]
     lib.capt_destroy.restype = None
+    lib.capt_destroy_async.argtypes = [P, P]
+    lib.capt_destroy_async.restype = None
     lib.capt_last_error.argtypes = []
     lib.capt_last_error.restype = C.c_char_p
     _lib = lib
@@ -149,6 +151,13 @@ class Forest:
     def close(self):
         if self._h and self._h.value:
             load_library().capt_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def release(self, stream=None):
+        """Stream-ordered close: every use of the forest is already queued on
+        `stream` (default: the current stream); the host does not wait."""
+        if self._h and self._h.value:
+            load_library().capt_destroy_async(self._h, _stream(stream))
             self._h = C.c_void_p(0)
 
     def __del__(self):

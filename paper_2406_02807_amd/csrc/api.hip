@@ -79,6 +79,43 @@ void dev_free(void *p, hipStream_t s) {
     (void)hipFreeAsync(p, s);
 }
 
+namespace {
+std::mutex g_pinned_mu;
+std::vector<std::pair<size_t, void *>> g_pinned_free;   // (size class, block)
+size_t pinned_class(size_t b) {
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+}  // namespace
+
+void *pinned_acquire(size_t bytes) {
+    const size_t c = pinned_class(bytes);
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        for (size_t i = 0; i < g_pinned_free.size(); ++i)
+            if (g_pinned_free[i].first == c) {
+                void *p = g_pinned_free[i].second;
+                g_pinned_free[i] = g_pinned_free.back();
+                g_pinned_free.pop_back();
+                return p;
+            }
+    }
+    // coherent: kernel stores reach host memory without a cache flush
+    void *p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void pinned_release(void *p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_pinned_free.emplace_back(pinned_class(bytes), p);
+}
+
 const DeviceInfo &device_info() {
     static DeviceInfo info;
     static std::once_flag once;
@@ -152,8 +189,21 @@ void destroy_forest(capt_forest_s *f) {
     if (!f) return;
     (void)hipDeviceSynchronize();
     free_plan(f->plan);
-    for (auto &c : f->clouds) free_cloud(c);
+    for (auto &c : f->clouds) free_cloud(c, nullptr);
     if (f->d_clouds) dev_free(f->d_clouds, nullptr);
+    delete f;
+}
+
+// Stream-ordered release: the memory returns to the allocator behind the
+// work already queued on s, so the host does not wait.
+void destroy_forest_async(capt_forest_s *f, hipStream_t s) {
+    if (!f) return;
+    if (f->plan) {
+        destroy_forest(f);
+        return;
+    }
+    for (auto &c : f->clouds) free_cloud(c, s);
+    if (f->d_clouds) dev_free(f->d_clouds, s);
     delete f;
 }
 
@@ -391,6 +441,8 @@ capt_status capt_clearance_backward(capt_forest f, const float *spheres, const i
 }
 
 void capt_destroy(capt_forest f) { destroy_forest(f); }
+
+void capt_destroy_async(capt_forest f, void *stream) { destroy_forest_async(f, static_cast<hipStream_t>(stream)); }
 
 capt_status capt_forest_info(capt_forest f, int32_t cloud, int64_t *n, int32_t *D, int64_t *set_total,
                              int64_t *pruned, int64_t *bytes) {

@@ -34,7 +34,7 @@ namespace {
 constexpr int TB = 256;
 constexpr int LMAX = 2048;   // subtree size finished in LDS
 constexpr int LMAX_LOG2 = 11;
-constexpr int LTB = 1024;    // threads of the LDS levels kernel
+constexpr int LTB = 512;     // threads of the LDS levels kernel (8 waves, so a block fits beside a running query)
 constexpr int AU = 2;        // 64-candidate steps in flight in the affordance kernels
 constexpr int GTILE = 2048;  // tile of the global partition passes
 
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(LTB) k_local_levels(const uint32_t *__restrict
         __syncthreads();
         for (int b = 1; b <= 2; ++b) {
             uint16_t *lb = lst[(a + b) % 3];
-            // exclusive scan of flags over the S0 positions (8 per thread)
+            // exclusive scan of flags over the S0 positions (a run per thread)
             const int per = (S0 + LTB - 1) / LTB;
             const int k0 = threadIdx.x * per;
             uint32_t c = 0;
@@ -753,6 +753,16 @@ __global__ void __launch_bounds__(TB) k_sum_partials(const unsigned long long *_
     }
 }
 
+// A cloud's totals and its error word into the caller's pinned host words
+// (one thread; every earlier kernel of the cloud has finished by then).
+__global__ void k_publish(const unsigned long long *__restrict__ totals, const uint32_t *__restrict__ errw,
+                          unsigned long long *__restrict__ host) {
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) host[k] = totals[k];
+        host[4] = *errw;
+    }
+}
+
 inline unsigned nblk(int64_t n, int tb = TB) { return (unsigned)((n + tb - 1) / tb); }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1007,9 +1017,9 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
 
 }  // namespace
 
-void free_cloud(CloudHost &c) {
-    if (c.fixed) dev_free(c.fixed, nullptr);
-    if (c.sets) dev_free(c.sets, nullptr);
+void free_cloud(CloudHost &c, hipStream_t s) {
+    if (c.fixed) dev_free(c.fixed, s);
+    if (c.sets) dev_free(c.sets, s);
     c.fixed = c.sets = nullptr;
 }
 
@@ -1039,15 +1049,29 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
         capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, s, f->clouds[c], work[c]);
         if (st) return st;
     }
-    // one device-to-host read of every cloud's totals
-    std::vector<unsigned long long> tot(4 * (size_t)ncloud);
-    std::vector<uint32_t> sort_err((size_t)ncloud);
-    for (int c = 0; c < ncloud; ++c) {
-        CAPT_HIP(hipMemcpyAsync(&tot[4 * c], work[c].totals, sizeof(unsigned long long) * 4,
-                                hipMemcpyDeviceToHost, s));
-        CAPT_HIP(hipMemcpyAsync(&sort_err[c], work[c].rad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // every cloud's totals and error word straight into pinned host memory,
+    // then one wait
+    Pinned res;
+    if (!res.alloc(sizeof(unsigned long long) * 5 * (size_t)ncloud)) {
+        set_error("pinned host allocation failed");
+        return CAPT_ENOMEM;
     }
-    CAPT_HIP(hipStreamSynchronize(s));
+    unsigned long long *hw = res.as<unsigned long long>();
+    for (int c = 0; c < ncloud; ++c) {
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(WAVE), 0, s, work[c].totals, work[c].rad, hw + 5 * c);
+        CAPT_LAUNCH_CHECK();
+    }
+    const hipError_t se = hipStreamSynchronize(s);
+    if (se != hipSuccess) {
+        res.p = nullptr;   // the kernels' state is unknown: never hand the block out again
+        return hip_fail(se, "hipStreamSynchronize", __FILE__, __LINE__);
+    }
+    std::vector<unsigned long long> tot(4 * (size_t)ncloud);
+    std::vector<unsigned long long> sort_err((size_t)ncloud);
+    for (int c = 0; c < ncloud; ++c) {
+        for (int k = 0; k < 4; ++k) tot[4 * c + k] = hw[5 * c + k];
+        sort_err[c] = hw[5 * c + 4];
+    }
     for (int c = 0; c < ncloud; ++c)
         if (sort_err[c]) {
             set_error("internal: radix sort look-back bound exceeded while building cloud %d", c);

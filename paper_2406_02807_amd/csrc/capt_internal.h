@@ -89,6 +89,29 @@ struct Scratch {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host memory for the few words a call reads back before it returns:
+// the last kernel of the call stores them straight into this memory and the
+// host waits on the stream, with no copy.  Blocks come from a process-wide
+// cache (allocated once, kept until the process ends).
+void *pinned_acquire(size_t bytes);
+void pinned_release(void *p, size_t bytes);
+struct Pinned {
+    void *p = nullptr;
+    size_t n = 0;
+    Pinned() = default;
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
+    ~Pinned() {
+        if (p) pinned_release(p, n);
+    }
+    bool alloc(size_t bytes) {
+        n = bytes;
+        p = pinned_acquire(bytes);
+        return p != nullptr;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
 // Device properties used for launch planning.
 struct DeviceInfo {
     int cus = 256;
@@ -171,7 +194,7 @@ namespace capt {
 capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                          float r_min, float r_max, uint32_t flags, hipStream_t s,
                          capt_forest_s *f);
-void free_cloud(CloudHost &c);
+void free_cloud(CloudHost &c, hipStream_t s);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)
 // Bounding box of every CHUNK-entry chunk of the stored sets (padding skipped).

@@ -44,7 +44,6 @@ struct FState {
     double scale;
     int64_t mm[2];      // mm[0]: survivors of the last pass (n until it ends)
     unsigned int bad;   // non-finite coordinates
-    unsigned int err;   // copy of the internal wait-bound error word
 };
 
 constexpr int BB_BLOCKS = 64;   // partial bounding boxes
@@ -141,7 +140,6 @@ __global__ void k_grid(const float *__restrict__ part, const unsigned int *__res
     st->mm[0] = n;
     st->mm[1] = 0;
     st->bad = bad;
-    st->err = 0;
 }
 
 // Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
@@ -427,11 +425,18 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     }
 }
 
+// Gathers the survivors; the first thread also stores the survivor count,
+// the non-finite count and the error word into the caller's pinned host
+// words (every earlier kernel of the call has finished by then).
 __global__ void k_output(const float *__restrict__ xyz, const uint32_t *__restrict__ cur, int64_t n,
-                         FState *__restrict__ st, const uint32_t *__restrict__ errw, float *__restrict__ out_xyz,
-                         int32_t *__restrict__ out_index) {
+                         const FState *__restrict__ st, const uint32_t *__restrict__ errw, float *__restrict__ out_xyz,
+                         int32_t *__restrict__ out_index, unsigned long long *__restrict__ host) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) st->err = *errw;   // one copy to the host carries everything
+    if (j == 0) {
+        host[0] = (unsigned long long)st->mm[0];
+        host[1] = st->bad;
+        host[2] = *errw;
+    }
     if (j >= n || j >= st->mm[0]) return;
     const uint32_t id = cur[j];
     out_xyz[3 * j] = xyz[3 * (int64_t)id];
@@ -475,6 +480,11 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
         set_error("device allocation of %zu filter scratch bytes failed", off);
         return CAPT_ENOMEM;
     }
+    Pinned res;
+    if (!res.alloc(3 * sizeof(unsigned long long))) {
+        set_error("pinned host allocation failed");
+        return CAPT_ENOMEM;
+    }
     char *B = sc.as<char>();
     FState *st = reinterpret_cast<FState *>(B + oSt);
     uint32_t *cur = reinterpret_cast<uint32_t *>(B + oCur);
@@ -515,20 +525,24 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
                                (int)(p == NP - 1), pp, pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index);
+    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index,
+                       res.as<unsigned long long>());
     CAPT_LAUNCH_CHECK();
-    FState h;
-    CAPT_HIP(hipMemcpyAsync(&h, st, sizeof(FState), hipMemcpyDeviceToHost, s));
-    CAPT_HIP(hipStreamSynchronize(s));
-    if (h.err) {
-        set_error("internal: a look-back wait bound was exceeded in the filter (code %u)", h.err);
+    const hipError_t se = hipStreamSynchronize(s);
+    if (se != hipSuccess) {
+        res.p = nullptr;   // the kernel's state is unknown: never hand the block out again
+        return hip_fail(se, "hipStreamSynchronize", __FILE__, __LINE__);
+    }
+    const unsigned long long *h = res.as<unsigned long long>();
+    if (h[2]) {
+        set_error("internal: a look-back wait bound was exceeded in the filter (code %llu)", h[2]);
         return CAPT_EHIP;
     }
-    if (h.bad) {
-        set_error("input holds %u non-finite coordinates", h.bad);
+    if (h[1]) {
+        set_error("input holds %llu non-finite coordinates", h[1]);
         return CAPT_EINVAL;
     }
-    *n_out = h.mm[0];
+    *n_out = (int64_t)h[0];
     return CAPT_OK;
 }
 

@@ -160,6 +160,24 @@ def test_collides_groups_tabletop(capt, orc, g):
     assert 0 < want.sum() <= len(want)
 
 
+def test_stream_ordered_release(capt, orc):
+    # per-frame pattern: build, query and release in stream order without a
+    # host wait; later builds reuse the released memory behind earlier queries
+    _say("case: stream-ordered release, 4 frames of tabletop-6k")
+    sph = synth.posed_spheres(synth.chain_template(2003), 800, synth.WORKSPACE, 95)
+    sd = dev(sph)
+    outs, clouds = [], []
+    for k in range(4):
+        pts = synth.tabletop_cloud(6000, 120 + k)
+        f = capt.capt_build(dev(pts), 0.015, 0.08)
+        outs.append(capt.capt_collides(f, sd, 60))
+        f.release()
+        clouds.append(pts)
+    torch.cuda.synchronize()
+    for pts, o in zip(clouds, outs):
+        assert np.array_equal(o.cpu().numpy(), orc.brute_f32(pts, sph, 60))
+
+
 def test_check_radii_flag(capt):
     pts = synth.tabletop_cloud(2000, 5)
     f = capt.capt_build(dev(pts), 0.015, 0.08)
