@@ -32,8 +32,8 @@ namespace capt {
 namespace {
 
 constexpr int TB = 256;
-constexpr int LMAX = 2048;   // subtree size finished in LDS
-constexpr int LMAX_LOG2 = 11;
+constexpr int LMAX = 1024;   // subtree size finished in LDS (27 KB, so a block fits beside a running query)
+constexpr int LMAX_LOG2 = 10;
 constexpr int LTB = 512;     // threads of the LDS levels kernel (8 waves, so a block fits beside a running query)
 constexpr int AU = 2;        // 64-candidate steps in flight in the affordance kernels
 constexpr int GTILE = 2048;  // tile of the global partition passes
