@@ -19,7 +19,10 @@ Functions and what they follow:
   build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning
   query            CollisionCheck (Alg. 3, Sec. IV-D) on a tree given as arrays
   morton_key       Z-order key (Sec. II-B, Sec. IV-C)
-  filter           Filter (Alg. 2, Sec. IV-C)
+  filter           Filter (Alg. 2, Sec. IV-C), optionally after crop
+  crop             reach crop for fixed-base arms (Sec. IV-C)
+  pad_radii        query padding r + r_filter (Sec. V-B, after the filter
+                   lemma)
 """
 from __future__ import annotations
 
@@ -97,8 +100,18 @@ def sqdist_f32(a, b) -> np.float32:
     return np.float32(_load().orc_sqdist_f32(_p(a), _p(b)))
 
 
-def brute_f32(points, spheres, group: int = 1) -> np.ndarray:
+def pad_radii(spheres, pad: float) -> np.ndarray:
+    """Query padding (Sec. V-B, after the filter lemma): every radius r
+    becomes r + pad, one float32 addition."""
+    sph = _f32(spheres, 4).copy()
+    sph[:, 3] = sph[:, 3] + np.float32(pad)
+    return sph
+
+
+def brute_f32(points, spheres, group: int = 1, pad: float = 0.0) -> np.ndarray:
     pts, sph = _f32(points, 3), _f32(spheres, 4)
+    if pad:
+        sph = pad_radii(sph, pad)
     assert len(sph) % group == 0
     out = np.zeros(len(sph) // group, dtype=np.uint8)
     _load().orc_brute_f32(_p(pts), len(pts), _p(sph), len(sph), group, _p(out))
@@ -238,9 +251,28 @@ def morton_cell(p, lo, scale: float) -> np.ndarray:
     return q
 
 
-def filter(points, r_filter: float, npass: int = 6):  # noqa: A001
+def crop(points, base, reach: float) -> np.ndarray:
+    """Reach crop for a fixed-base arm (Sec. IV-C): indices, in input order,
+    of the points whose float32 squared distance to the base,
+    ((dx*dx + dy*dy) + dz*dz) with every operation rounded on its own, is at
+    most fl(reach * reach).  Non-finite points fail the test."""
+    pts = _f32(points, 3)
+    b = np.asarray(base, dtype=np.float32).reshape(3)
+    with np.errstate(invalid="ignore", over="ignore"):
+        d = pts - b
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        keep = d2 <= np.float32(reach) * np.float32(reach)
+    return np.nonzero(keep)[0].astype(np.int32)
+
+
+def filter(points, r_filter: float, npass: int = 6, base=None, reach=None):  # noqa: A001
     """Filter (Alg. 2).  Returns (kept original indices in final order,
-    counts after each pass)."""
+    counts after each pass).  With base and reach, the reach crop runs first
+    and the filter sees only the cropped points, in input order."""
+    if base is not None:
+        keep = crop(points, base, reach)
+        idx, counts = filter(_f32(points, 3)[keep], r_filter, npass)
+        return keep[idx].astype(np.int32), counts
     pts = _f32(points, 3)
     out = np.zeros(max(len(pts), 1), dtype=np.int32)
     counts = np.zeros(npass, dtype=np.int64)
