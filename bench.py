@@ -283,9 +283,18 @@ def bench_frame(capt, torch, reps=10):
             tb.append(b.elapsed_time(c))
             info = f.info()
             f.close()
+        # the same frame through the one-call filter + build
+        tfu = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f = capt.capt_build_filtered(xyz, rf, 0.015, 0.08)
+            torch.cuda.synchronize()
+            tfu.append((time.perf_counter() - t0) * 1e3)
+            f.close()
         rows.append({"r_filter": rf, "points_after_filter": int(fx.shape[0]),
                      "set_entries": info["set_total"], "filter_ms": float(np.median(tf)),
                      "build_ms": float(np.median(tb)), "frame_ms_wall": float(np.median(tw)),
+                     "frame_ms_wall_one_call": float(np.median(tfu)),
                      "budget_60hz_ms": 1000.0 / 60.0})
     return {"workload": "one 640 x 480 synthetic depth frame of the tabletop scene in a 6 x 6 x 3 m room "
                         "(307,200 points, depth noise 0.001 m x depth^2), r_min = 0.015, r_max = 0.08",
@@ -389,8 +398,7 @@ def main():
 
     def piped_step(prev, qev=None):
         with torch.cuda.stream(s_build):
-            fx, _ = capt.capt_filter(xyz, w.r_filter)
-            f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+            f = capt.capt_build_filtered(xyz, w.r_filter, w.r_min, w.r_max)
             ready = torch.cuda.Event()
             ready.record(s_build)
         s_query.wait_event(ready)
@@ -404,18 +412,18 @@ def main():
                 qev.append(e)
             if prev is not None:
                 prev.release()
-        return f, fx
+        return f
 
     forest = None
     for _ in range(args.warmup):
-        forest, fx = piped_step(forest)
+        forest = piped_step(forest)
     torch.cuda.synchronize()
     out.zero_()
     torch.cuda.synchronize()
     qev = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        forest, fx = piped_step(forest, qev)
+        forest = piped_step(forest, qev)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_step = t_total / args.steps * 1e3

@@ -79,6 +79,22 @@ capt_status capt_filter(const float *xyz, int64_t n, float r_filter,
                         void *stream);
 
 /*
+ * Filter with a reach crop for a fixed-base arm (Sec. IV-C): a point can only
+ * touch the robot if it lies within the arm's reach of its base, so points
+ * farther away are removed first and capt_filter runs on the rest, in input
+ * order (the Morton grid is over the cropped points).  A point stays iff it
+ * is finite and ((dx*dx + dy*dy) + dz*dz) <= fl(reach * reach) in float32,
+ * every operation rounded on its own, d = point - base.  The caller folds any
+ * margin (link and sphere radii) into reach.
+ *   crop       host [4]: base x, y, z (finite), reach (>= 0, may be +inf)
+ *   others     as capt_filter; out_index holds input indices
+ * n must be below 2^30.  Synchronises on `stream` twice.
+ */
+capt_status capt_filter_crop(const float *xyz, int64_t n, float r_filter,
+                             const float *crop, float *out_xyz,
+                             int32_t *out_index, int64_t *n_out, void *stream);
+
+/*
  * Construct (Alg. 1, Sec. IV-A/B) for `ncloud` independent clouds.
  *   xyz        [sum n_c][3] points of all clouds back to back (finite)
  *   cloud_off  host [ncloud + 1]; cloud c is xyz[cloud_off[c] .. cloud_off[c+1])
@@ -106,6 +122,26 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
                        capt_forest *out);
 
 /*
+ * Per-frame rebuild (Sec. IV-C followed by Sec. IV-A/B): capt_filter (or,
+ * with crop, capt_filter_crop) of one cloud, then capt_build of the kept
+ * points, in one call with no host work between the two.  The forest equals
+ * capt_build's on the filter's output.
+ *   xyz, n, r_filter   as capt_filter
+ *   crop       host [4] as capt_filter_crop, or NULL for no crop
+ *   r_min, r_max, flags as capt_build (one cloud)
+ *   kept_index [n] capacity or NULL; original index of each kept point, in the
+ *              order the forest was built from
+ *   n_kept     host or NULL; number of kept points
+ *   out        host; receives the forest
+ * Synchronises on `stream` twice (the kept count, then the set sizes), or
+ * three times with a crop.
+ */
+capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter,
+                                const float *crop, float r_min, float r_max, uint32_t flags,
+                                int32_t *kept_index, int64_t *n_kept,
+                                void *stream, capt_forest *out);
+
+/*
  * CollisionCheck (Alg. 3, Sec. IV-D) with configuration-level early exit.
  *   f          forest from capt_build / capt_import
  *   spheres    [M][4]; the spheres of cloud c are
@@ -124,6 +160,20 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
  */
 capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *query_off,
                           int32_t group, uint8_t *out, uint32_t flags, void *stream);
+
+/*
+ * capt_collides with query padding (Sec. V-B, after the filter lemma): every
+ * radius r becomes fl(r + pad) before the test, so that a forest built from a
+ * filtered cloud answers conservatively (pad = r_filter per filter pass that
+ * removed points: a dropped point lies within r_filter of a point its pass
+ * kept).  Every padded radius must lie in [r_min, r_max] of the forest
+ * (CAPT_CHECK_RADII validates that).  Same arguments as capt_collides; pad is
+ * finite and >= 0; flags: 0 or CAPT_CHECK_RADII.  Forests of several clouds
+ * take one launch per cloud.
+ */
+capt_status capt_collides_padded(capt_forest f, const float *spheres,
+                                 const int64_t *query_off, int32_t group, float pad,
+                                 uint8_t *out, uint32_t flags, void *stream);
 
 /*
  * CollisionCheck (Alg. 3) on robot configurations given as rigid poses of one

@@ -26,7 +26,8 @@ CAPT_PER_CLOUD = 0x4
 CAPT_NO_GRAPH = 0x8
 
 EXPORTS = [
-    "capt_filter", "capt_build", "capt_collides", "capt_clearance", "capt_clearance_backward",
+    "capt_filter", "capt_filter_crop", "capt_build", "capt_build_filtered", "capt_collides",
+    "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
     "capt_get_tuning",
@@ -60,6 +61,9 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "capt_filter": [P, i64, f32, P, P, P, P],
         "capt_build": [P, P, i32, f32, f32, u32, P, P],
+        "capt_build_filtered": [P, i64, f32, P, f32, f32, u32, P, P, P, P],
+        "capt_filter_crop": [P, i64, f32, P, P, P, P, P],
+        "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
         "capt_collides": [P, P, P, i32, P, u32, P],
         "capt_clearance": [P, P, P, P, P, P],
         "capt_clearance_backward": [P, P, P, P, P, P, P],
@@ -170,8 +174,15 @@ class Forest:
 # ---------------------------------------------------------------------------
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
-def capt_filter(xyz, r_filter: float, stream=None):
-    """Alg. 2: returns (kept points [n', 3], original indices [n'])."""
+def _crop_arg(base, reach):
+    if base is None:
+        return None
+    return (C.c_float * 4)(*[float(v) for v in base], float(reach))
+
+
+def capt_filter(xyz, r_filter: float, base=None, reach=None, stream=None):
+    """Alg. 2: returns (kept points [n', 3], original indices [n']).  With
+    base (x, y, z) and reach, the reach crop runs first (capt_filter_crop)."""
     import torch
     lib = load_library()
     xyz = _dev(xyz, torch.float32, 3, "xyz")
@@ -179,8 +190,13 @@ def capt_filter(xyz, r_filter: float, stream=None):
     out = torch.empty((max(n, 1), 3), dtype=torch.float32, device=xyz.device)
     idx = torch.empty((max(n, 1),), dtype=torch.int32, device=xyz.device)
     n_out = C.c_int64()
-    _check(lib.capt_filter(_ptr(xyz), n, float(r_filter), _ptr(out), _ptr(idx), C.byref(n_out),
-                           _stream(stream)))
+    crop = _crop_arg(base, reach)
+    if crop is None:
+        _check(lib.capt_filter(_ptr(xyz), n, float(r_filter), _ptr(out), _ptr(idx), C.byref(n_out),
+                               _stream(stream)))
+    else:
+        _check(lib.capt_filter_crop(_ptr(xyz), n, float(r_filter), crop, _ptr(out), _ptr(idx),
+                                    C.byref(n_out), _stream(stream)))
     k = n_out.value
     return out[:k], idx[:k]
 
@@ -204,6 +220,24 @@ def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=No
                   clouds=(xyz, off))
 
 
+def capt_build_filtered(xyz, r_filter: float, r_min: float, r_max: float, prune: bool = True,
+                        kept_index: bool = False, base=None, reach=None, stream=None):
+    """Filter (Alg. 2) then build (Alg. 1) of one cloud in one library call.
+    Returns the forest, or (forest, kept original indices [n']) with kept_index."""
+    import torch
+    lib = load_library()
+    xyz = _dev(xyz, torch.float32, 3, "xyz")
+    n = xyz.shape[0]
+    idx = torch.empty((max(n, 1),), dtype=torch.int32, device=xyz.device) if kept_index else None
+    h = C.c_void_p()
+    m = C.c_int64()
+    _check(lib.capt_build_filtered(_ptr(xyz), n, float(r_filter), _crop_arg(base, reach), float(r_min), float(r_max),
+                                   0 if prune else CAPT_NO_PRUNE, _ptr(idx),
+                                   C.byref(m), _stream(stream), C.byref(h)))
+    f = Forest(h.value, 1, float(np.float32(r_min)), float(np.float32(r_max)))
+    return (f, idx[:m.value]) if kept_index else f
+
+
 def capt_collides(forest: Forest, spheres, group: int = 1, query_off=None, flags: int = 0,
                   out=None, stream=None):
     """Alg. 3 with configuration-level early exit: uint8 [M / group]."""
@@ -220,6 +254,25 @@ def capt_collides(forest: Forest, spheres, group: int = 1, query_off=None, flags
         out = torch.empty((M // group,), dtype=torch.uint8, device=spheres.device)
     _check(lib.capt_collides(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
                              _ptr(out), flags, _stream(stream)))
+    return out
+
+
+def capt_collides_padded(forest: Forest, spheres, group: int, pad: float, query_off=None, flags: int = 0,
+                         out=None, stream=None):
+    """capt_collides with every radius r replaced by r + pad (query padding)."""
+    import torch
+    lib = load_library()
+    spheres = _dev(spheres, torch.float32, 4, "spheres")
+    M = spheres.shape[0]
+    if query_off is None:
+        if forest.ncloud != 1:
+            raise ValueError("query_off is required for a forest of several clouds")
+        query_off = [0, M]
+    off = _offsets(query_off, forest.ncloud)
+    if out is None:
+        out = torch.empty((M // group,), dtype=torch.uint8, device=spheres.device)
+    _check(lib.capt_collides_padded(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
+                                    float(pad), _ptr(out), flags, _stream(stream)))
     return out
 
 

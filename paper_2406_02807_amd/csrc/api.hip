@@ -1,5 +1,6 @@
 // C ABI of the CAPT library: argument checks, error state, allocator hooks,
 // forest lifetime, import/export, and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -310,7 +311,46 @@ capt_status capt_filter(const float *xyz, int64_t n, float r_filter, float *out_
         set_error("cloud of %lld points exceeds 2^31", (long long)n);
         return CAPT_EUNSUPPORTED;
     }
-    return filter(xyz, n, r_filter, out_xyz, out_index, n_out, (hipStream_t)stream);
+    return filter(xyz, n, r_filter, nullptr, out_xyz, out_index, n_out, (hipStream_t)stream);
+}
+
+namespace {
+capt_status check_crop(const float *crop) {
+    if (!crop) {
+        set_error("crop is NULL");
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(crop[0]) || !finite_f(crop[1]) || !finite_f(crop[2]) || std::isnan(crop[3]) || !(crop[3] >= 0.0f)) {
+        set_error("crop base (%g, %g, %g) must be finite and reach %g >= 0", (double)crop[0], (double)crop[1],
+                  (double)crop[2], (double)crop[3]);
+        return CAPT_EINVAL;
+    }
+    return CAPT_OK;
+}
+}  // namespace
+
+capt_status capt_filter_crop(const float *xyz, int64_t n, float r_filter, const float *crop, float *out_xyz,
+                             int32_t *out_index, int64_t *n_out, void *stream) {
+    ApiGuard g;
+    if (!n_out) {
+        set_error("n_out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (n < 0 || (n > 0 && (!xyz || !out_xyz))) {
+        set_error("bad cloud arguments (n = %lld)", (long long)n);
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(r_filter) || !(r_filter >= 0.0f)) {
+        set_error("r_filter = %g must be finite and >= 0", (double)r_filter);
+        return CAPT_EINVAL;
+    }
+    capt_status st = check_crop(crop);
+    if (st) return st;
+    if (n >= ((int64_t)1 << 30)) {
+        set_error("cropped filter of %lld points exceeds 2^30", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    return filter(xyz, n, r_filter, crop, out_xyz, out_index, n_out, (hipStream_t)stream);
 }
 
 capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
@@ -354,6 +394,66 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
     return CAPT_OK;
 }
 
+capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, const float *crop, float r_min,
+                                float r_max, uint32_t flags, int32_t *kept_index, int64_t *n_kept, void *stream,
+                                capt_forest *out) {
+    ApiGuard g;
+    if (!out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    *out = nullptr;
+    if (n < 0 || (n > 0 && !xyz)) {
+        set_error("bad cloud arguments (n = %lld)", (long long)n);
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(r_filter) || !(r_filter >= 0.0f)) {
+        set_error("r_filter = %g must be finite and >= 0", (double)r_filter);
+        return CAPT_EINVAL;
+    }
+    if (crop) {
+        capt_status cs = check_crop(crop);
+        if (cs) return cs;
+    }
+    if (n >= ((int64_t)1 << (crop ? 30 : 31))) {
+        set_error("cloud of %lld points exceeds the filter's limit", (long long)n);
+        return CAPT_EUNSUPPORTED;
+    }
+    if (!finite_f(r_min) || !finite_f(r_max) || !(r_min >= 0.0f) || !(r_max > 0.0f) || r_min > r_max) {
+        set_error("radii r_min = %g, r_max = %g must satisfy 0 <= r_min <= r_max, r_max > 0", (double)r_min,
+                  (double)r_max);
+        return CAPT_EINVAL;
+    }
+    if (flags & ~CAPT_NO_PRUNE) {
+        set_error("unknown build flags 0x%x", flags);
+        return CAPT_EINVAL;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    // the kept points live in stream-ordered scratch: the build copies them
+    Scratch kept;
+    if (!kept.alloc(sizeof(float) * 3 * (size_t)std::max<int64_t>(n, 1), s)) {
+        set_error("device allocation of the kept points failed");
+        return CAPT_ENOMEM;
+    }
+    int64_t m = 0;
+    capt_status st = filter(xyz, n, r_filter, crop, kept.as<float>(), kept_index, &m, s);
+    if (st) return st;
+    if (n_kept) *n_kept = m;
+    capt_forest_s *f = new (std::nothrow) capt_forest_s();
+    if (!f) {
+        set_error("host allocation failed");
+        return CAPT_ENOMEM;
+    }
+    const int64_t off[2] = {0, m};
+    st = build_forest(kept.as<float>(), off, 1, r_min, r_max, flags, s, f);
+    if (st) {
+        destroy_forest(f);
+        return st;
+    }
+    *out = f;
+    return CAPT_OK;
+}
+
 capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
                           uint8_t *out, uint32_t flags, void *stream) {
     ApiGuard g;
@@ -370,6 +470,28 @@ capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *qu
     }
     if (M == 0) return CAPT_OK;
     return collides(f, spheres, query_off, group, out, flags, (hipStream_t)stream);
+}
+
+capt_status capt_collides_padded(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
+                                 float pad, uint8_t *out, uint32_t flags, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, group);
+    if (st) return st;
+    if (flags & ~CAPT_CHECK_RADII) {
+        set_error("unknown padded query flags 0x%x", flags);
+        return CAPT_EINVAL;
+    }
+    if (!finite_f(pad) || !(pad >= 0.0f)) {
+        set_error("pad = %g must be finite and >= 0", (double)pad);
+        return CAPT_EINVAL;
+    }
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && !out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (M == 0) return CAPT_OK;
+    return collides_padded(f, spheres, query_off, group, pad, out, flags, (hipStream_t)stream);
 }
 
 capt_status capt_collides_posed(capt_forest f, const float *tmpl, int32_t g, const float *poses,

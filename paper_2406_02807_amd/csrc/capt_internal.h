@@ -216,7 +216,9 @@ capt_status chunk_stats(capt_forest_s *f, const float *spheres, const int64_t *q
 capt_status bruteforce(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                        const float *spheres, const int64_t *query_off, int32_t group,
                        uint8_t *out, hipStream_t s);
-capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s);
+capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s, float pad = 0.0f);
+capt_status collides_padded(capt_forest_s *f, const float *spheres, const int64_t *query_off, int32_t group, float pad,
+                            uint8_t *out, uint32_t flags, hipStream_t s);
 void free_plan(BatchPlan *p);
 capt_tuning &tuning();
 
@@ -228,7 +230,8 @@ capt_status clearance_bwd(capt_forest_s *f, const float *spheres, const int64_t 
                           hipStream_t s);
 
 // filter.hip
-capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz,
+// crop: host [4] (base x, y, z, reach) or NULL
+capt_status filter(const float *xyz, int64_t n, float r_filter, const float *crop, float *out_xyz,
                    int32_t *out_index, int64_t *n_out, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,7 @@
 // next pass's liveness flags.  The last pass also writes its survivors in
 // order, at offsets found by decoupled look-back over earlier chunks' counts.
 // Only the final count crosses to the host.
+#include <algorithm>
 #include <cmath>
 
 #include "capt_internal.h"
@@ -430,7 +431,8 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
 // words (every earlier kernel of the call has finished by then).
 __global__ void k_output(const float *__restrict__ xyz, const uint32_t *__restrict__ cur, int64_t n,
                          const FState *__restrict__ st, const uint32_t *__restrict__ errw, float *__restrict__ out_xyz,
-                         int32_t *__restrict__ out_index, unsigned long long *__restrict__ host) {
+                         int32_t *__restrict__ out_index, const uint32_t *__restrict__ map,
+                         unsigned long long *__restrict__ host) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j == 0) {
         host[0] = (unsigned long long)st->mm[0];
@@ -442,13 +444,60 @@ __global__ void k_output(const float *__restrict__ xyz, const uint32_t *__restri
     out_xyz[3 * j] = xyz[3 * (int64_t)id];
     out_xyz[3 * j + 1] = xyz[3 * (int64_t)id + 1];
     out_xyz[3 * j + 2] = xyz[3 * (int64_t)id + 2];
-    if (out_index) out_index[j] = (int32_t)id;
+    if (out_index) out_index[j] = (int32_t)(map ? map[id] : id);
+}
+
+// Zero n words (the crop's counters and the scan's status words).
+__global__ void k_zero_words(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// Reach crop: flag[j] = 1 iff point j is finite and its float32 squared
+// distance to the base is at most reach2; non-finite coordinates are counted
+// into *bad (zeroed beforehand).
+__global__ void k_crop_flag(const float *__restrict__ xyz, int64_t n, float bx, float by, float bz, float reach2,
+                            uint32_t *__restrict__ flag, unsigned int *__restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = t; j < n; j += stride) {
+        const float x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+        const unsigned int nb = (unsigned int)!isfinite(x) + (unsigned int)!isfinite(y) + (unsigned int)!isfinite(z);
+        if (nb) atomicAdd(bad, nb);
+        flag[j] = (nb == 0 && sqdist(x, y, z, bx, by, bz) <= reach2) ? 1u : 0u;
+    }
+}
+
+// Stable compaction of the cropped points (pos = exclusive scan of flag);
+// map[k] = input index of compacted point k.  The last thread stores the
+// count, the non-finite count and the scan's error word into the caller's
+// pinned host words.
+__global__ void k_crop_compact(const float *__restrict__ xyz, int64_t n, const uint32_t *__restrict__ flag,
+                               const uint32_t *__restrict__ pos, float *__restrict__ cxyz, uint32_t *__restrict__ map,
+                               const unsigned int *__restrict__ bad, const uint32_t *__restrict__ errw,
+                               unsigned long long *__restrict__ host) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t k = pos[j];
+    if (flag[j]) {
+        cxyz[3 * (int64_t)k] = xyz[3 * j];
+        cxyz[3 * (int64_t)k + 1] = xyz[3 * j + 1];
+        cxyz[3 * (int64_t)k + 2] = xyz[3 * j + 2];
+        map[k] = (uint32_t)j;
+    }
+    if (j == n - 1) {
+        host[0] = (unsigned long long)(k + flag[j]);
+        host[1] = *bad;
+        host[2] = *errw;
+    }
 }
 
 }  // namespace
 
-capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, int32_t *out_index,
-                   int64_t *n_out, hipStream_t s) {
+namespace {
+
+capt_status filter_core(const float *xyz, int64_t n, float r_filter, const uint32_t *map, float *out_xyz,
+                        int32_t *out_index, int64_t *n_out, hipStream_t s) {
     if (n == 0) {
         *n_out = 0;
         return CAPT_OK;
@@ -525,7 +574,7 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
                                (int)(p == NP - 1), pp, pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         CAPT_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index,
+    hipLaunchKernelGGL(k_output, dim3(nblk(n)), dim3(TB), 0, s, xyz, cur, n, st, rad, out_xyz, out_index, map,
                        res.as<unsigned long long>());
     CAPT_LAUNCH_CHECK();
     const hipError_t se = hipStreamSynchronize(s);
@@ -544,6 +593,66 @@ capt_status filter(const float *xyz, int64_t n, float r_filter, float *out_xyz, 
     }
     *n_out = (int64_t)h[0];
     return CAPT_OK;
+}
+
+}  // namespace
+
+capt_status filter(const float *xyz, int64_t n, float r_filter, const float *crop, float *out_xyz,
+                   int32_t *out_index, int64_t *n_out, hipStream_t s) {
+    if (!crop || n == 0) return filter_core(xyz, n, r_filter, nullptr, out_xyz, out_index, n_out, s);
+    // the crop first: stable compaction of the points inside the reach ball,
+    // then the filter on them with their input indices as the index map
+    const size_t wn = (size_t)n;
+    const size_t nst = scan_lb_words(n) + 64;
+    const size_t oC = 0;
+    const size_t oMap = align256(oC + sizeof(float) * 3 * wn);
+    const size_t oFlag = align256(oMap + sizeof(uint32_t) * wn);
+    const size_t oPos = align256(oFlag + sizeof(uint32_t) * wn);
+    const size_t oSt = align256(oPos + sizeof(uint32_t) * wn);
+    const size_t bytes = align256(oSt + sizeof(uint32_t) * nst);
+    Scratch sc;
+    if (!sc.alloc(bytes, s)) {
+        set_error("device allocation of %zu crop scratch bytes failed", bytes);
+        return CAPT_ENOMEM;
+    }
+    Pinned res;
+    if (!res.alloc(3 * sizeof(unsigned long long))) {
+        set_error("pinned host allocation failed");
+        return CAPT_ENOMEM;
+    }
+    char *B = sc.as<char>();
+    float *cxyz = reinterpret_cast<float *>(B + oC);
+    uint32_t *map = reinterpret_cast<uint32_t *>(B + oMap);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(B + oFlag);
+    uint32_t *pos = reinterpret_cast<uint32_t *>(B + oPos);
+    uint32_t *status = reinterpret_cast<uint32_t *>(B + oSt);   // [0, 64): bad count and error word
+    const float reach2 = crop[3] * crop[3];   // one float32 product (contraction is off)
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>((int64_t)(nst + TB - 1) / TB, 1024)), dim3(TB),
+                       0, s, status, (int64_t)nst);
+    CAPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_crop_flag, dim3((unsigned)std::min<int64_t>(nblk(n), 4096)), dim3(TB), 0, s, xyz, n, crop[0],
+                       crop[1], crop[2], reach2, flag, reinterpret_cast<unsigned int *>(status));
+    CAPT_LAUNCH_CHECK();
+    capt_status e = scan_exclusive_u32_lb(flag, pos, n, status + 64, status + 1, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_crop_compact, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, flag, pos, cxyz, map,
+                       reinterpret_cast<const unsigned int *>(status), status + 1, res.as<unsigned long long>());
+    CAPT_LAUNCH_CHECK();
+    const hipError_t se = hipStreamSynchronize(s);
+    if (se != hipSuccess) {
+        res.p = nullptr;   // the kernels' state is unknown: never hand the block out again
+        return hip_fail(se, "hipStreamSynchronize", __FILE__, __LINE__);
+    }
+    const unsigned long long *h = res.as<unsigned long long>();
+    if (h[2]) {
+        set_error("internal: a look-back wait bound was exceeded in the crop (code %llu)", h[2]);
+        return CAPT_EHIP;
+    }
+    if (h[1]) {
+        set_error("input holds %llu non-finite coordinates", h[1]);
+        return CAPT_EINVAL;
+    }
+    return filter_core(cxyz, (int64_t)h[0], r_filter, map, out_xyz, out_index, n_out, s);
 }
 
 }  // namespace capt

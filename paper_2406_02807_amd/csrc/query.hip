@@ -394,6 +394,18 @@ struct PosedSrc {
     }
 };
 
+// Padded spheres (query padding, Sec. V-B): radius r + pad, one float32
+// addition, so that a filtered cloud answers conservatively.
+struct PaddedSrc {
+    const float4 *sph;
+    float pad;
+    __device__ __forceinline__ float4 operator()(int64_t item, int k, int len) const {
+        float4 q = sph[item * len + k];
+        q.w = __fadd_rn(q.w, pad);
+        return q;
+    }
+};
+
 // Items (configurations, or edges of posed configurations) of `len` spheres,
 // with early exit inside an item: the wave's 64 lanes form four slots of
 // SLOT lanes; a slot holds one item and tests its spheres SLOT at a time, in
@@ -666,13 +678,13 @@ __global__ void k_chunk_stats(CloudDev C, const float4 *__restrict__ sph, int64_
     if (chunks) chunks[s] = nc;
 }
 
-__global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r_min, float r_max,
+__global__ void k_check_radii(const float4 *__restrict__ sph, int64_t m, float r_min, float r_max, float pad,
                               unsigned int *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned int b = 0;
     for (; i < m; i += stride) {
-        const float r = sph[i].w;
+        const float r = __fadd_rn(sph[i].w, pad);
         b += !(r >= r_min && r <= r_max);
     }
     if (b) atomicAdd(bad, b);
@@ -905,7 +917,7 @@ bool same_tuning(const capt_tuning &a, const capt_tuning &b) {
 
 }  // namespace
 
-capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s) {
+capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_max, hipStream_t s, float pad) {
     if (m <= 0) return CAPT_OK;
     Scratch sc;
     if (!sc.alloc(256, s)) {
@@ -915,13 +927,14 @@ capt_status check_radii(const float *spheres, int64_t m, float r_min, float r_ma
     CAPT_HIP(hipMemsetAsync(sc.p, 0, 4, s));
     const int64_t blocks = std::min<int64_t>((m + 255) / 256, 4096);
     hipLaunchKernelGGL(k_check_radii, dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const float4 *>(spheres), m, r_min, r_max, sc.as<unsigned int>());
+                       reinterpret_cast<const float4 *>(spheres), m, r_min, r_max, pad, sc.as<unsigned int>());
     CAPT_LAUNCH_CHECK();
     unsigned int bad = 0;
     CAPT_HIP(hipMemcpyAsync(&bad, sc.p, 4, hipMemcpyDeviceToHost, s));
     CAPT_HIP(hipStreamSynchronize(s));
     if (bad) {
-        set_error("%u query radii lie outside [r_min, r_max] = [%g, %g]", bad, (double)r_min, (double)r_max);
+        set_error("%u query radii (after padding by %g) lie outside [r_min, r_max] = [%g, %g]", bad, (double)pad,
+                  (double)r_min, (double)r_max);
         return CAPT_ERADIUS;
     }
     return CAPT_OK;
@@ -1001,6 +1014,30 @@ capt_status collides_posed(capt_forest_s *f, const float *tmpl, int32_t g, const
         if (np <= 0) continue;
         PosedSrc src{poses + 12 * poff[c], reinterpret_cast<const float4 *>(tmpl), g};
         capt_status st = launch_slots(f->clouds[c].dev, src, np / edge, edge * g, out + poff[c] / edge,
+                                      ctr.as<unsigned int>() + (size_t)c * NXCD * CTR_STRIDE, s);
+        if (st) return st;
+    }
+    return CAPT_OK;
+}
+
+capt_status collides_padded(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, float pad,
+                            uint8_t *out, uint32_t flags, hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    if (flags & CAPT_CHECK_RADII) {
+        capt_status st = check_radii(spheres, qoff[nc], f->r_min, f->r_max, s, pad);
+        if (st) return st;
+    }
+    Scratch ctr;
+    if (!ctr.alloc(sizeof(unsigned int) * NXCD * CTR_STRIDE * (size_t)nc, s)) {
+        set_error("device allocation for queue counters failed");
+        return CAPT_ENOMEM;
+    }
+    // every group size goes through the slot kernel (one cloud per launch)
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        if (m <= 0) continue;
+        PaddedSrc src{reinterpret_cast<const float4 *>(spheres) + qoff[c], pad};
+        capt_status st = launch_slots(f->clouds[c].dev, src, m / g, g, out + qoff[c] / g,
                                       ctr.as<unsigned int>() + (size_t)c * NXCD * CTR_STRIDE, s);
         if (st) return st;
     }

@@ -76,6 +76,28 @@ def test_no_gpu_needed_for_validation(lib):
     assert lib.capt_filter(P(1), 10, -1.0, P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
     assert lib.capt_filter(P(1), 10, float("nan"), P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
     assert lib.capt_filter(P(1), 10, 0.01, P(1), None, None, None) == capt.CAPT_EINVAL
+    # filter + build: NULL out, bad filter radius, bad build radii, unknown flags, bad crop
+    m = C.c_int64()
+    crop = (C.c_float * 4)(0.0, 0.0, 0.0, 1.0)
+    bad_crop = (C.c_float * 4)(0.0, float("nan"), 0.0, 1.0)
+    neg_reach = (C.c_float * 4)(0.0, 0.0, 0.0, -1.0)
+    bf = lib.capt_build_filtered
+    assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, None) == capt.CAPT_EINVAL
+    assert bf(P(1), 10, -0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bf(P(1), 10, 0.01, None, 0.05, 0.01, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0x10, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bf(None, 10, 0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bf(P(1), 10, 0.01, bad_crop, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    # cropped filter: NULL / non-finite base / negative reach / NULL count
+    fc = lib.capt_filter_crop
+    assert fc(P(1), 10, 0.01, None, P(1), None, C.byref(m), None) == capt.CAPT_EINVAL
+    assert fc(P(1), 10, 0.01, bad_crop, P(1), None, C.byref(m), None) == capt.CAPT_EINVAL
+    assert fc(P(1), 10, 0.01, neg_reach, P(1), None, C.byref(m), None) == capt.CAPT_EINVAL
+    assert fc(P(1), 10, 0.01, crop, P(1), None, None, None) == capt.CAPT_EINVAL
+    assert fc(P(1), 1 << 30, 0.01, crop, P(1), None, C.byref(m), None) == capt.CAPT_EUNSUPPORTED
+    # padded queries: NULL forest, bad pad, unknown flags
+    cp = lib.capt_collides_padded
+    assert cp(None, P(1), q.ctypes.data_as(P), 1, 0.01, P(1), 0, None) == capt.CAPT_EINVAL
     # brute force: group not dividing the range
     q7 = np.array([0, 7], np.int64)
     assert lib.capt_bruteforce_collides(P(1), offp, 1, P(1), q7.ctypes.data_as(P), 2, P(1), None) == capt.CAPT_EINVAL

@@ -160,6 +160,102 @@ def test_collides_groups_tabletop(capt, orc, g):
     assert 0 < want.sum() <= len(want)
 
 
+@pytest.mark.parametrize("name,n,rf", [("tabletop", 50_000, 0.01), ("uniform", 3000, 0.02), ("empty", 0, 0.01)])
+def test_build_filtered_equals_filter_then_build(capt, name, n, rf):
+    _say(f"case: build_filtered {name} n={n} rf={rf}")
+    if name == "tabletop":
+        pts = synth.tabletop_cloud(n, 2001)
+    else:
+        pts = synth.uniform_cube_cloud(n, 77) if n else np.zeros((0, 3), np.float32)
+    x = dev(pts)
+    fx, fi = capt.capt_filter(x, rf)
+    f_ref = capt.capt_build(fx.contiguous(), 0.015, 0.08)
+    f, ki = capt.capt_build_filtered(x, rf, 0.015, 0.08, kept_index=True)
+    assert np.array_equal(ki.cpu().numpy(), fi.cpu().numpy())
+    a, b = capt.parse_blob(capt.capt_export(f)), capt.parse_blob(capt.capt_export(f_ref))
+    assert (a.n, a.N, a.D) == (b.n, b.N, b.D)
+    assert np.array_equal(bits(a.T), bits(b.T))
+    assert np.array_equal(a.rep, b.rep) and np.array_equal(a.pruned, b.pruned)
+    assert all(np.array_equal(u, v) for u, v in zip(canonical_sets(a.off, a.idx), canonical_sets(b.off, b.idx)))
+    assert np.array_equal(a.aabb, b.aabb)
+
+
+@pytest.mark.parametrize("name,base,reach", [("tabletop-half", (0.0, 0.0, 0.4), 0.9),
+                                               ("tabletop-all", (0.0, 0.0, 0.4), float("inf")),
+                                               ("tabletop-none", (9.0, 9.0, 9.0), 0.5),
+                                               ("room-arm", (3.0, 3.0, 0.8), 1.5)])
+def test_filter_crop_matches_oracle(capt, orc, name, base, reach):
+    _say(f"case: filter crop {name}")
+    pts = synth.room_cloud(180_000, 20_000, 1005) if name.startswith("room") else synth.tabletop_cloud(50_000, 2001)
+    rf = 0.01
+    fx, fi = capt.capt_filter(dev(pts), rf, base=base, reach=reach)
+    want, _ = orc.filter(pts, rf, base=base, reach=reach)
+    assert np.array_equal(fi.cpu().numpy(), want)
+    assert np.array_equal(bits(fx.cpu().numpy()), bits(pts[want]))
+    if name == "tabletop-all":
+        assert np.array_equal(want, orc.filter(pts, rf)[0])
+    if name == "tabletop-none":
+        assert len(want) == 0
+
+
+def test_filter_crop_rejects_nonfinite(capt):
+    pts = synth.tabletop_cloud(5000, 3)
+    pts[1234, 1] = np.nan   # outside any reach ball, still an error
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_filter(dev(pts), 0.01, base=(0.0, 0.0, 0.4), reach=0.5)
+    assert e.value.status == capt.CAPT_EINVAL
+
+
+def test_build_filtered_with_crop(capt):
+    _say("case: build_filtered with crop")
+    pts = synth.tabletop_cloud(50_000, 2001)
+    x = dev(pts)
+    base, reach = (0.2, 0.1, 0.3), 0.9
+    fx, fi = capt.capt_filter(x, 0.01, base=base, reach=reach)
+    f_ref = capt.capt_build(fx.contiguous(), 0.015, 0.08)
+    f, ki = capt.capt_build_filtered(x, 0.01, 0.015, 0.08, kept_index=True, base=base, reach=reach)
+    assert np.array_equal(ki.cpu().numpy(), fi.cpu().numpy())
+    a, b = capt.parse_blob(capt.capt_export(f)), capt.parse_blob(capt.capt_export(f_ref))
+    assert (a.n, a.D) == (b.n, b.D) and np.array_equal(bits(a.T), bits(b.T)) and np.array_equal(a.rep, b.rep)
+
+
+@pytest.mark.parametrize("g", [1, 7, 60])
+def test_collides_padded_matches_oracle(capt, orc, g):
+    _say(f"case: padded queries g={g}")
+    pts = synth.tabletop_cloud(12_000, 91)
+    f = capt.capt_build(dev(pts), 0.015, 0.08)
+    pad = 0.02
+    if g == 60:
+        sph = synth.posed_spheres(synth.chain_template(2003), 2001, synth.WORKSPACE, 92)
+        sph[:, 3] = np.minimum(sph[:, 3], np.float32(0.06))
+    else:
+        sph = synth.uniform_spheres(g * 1501, synth.WORKSPACE, 0.015, 0.06, 93)
+    got = capt.capt_collides_padded(f, dev(sph), g, pad, flags=capt.CAPT_CHECK_RADII).cpu().numpy()
+    want = orc.brute_f32(pts, sph, g, pad=pad)
+    assert np.array_equal(got, want)
+    assert want.sum() > orc.brute_f32(pts, sph, g).sum()   # the padding changes answers
+    # pad 0 is the unpadded query
+    assert np.array_equal(capt.capt_collides_padded(f, dev(sph), g, 0.0).cpu().numpy(),
+                          capt.capt_collides(f, dev(sph), g).cpu().numpy())
+
+
+def test_collides_padded_radius_check_and_forest(capt, orc):
+    pts = [synth.tabletop_cloud(3000, 200 + c) for c in range(3)]
+    f = capt.capt_build(dev(np.concatenate(pts)), 0.015, 0.08, cloud_off=[0, 3000, 6000, 9000])
+    sph = [synth.uniform_spheres(60 * 300, synth.WORKSPACE, 0.015, 0.05, 300 + c) for c in range(3)]
+    qoff = [0, 18000, 36000, 54000]
+    got = capt.capt_collides_padded(f, dev(np.concatenate(sph)), 60, 0.03, query_off=qoff).cpu().numpy()
+    want = np.concatenate([orc.brute_f32(p, q, 60, pad=0.03) for p, q in zip(pts, sph)])
+    assert np.array_equal(got, want)
+    with pytest.raises(capt.CaptError) as e:   # 0.05 + 0.04 > r_max
+        capt.capt_collides_padded(f, dev(np.concatenate(sph)), 60, 0.04, query_off=qoff,
+                                  flags=capt.CAPT_CHECK_RADII)
+    assert e.value.status == capt.CAPT_ERADIUS
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_collides_padded(f, dev(np.concatenate(sph)), 60, float("nan"), query_off=qoff)
+    assert e.value.status == capt.CAPT_EINVAL
+
+
 def test_stream_ordered_release(capt, orc):
     # per-frame pattern: build, query and release in stream order without a
     # host wait; later builds reuse the released memory behind earlier queries
