@@ -5,7 +5,7 @@
 // sort counts all digits once, then makes one kernel per 8-bit digit with
 // decoupled look-back for the tile offsets; the rank of an element among
 // equal digits inside a tile comes from wave ballots (eight ballots match the
-// digit across the 64 lanes) and per-wave digit counts in LDS.
+// digit across the 64 lanes) and per-wave running offsets in LDS.
 #include "capt_internal.h"
 
 namespace capt {
@@ -257,56 +257,75 @@ __global__ void k_os_hist_sum(const uint32_t *__restrict__ part, int nblocks, in
     ghist[((size_t)p * nseg + g) * 256 + d] = t;
 }
 
+// One digit pass.  Wave w of a tile owns the tile's items [w * 512, (w + 1) *
+// 512) and walks them in eight rounds of 64; a lane's rank among the round's
+// items with its digit comes from ballots, and each wave keeps its own running
+// offset per digit in LDS, so the ranking needs no block barrier.
 template <class K>
 __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                    K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t len,
                                                    int64_t tps, int shift, const uint32_t *__restrict__ ghist,
                                                    uint32_t *__restrict__ status, uint32_t *__restrict__ tile_ctr,
                                                    uint32_t *__restrict__ err) {
+    constexpr int R = 256;
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t cnt[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[NW][256];
+    __shared__ uint32_t start[R];     // where the tile's run of each digit begins in the segment
+    __shared__ uint32_t wrun[NW][R];  // per-wave digit counts, then per-wave running offsets
     __shared__ uint32_t lw[NW];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    cnt[threadIdx.x] = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) wrun[q][threadIdx.x] = 0;
     __syncthreads();
     const uint32_t t = s_tile;               // global tile id
     const int64_t g = (int64_t)t / tps;      // its segment
     const int64_t ts = (int64_t)t - g * tps; // tile within the segment
     const int64_t seg0 = g * len;
-    const int64_t base = ts * TILE;          // within the segment
-    // the tile's items stay in registers for the whole pass (one load round)
+    const int64_t wbase = ts * TILE + (int64_t)w * (IPT * WAVE);   // this wave's first item in the segment
+    // the wave's items stay in registers for the whole pass (one load round)
     K key[IPT];
     uint32_t val[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const int64_t j = base + (int64_t)r * TB + threadIdx.x;
+        const int64_t j = wbase + (int64_t)r * WAVE + lane;
         key[r] = j < len ? kin[seg0 + j] : K(0);
         val[r] = j < len ? vin[seg0 + j] : 0u;
     }
+    // lanes with the same digit in each round (eight ballots match the digit)
+    uint64_t same[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        if (j < len) atomicAdd(&cnt[(uint32_t)(key[r] >> shift) & 255u], 1u);
+        const bool valid = wbase + (int64_t)r * WAVE + lane < len;
+        const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot(valid && ((dg >> b) & 1u));
+            m &= ((dg >> b) & 1u) ? bal : ~bal;
+        }
+        same[r] = valid ? m : 0ull;
+        // the lowest lane of each digit group adds the group's size (one
+        // writer per address per round; a wave's LDS operations stay in order)
+        if (valid && __popcll(m & lt_mask) == 0) wrun[w][dg] += (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // publish this tile's digit counts, then look back over the segment's
-    // earlier tiles
+    // this tile's count of digit d: publish it, then look back over the
+    // segment's earlier tiles
     const int d = threadIdx.x;
-    const uint32_t c = cnt[d];
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) c += wrun[q][d];
     uint32_t excl = 0;
     if (ts == 0) {
-        store_agent(&status[(size_t)t * 256 + d], ST_PRE | c);
+        store_agent(&status[(size_t)t * R + d], ST_PRE | c);
     } else {
-        store_agent(&status[(size_t)t * 256 + d], ST_AGG | c);
+        store_agent(&status[(size_t)t * R + d], ST_AGG | c);
         int64_t q = (int64_t)t - 1;
         uint32_t spins = 0;
         while (true) {
-            const uint32_t v = load_agent(&status[(size_t)q * 256 + d]);
+            const uint32_t v = load_agent(&status[(size_t)q * R + d]);
             const uint32_t flag = v & ~ST_VAL;
             if (flag == 0) {
                 if (++spins > LOOKBACK_SPINS) {
@@ -319,43 +338,30 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
             if (flag == ST_PRE) break;
             --q;   // a segment's first tile publishes a prefix, so q stays in the segment
         }
-        store_agent(&status[(size_t)t * 256 + d], ST_PRE | (excl + c));
+        store_agent(&status[(size_t)t * R + d], ST_PRE | (excl + c));
     }
     // start of every digit in the segment: counts of smaller digits
     uint32_t tot;
-    const uint32_t gex = block_excl_scan(ghist[(size_t)g * 256 + d], lw, &tot);
-    run[d] = gex + excl;
+    const uint32_t gex = block_excl_scan(ghist[(size_t)g * R + d], lw, &tot);
+    start[d] = gex + excl;
+    // per-wave counts -> offsets of each wave's run inside the tile's run
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const uint32_t k = wrun[q][d];
+        wrun[q][d] = run;
+        run += k;
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-#pragma unroll
-        for (int q = 0; q < NW; ++q) wc[q][threadIdx.x] = 0;
-        __syncthreads();
-        const int64_t j = base + (int64_t)r * TB + threadIdx.x;
-        const bool valid = j < len;
+        if (same[r] == 0ull) continue;   // lane holds no item in this round
         const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
-        uint64_t same = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot(valid && ((dg >> b) & 1u));
-            same &= ((dg >> b) & 1u) ? bal : ~bal;
-        }
-        const uint32_t rank = __popcll(same & lt_mask);
-        if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(same);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[dg];
-            for (int q = 0; q < w; ++q) pos += wc[q][dg];
-            pos += rank;
-            kout[seg0 + pos] = key[r];
-            vout[seg0 + pos] = val[r];
-        }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) add += wc[q][threadIdx.x];
-        run[threadIdx.x] += add;
-        __syncthreads();
+        const uint32_t rank = (uint32_t)__popcll(same[r] & lt_mask);
+        const uint32_t pos = start[dg] + wrun[w][dg] + rank;
+        kout[seg0 + pos] = key[r];
+        vout[seg0 + pos] = val[r];
+        if (rank == 0) wrun[w][dg] += (uint32_t)__popcll(same[r]);
     }
 }
 
