@@ -117,6 +117,60 @@ void pinned_release(void *p, size_t bytes) {
     g_pinned_free.emplace_back(pinned_class(bytes), p);
 }
 
+namespace {
+struct SideCtx {
+    int dev;
+    hipStream_t side;
+    hipEvent_t e1, e2;
+};
+std::mutex g_side_mu;
+std::vector<SideCtx> g_side_free;
+}  // namespace
+
+capt_status ForkJoin::fork(hipStream_t s) {
+    CAPT_HIP(hipGetDevice(&dev));
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lock(g_side_mu);
+        for (size_t i = 0; i < g_side_free.size(); ++i)
+            if (g_side_free[i].dev == dev) {
+                side = g_side_free[i].side;
+                ev_fork = g_side_free[i].e1;
+                ev_join = g_side_free[i].e2;
+                g_side_free[i] = g_side_free.back();
+                g_side_free.pop_back();
+                have = true;
+                break;
+            }
+    }
+    if (!have) {
+        // default priority, no implicit ordering with the null stream
+        CAPT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        CAPT_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        CAPT_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
+    main = s;
+    CAPT_HIP(hipEventRecord(ev_fork, s));
+    CAPT_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    forked = true;
+    return CAPT_OK;
+}
+
+capt_status ForkJoin::join(hipStream_t s) {
+    if (!forked) return CAPT_OK;
+    forked = false;
+    CAPT_HIP(hipEventRecord(ev_join, side));
+    CAPT_HIP(hipStreamWaitEvent(s, ev_join, 0));
+    return CAPT_OK;
+}
+
+ForkJoin::~ForkJoin() {
+    if (!side) return;
+    if (forked && (join(main) != CAPT_OK)) (void)hipStreamSynchronize(side);
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    g_side_free.push_back({dev, side, ev_fork, ev_join});
+}
+
 const DeviceInfo &device_info() {
     static DeviceInfo info;
     static std::once_flag once;

@@ -63,11 +63,13 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 
 // Zero the phase's counters and bins in one launch.
 __global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__restrict__ errw,
-                        uint32_t *__restrict__ cstart, int64_t ncs, uint32_t *__restrict__ scan_st, int64_t nss) {
+                        uint32_t *__restrict__ errw2, uint32_t *__restrict__ cstart, int64_t ncs,
+                        uint32_t *__restrict__ scan_st, int64_t nss) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 4) totals[t] = 0ull;
     if (t < 64) errw[t] = 0u;
+    if (t < 64) errw2[t] = 0u;
     for (int64_t i = t; i < ncs; i += stride) cstart[i] = 0u;
     for (int64_t i = t; i < nss; i += stride) scan_st[i] = 0u;
 }
@@ -756,10 +758,10 @@ __global__ void __launch_bounds__(TB) k_sum_partials(const unsigned long long *_
 // A cloud's totals and its error word into the caller's pinned host words
 // (one thread; every earlier kernel of the cloud has finished by then).
 __global__ void k_publish(const unsigned long long *__restrict__ totals, const uint32_t *__restrict__ errw,
-                          unsigned long long *__restrict__ host) {
+                          const uint32_t *__restrict__ errw2, unsigned long long *__restrict__ host) {
     if (threadIdx.x == 0) {
         for (int k = 0; k < 4; ++k) host[k] = totals[k];
-        host[4] = *errw;
+        host[4] = *errw | *errw2;
     }
 }
 
@@ -771,6 +773,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct CloudWork {
     Scratch scratch;
     uint32_t *rad = nullptr;       // radix sort scratch; rad[0] = error word
+    uint32_t *rad_g = nullptr;     // the grid branch's radix scratch; rad_g[0] = its error word
     uint32_t *count = nullptr;     // entries per leaf
     uint32_t *pstart = nullptr;    // exclusive scan of padded counts
     uint32_t *scan_tmp = nullptr;
@@ -832,15 +835,16 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         return o;
     };
     const size_t oL = take(sizeof(uint32_t) * 6 * wN);     // 3 lists x 2 buffers
-    const size_t oK = take(sizeof(uint32_t) * 2 * std::max(3 * wN, wn));   // sort keys x 2
-    const size_t oV = take(sizeof(uint32_t) * 2 * wn);     // grid sort values x 2
+    const size_t oK = take(sizeof(uint32_t) * 2 * 3 * wN);   // presort keys x 2
+    const size_t oKg = take(sizeof(uint32_t) * 2 * wn);      // grid sort keys x 2
+    const size_t oV = take(sizeof(uint32_t) * 2 * wn);       // grid sort values x 2
     const size_t oInv = take(sizeof(uint32_t) * wN);
     const size_t oLeft = take(2 * wN);   // "goes left" flags, two levels
     const int nglob = std::max(0, D - LMAX_LOG2);   // global levels (segments above LMAX)
     const size_t lvl_words = 2 * ntile + 64;          // per global level: two status lists, two counters
     const size_t oSums = take(sizeof(uint32_t) * (lvl_words * (size_t)std::max(nglob, 1) + 64));
-    const size_t oRad = take(sizeof(uint32_t) * std::max(radix_tmp_words(std::max<int64_t>(N, n)),
-                                                         radix_tmp_words_seg(3, N)));
+    const size_t oRad = take(sizeof(uint32_t) * radix_tmp_words_seg(3, N));
+    const size_t oRadG = take(sizeof(uint32_t) * radix_tmp_words(std::max<int64_t>(n, 1)));
     const size_t oCells = take(sizeof(float) * 6 * wN);
     const size_t oCnt = take(sizeof(uint32_t) * (wN + 1));
     const size_t oPs = take(sizeof(uint32_t) * (wN + 1));
@@ -859,12 +863,15 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     char *Sb = W.scratch.as<char>();
     uint32_t *Lbuf = reinterpret_cast<uint32_t *>(Sb + oL);
     uint32_t *keys = reinterpret_cast<uint32_t *>(Sb + oK);
+    uint32_t *gkeys = reinterpret_cast<uint32_t *>(Sb + oKg);
     uint32_t *gval = reinterpret_cast<uint32_t *>(Sb + oV);
     uint32_t *inv = reinterpret_cast<uint32_t *>(Sb + oInv);
     uint8_t *left = reinterpret_cast<uint8_t *>(Sb + oLeft);
     uint32_t *sums = reinterpret_cast<uint32_t *>(Sb + oSums);
     uint32_t *rad = reinterpret_cast<uint32_t *>(Sb + oRad);
+    uint32_t *rad_g = reinterpret_cast<uint32_t *>(Sb + oRadG);
     W.rad = rad;
+    W.rad_g = rad_g;
     float *cells = reinterpret_cast<float *>(Sb + oCells);
     W.count = reinterpret_cast<uint32_t *>(Sb + oCnt);
     W.pstart = reinterpret_cast<uint32_t *>(Sb + oPs);
@@ -878,7 +885,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     uint32_t *badp = reinterpret_cast<uint32_t *>(bbp + 6 * nbN);                         // [nbN]
     uint32_t *prp = badp + nbN;                                                           // [nbN]
     hipLaunchKernelGGL(k_binit, dim3((unsigned)std::min<int64_t>((cell_cap + TB) / TB + 1, 1024)), dim3(TB), 0, s,
-                       W.totals, rad, cstart, cell_cap + 1, W.scan_tmp, (int64_t)(nscan_cs + nscan_ps));
+                       W.totals, rad, rad_g, cstart, cell_cap + 1, W.scan_tmp, (int64_t)(nscan_cs + nscan_ps));
     CAPT_LAUNCH_CHECK();
 
     // 1. presort: list a sorted by (coordinate a, id), the three lists in
@@ -887,15 +894,47 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 2; ++b) L[a][b] = Lbuf + (size_t)(3 * b + a) * wN;
     int cur[3] = {0, 0, 0};
+    hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, keys, L[0][0], pts, bbp, badp);
+    CAPT_LAUNCH_CHECK();
+
+    // The grid of the points (step 4) needs only the points and the box
+    // partials: it runs on a side stream while the splits run on s, and s
+    // waits for it before the affordance sets.
+    const double R = (double)r_max * (1.0 + 0x1p-20);
+    ForkJoin fj;
+    capt_status fs = fj.fork(s);
+    if (fs) return fs;
+    const hipStream_t sg = fj.side;
+
     {
-        hipLaunchKernelGGL(k_presort_keys, dim3(nblk(N)), dim3(TB), 0, s, xyz, n, N, keys, L[0][0], pts, bbp,
-                           badp);
-        CAPT_LAUNCH_CHECK();
         int where = 0;
         capt_status st = radix_sort_u32_seg(keys, L[0][0], keys + 3 * wN, L[0][1], 3, N, 32, rad, s, &where);
         if (st) return st;
         cur[0] = cur[1] = cur[2] = where;
     }
+
+    // the grid branch's launches follow the presort's, so the split chain starts first
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(TB), 0, sg, bbp, badp, nbN, R, cell_cap, grid, W.totals);
+    CAPT_LAUNCH_CHECK();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_grid_keys, dim3(nblk(n)), dim3(TB), 0, sg, xyz, n, grid, gkeys, gval, cstart);
+        CAPT_LAUNCH_CHECK();
+    }
+    // bin starts: exclusive scan over the cap; cstart[ncells .. cap] = n
+    fs = scan_exclusive_u32_lb(cstart, cstart, cell_cap + 1, W.scan_tmp, rad_g, sg);
+    if (fs) return fs;
+    int gwhere = 0;
+    if (n > 1) {
+        fs = radix_sort_u32(gkeys, gval, gkeys + wn, gval + wn, n, cell_bits, rad_g, sg, &gwhere);
+        if (fs) return fs;
+    }
+    const uint32_t *sid = gwhere ? gval + wn : gval;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_grid_gather, dim3(nblk(n)), dim3(TB), 0, sg, xyz, sid, n, sxyz, sxyz + wn,
+                           sxyz + 2 * wn);
+        CAPT_LAUNCH_CHECK();
+    }
+
 
     // 2. splits: global levels while segments exceed LMAX, then LDS levels
     int d = 0;
@@ -935,28 +974,9 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
                        C.pruned_flag, prp);
     CAPT_LAUNCH_CHECK();
 
-    // 4. grid of the points: bins of side >= R / 2, points sorted by bin
-    const double R = (double)r_max * (1.0 + 0x1p-20);
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(TB), 0, s, bbp, badp, nbN, R, cell_cap, grid, W.totals);
-    CAPT_LAUNCH_CHECK();
-    if (n > 0) {
-        hipLaunchKernelGGL(k_grid_keys, dim3(nblk(n)), dim3(TB), 0, s, xyz, n, grid, keys, gval, cstart);
-        CAPT_LAUNCH_CHECK();
-    }
-    // bin starts: exclusive scan over the cap; cstart[ncells .. cap] = n
-    capt_status st = scan_exclusive_u32_lb(cstart, cstart, cell_cap + 1, W.scan_tmp, rad, s);
-    if (st) return st;
-    int where = 0;
-    if (n > 1) {
-        st = radix_sort_u32(keys, gval, keys + wn, gval + wn, n, cell_bits, rad, s, &where);
-        if (st) return st;
-    }
-    const uint32_t *sid = where ? gval + wn : gval;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_grid_gather, dim3(nblk(n)), dim3(TB), 0, s, xyz, sid, n, sxyz, sxyz + wn,
-                           sxyz + 2 * wn);
-        CAPT_LAUNCH_CHECK();
-    }
+    // 4. join the grid branch (bins of side >= R / 2, points sorted by bin)
+    fs = fj.join(s);
+    if (fs) return fs;
 
     // 5. affordance counts and placement
     AffArgs &A = W.args;
@@ -1058,7 +1078,8 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     }
     unsigned long long *hw = res.as<unsigned long long>();
     for (int c = 0; c < ncloud; ++c) {
-        hipLaunchKernelGGL(k_publish, dim3(1), dim3(WAVE), 0, s, work[c].totals, work[c].rad, hw + 5 * c);
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(WAVE), 0, s, work[c].totals, work[c].rad, work[c].rad_g,
+                           hw + 5 * c);
         CAPT_LAUNCH_CHECK();
     }
     const hipError_t se = hipStreamSynchronize(s);

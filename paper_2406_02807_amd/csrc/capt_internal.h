@@ -112,6 +112,26 @@ struct Pinned {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Fork-join of a library-owned side stream inside one call: fork() makes the
+// side stream wait for the work queued on s so far, join() makes s wait for
+// the side stream's work.  A ForkJoin that is still forked joins on
+// destruction (so stream-ordered releases on s come after the side work).
+// Side streams and events come from a process-wide pool, one context per
+// concurrent user.
+struct ForkJoin {
+    hipStream_t side = nullptr;
+    hipStream_t main = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int dev = -1;
+    bool forked = false;
+    ForkJoin() = default;
+    ForkJoin(const ForkJoin &) = delete;
+    ForkJoin &operator=(const ForkJoin &) = delete;
+    ~ForkJoin();
+    capt_status fork(hipStream_t s);
+    capt_status join(hipStream_t s);
+};
+
 // Device properties used for launch planning.
 struct DeviceInfo {
     int cus = 256;
