@@ -7,6 +7,11 @@ candidate with HIP events on the current stream.  Every candidate's answers
 must equal the first candidate's bit for bit (the launch shape never changes
 an answer); a mismatch raises.  The winner is applied with `capt_set_tuning`
 and can be cached in a JSON file keyed by a workload signature.
+
+`autotune_step` tunes the same knobs for a caller-defined step instead of a
+lone query launch (for example double-buffered frames, where the query shares
+the chip with the next frame's filter and build and the best shape leaves
+room for them), timed by wall clock with the device synchronised.
 """
 from __future__ import annotations
 
@@ -113,4 +118,61 @@ def autotune(forest, spheres, group, query_off=None, flags=0, space=None, reps=3
         data[key] = best
         with open(cache, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
+    return best, history
+
+
+STEP_SPACE = {
+    "waves_per_group": [8, 12, 14, 16],
+    "groups_per_cu": [1, 2, 3, 4],
+    "lds_levels": [12, 13, 14],
+    "scan_unroll": [1, 2, 4],
+}
+
+
+def autotune_step(step, answers, space=None, reps=3, rounds=2, verbose=False):
+    """Coordinate descent over the launch shape for `step()` (any host code
+    that runs the workload and returns when it is queued); `answers()` returns
+    the tensor of results, which must not change with the shape.  Each
+    candidate's cost is the median wall time of `reps` synchronised runs.
+    Returns (best tuning dict, list of (tuning, ms))."""
+    import torch
+    space = dict(STEP_SPACE if space is None else space)
+
+    def run(t):
+        capt_set_tuning(**t)
+        step()                                  # warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    best = capt_get_tuning()
+    best_ms = run(best)
+    ref = answers().clone()
+    history = [(dict(best), best_ms)]
+    for _ in range(rounds):
+        improved = False
+        for name, values in space.items():
+            for v in values:
+                if best[name] == v:
+                    continue
+                cand = dict(best)
+                cand[name] = v
+                ms = run(cand)
+                if not torch.equal(answers(), ref):
+                    capt_set_tuning(**best)
+                    raise RuntimeError(f"launch shape {cand} changed an answer")
+                history.append((cand, ms))
+                if verbose:
+                    print(f"  {cand} {ms:.3f} ms", flush=True)
+                if ms < best_ms * 0.99:
+                    best, best_ms, improved = cand, ms, True
+        if not improved:
+            break
+    capt_set_tuning(**best)
     return best, history

@@ -413,8 +413,11 @@ struct PaddedSrc {
 // item would); a slot that finishes takes the next item from the wave's
 // popped range (per-XCD queues as above).  The slots of a wave run together
 // through the two-level scan, each slot a group.
+// U <= 2 is held to 64 VGPRs, so that eight waves fit per SIMD (32 per CU):
+// the kernel is bound by memory latency and more resident waves hide more
+// of it; U = 4 would spill at that budget.
 template <int U, class Src>
-__global__ void k_collide_slots(CloudDev C, Src src, int64_t ncfg, int g,
+__global__ void __attribute__((amdgpu_waves_per_eu(U <= 2 ? 8 : 1, 8))) k_collide_slots(CloudDev C, Src src, int64_t ncfg, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float4 lds4[];
     WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
