@@ -489,6 +489,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
+            "achieved_query_alone": alg_bytes / (q_alone_ms * 1e-3) / 1e9,
+            "frac_query_alone": alg_bytes / (q_alone_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
             **alg,
