@@ -310,6 +310,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--tune-query", default=None, metavar="JSON",
+                    help="launch shape for the serial frames instead of autotuning (e.g. for profiling)")
+    ap.add_argument("--tune-steps", default=None, metavar="JSON",
+                    help="launch shape for the timed steps instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -366,7 +370,11 @@ def main():
     # launch shape from the project autotuner, on this workload, before timing
     from paper_2406_02807_amd import autotune
     f, fx = step()
-    tuned, _ = autotune.autotune(f, sph, G)
+    if args.tune_query:
+        tuned = json.loads(args.tune_query)
+        capt.capt_set_tuning(**tuned)
+    else:
+        tuned, _ = autotune.autotune(f, sph, G)
     f.close()
     log(f"tuning: {tuned}")
     for _ in range(args.warmup):
@@ -423,7 +431,11 @@ def main():
 
     # launch shape for these steps: the query shares the chip with the next
     # frame's build, so the best shape is tuned on the steps themselves
-    tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
+    if args.tune_steps:
+        tuned_step = json.loads(args.tune_steps)
+        capt.capt_set_tuning(**tuned_step)
+    else:
+        tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
     log(f"tuning for the double-buffered steps: {tuned_step}")
     forest = None
     for _ in range(args.warmup):
