@@ -80,8 +80,8 @@ __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, in
 
 // The same descent, shaped for latency: the LDS levels are taken three per
 // round trip (the node, both children and all four grandchildren are read
-// together, then three comparisons pick the path), and the last two global
-// levels are read together (the node and both children), so the leaf record
+// together, then three comparisons pick the path), and the last three (or
+// two) global levels are read together the same way, so the leaf record
 // arrives two memory round trips after the LDS part.  Returns the leaf
 // record; *lf gets its index.
 __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, int L, const float *__restrict__ Tg,
@@ -104,11 +104,25 @@ __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, i
         i = 2 * i + 1 + (xs[a] > Tl[i] ? 1u : 0u);
         a = (a == 2) ? 0 : a + 1;
     }
-    for (; lv + 2 < D; ++lv) {
+    for (; lv + 3 < D; ++lv) {
         i = 2 * i + 1 + (xs[a] > ld32(Tg, 4u * i) ? 1u : 0u);
         a = (a == 2) ? 0 : a + 1;
     }
-    if (D - lv == 2) {
+    if (D - lv == 3) {
+        // the last three levels in one round trip: the node, both children
+        // and all four grandchildren
+        const float t0 = ld32(Tg, 4u * i);
+        const float t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
+        const float t2a = ld32(Tg, 16u * i + 12u), t2b = ld32(Tg, 16u * i + 16u);
+        const float t2c = ld32(Tg, 16u * i + 20u), t2d = ld32(Tg, 16u * i + 24u);
+        const int a1 = (a == 2) ? 0 : a + 1;
+        const int a2 = (a1 == 2) ? 0 : a1 + 1;
+        const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
+        const uint32_t b1 = xs[a1] > (b0 ? t1b : t1a) ? 1u : 0u;
+        const float t2 = b0 ? (b1 ? t2d : t2c) : (b1 ? t2b : t2a);
+        const uint32_t b2 = xs[a2] > t2 ? 1u : 0u;
+        i = 8 * i + 7 + 4 * b0 + 2 * b1 + b2;
+    } else if (D - lv == 2) {
         const float t0 = ld32(Tg, 4u * i), t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
         const int a1 = (a == 2) ? 0 : a + 1;
         const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
@@ -120,6 +134,9 @@ __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, i
     *lf = i - ((1u << D) - 1u);
     return leaves[*lf];
 }
+
+// Lanes per configuration slot of the slot kernels (four slots per wave).
+constexpr int SLOT = 16;
 
 // Per-wave LDS scratch of the two-level set scan.
 constexpr uint32_t RING = 128;                 // chunks awaiting the entry scan (power of two)
@@ -221,19 +238,39 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             py[u] = in[u] ? ld32(PY, 4u * e) : 0.f;
             pz[u] = in[u] ? ld32(PZ, 4u * e) : 0.f;
         }
-        uint64_t om = 0;   // owners hit by this lane's entries
+        bool hit[U];
+        bool any = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (in[u] && sqdist(s[u].x, s[u].y, s[u].z, px[u], py[u], pz[u]) <= s[u].w) om |= 1ull << own[u];
+        for (int u = 0; u < U; ++u) {
+            hit[u] = in[u] && sqdist(s[u].x, s[u].y, s[u].z, px[u], py[u], pz[u]) <= s[u].w;
+            any = any || hit[u];
+        }
         head += nproc;
-        if (__ballot(om != 0) == 0) return false;
+        if (__ballot(any) == 0) return false;
         if (single) {
             done = valid;
             return true;
         }
+        if (gg == SLOT) {
+            // four groups of 16 lanes: one ballot per group
+            uint32_t gm = 0;
 #pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) om |= __shfl_xor(om, d, WAVE);
-        if (valid) done = done || (((om >> (cfg * gg)) & gmask) != 0);
+            for (int c = 0; c < WAVE / SLOT; ++c) {
+                bool h = false;
+#pragma unroll
+                for (int u = 0; u < U; ++u) h = h || (hit[u] && own[u] / SLOT == c);
+                if (__ballot(h) != 0) gm |= 1u << c;
+            }
+            if (valid) done = done || ((gm >> cfg) & 1u) != 0;
+        } else {
+            uint64_t om = 0;   // owners hit by this lane's entries
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (hit[u]) om |= 1ull << own[u];
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) om |= __shfl_xor(om, d, WAVE);
+            if (valid) done = done || (((om >> (cfg * gg)) & gmask) != 0);
+        }
         dead = __ballot(done);
         return true;
     };
@@ -358,7 +395,6 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
     }
 }
 
-constexpr int SLOT = 16;
 
 // Sphere sources of the slot kernel: item i has `len` spheres in test order.
 // Materialised spheres: item = configuration, sphere k = spheres[i * g + k].
