@@ -218,6 +218,44 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
     }
 
 
+def bench_indexed(capt, torch, reps=5):
+    """Indexed affordance sets (point indices only) against plain sets on the
+    room scene (1.2M points filtered at 5 mm, r_max = 0.1 m): forest bytes and
+    the time of 10,000,000 single-sphere queries, with equal answers."""
+    import synth
+    w = synth.workload(5)
+    xyz = torch.from_numpy(w.cloud).cuda()
+    sph = torch.from_numpy(w.spheres[:10_000_000]).cuda()
+    fx, _ = capt.capt_filter(xyz, w.r_filter)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    rows = {}
+    outs = {}
+    for name, ix in (("plain", False), ("indexed", True)):
+        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max, indexed=ix)
+        out = capt.capt_collides(f, sph, 1)
+        torch.cuda.synchronize()
+        rows[name + "_ms"] = timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps)
+        rows[name + "_bytes"] = int(f.info()["bytes"])
+        outs[name] = out.clone()
+        f.close()
+    rows["same_answers"] = bool(torch.equal(outs["plain"], outs["indexed"]))
+    rows["workload"] = "room scene, 1.2M points -> 5 mm filter, r_max = 0.1, 10,000,000 single-sphere queries"
+    return rows
+
+
 def bench_posed(capt, torch, forest, reps=5):
     """Motion-edge validation: 100,000 edges of 10 rigid poses of the 60-sphere
     template (translation within 0.4 m, rotation by slerp) on the tabletop
@@ -540,6 +578,8 @@ def main():
         result["posed"] = bench_posed(capt, torch, f_posed)
         f_posed.close()
         log(f"posed: {result['posed']}")
+        result["indexed_sets"] = bench_indexed(capt, torch)
+        log(f"indexed sets: {result['indexed_sets']}")
 
     if not args.no_cpu:
         cb, ref = cpu_baseline(w, G, min(args.cpu_sample, m // G))

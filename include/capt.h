@@ -51,6 +51,8 @@ typedef int32_t capt_status;
 
 /* Build flags */
 #define CAPT_NO_PRUNE     0x1u  /* never apply r_min pruning (Sec. IV-B) */
+#define CAPT_INDEXED_SETS 0x10u /* sets hold point indices only; queries gather the
+                                   coordinates from the forest's point table */
 /* Query flags */
 #define CAPT_CHECK_RADII  0x2u  /* validate radii first (one device-to-host sync) */
 #define CAPT_PER_CLOUD    0x4u  /* forests: one launch per cloud, not one batched launch */
@@ -101,7 +103,12 @@ capt_status capt_filter_crop(const float *xyz, int64_t n, float r_filter,
  *              (non-decreasing, cloud_off[0] = 0; empty clouds allowed)
  *   r_min      0 <= r_min <= r_max, finite; r_min = 0 disables pruning
  *   r_max      > 0, finite
- *   flags      CAPT_NO_PRUNE or 0
+ *   flags      0, CAPT_NO_PRUNE, CAPT_INDEXED_SETS or both.  With
+ *              CAPT_INDEXED_SETS the affordance sets store only the index of
+ *              each member (4 bytes instead of 16 per entry; the memory of
+ *              Sec. IV-B grows with the total set size) and every query reads a
+ *              member's coordinates from the forest's copy of the cloud: the
+ *              same answers, one more dependent load per scanned chunk.
  *   out        host; receives the forest
  * Each cloud of n points is padded with points at +inf to N = 2^D >= n
  * (Sec. IV-A).  Node i at depth d splits on axis d mod 3 at the coordinate of

@@ -24,6 +24,7 @@ CAPT_NO_PRUNE = 0x1
 CAPT_CHECK_RADII = 0x2
 CAPT_PER_CLOUD = 0x4
 CAPT_NO_GRAPH = 0x8
+CAPT_INDEXED_SETS = 0x10
 
 EXPORTS = [
     "capt_filter", "capt_filter_crop", "capt_build", "capt_build_filtered", "capt_collides",
@@ -202,8 +203,9 @@ def capt_filter(xyz, r_filter: float, base=None, reach=None, stream=None):
 
 
 def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=None,
-               stream=None) -> Forest:
-    """Alg. 1 for one cloud (xyz [n, 3]) or several (cloud_off host [ncloud+1])."""
+               stream=None, indexed: bool = False) -> Forest:
+    """Alg. 1 for one cloud (xyz [n, 3]) or several (cloud_off host [ncloud+1]).
+    indexed: the sets store point indices only (CAPT_INDEXED_SETS)."""
     import torch
     lib = load_library()
     xyz = _dev(xyz, torch.float32, 3, "xyz")
@@ -213,7 +215,7 @@ def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=No
     if off[-1] != xyz.shape[0]:
         raise ValueError("cloud_off[-1] must equal the number of points")
     h = C.c_void_p()
-    flags = 0 if prune else CAPT_NO_PRUNE
+    flags = (0 if prune else CAPT_NO_PRUNE) | (CAPT_INDEXED_SETS if indexed else 0)
     _check(lib.capt_build(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
                           float(r_max), flags, _stream(stream), C.byref(h)))
     return Forest(h.value, len(off) - 1, float(np.float32(r_min)), float(np.float32(r_max)),
@@ -221,7 +223,7 @@ def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=No
 
 
 def capt_build_filtered(xyz, r_filter: float, r_min: float, r_max: float, prune: bool = True,
-                        kept_index: bool = False, base=None, reach=None, stream=None):
+                        kept_index: bool = False, base=None, reach=None, stream=None, indexed: bool = False):
     """Filter (Alg. 2) then build (Alg. 1) of one cloud in one library call.
     Returns the forest, or (forest, kept original indices [n']) with kept_index."""
     import torch
@@ -232,7 +234,8 @@ def capt_build_filtered(xyz, r_filter: float, r_min: float, r_max: float, prune:
     h = C.c_void_p()
     m = C.c_int64()
     _check(lib.capt_build_filtered(_ptr(xyz), n, float(r_filter), _crop_arg(base, reach), float(r_min), float(r_max),
-                                   0 if prune else CAPT_NO_PRUNE, _ptr(idx),
+                                   (0 if prune else CAPT_NO_PRUNE) | (CAPT_INDEXED_SETS if indexed else 0),
+                                   _ptr(idx),
                                    C.byref(m), _stream(stream), C.byref(h)))
     f = Forest(h.value, 1, float(np.float32(r_min)), float(np.float32(r_max)))
     return (f, idx[:m.value]) if kept_index else f

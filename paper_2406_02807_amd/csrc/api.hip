@@ -430,7 +430,7 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
                   (double)r_max);
         return CAPT_EINVAL;
     }
-    if (flags & ~CAPT_NO_PRUNE) {
+    if (flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS)) {
         set_error("unknown build flags 0x%x", flags);
         return CAPT_EINVAL;
     }
@@ -478,7 +478,7 @@ capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, con
                   (double)r_max);
         return CAPT_EINVAL;
     }
-    if (flags & ~CAPT_NO_PRUNE) {
+    if (flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS)) {
         set_error("unknown build flags 0x%x", flags);
         return CAPT_EINVAL;
     }
@@ -695,7 +695,8 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     memcpy(&h, B, sizeof h);
     if (h.magic != BLOB_MAGIC || h.version != BLOB_VERSION || h.n < 0 || h.D < 0 || h.D > 30 ||
         h.N != ((int64_t)1 << h.D) || h.n > h.N || (h.n > 0 && h.N >= 2 * h.n) || h.set_total < 0 ||
-        !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max) {
+        !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max ||
+        (h.flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS))) {
         set_error("blob header is invalid");
         return CAPT_EINVAL;
     }
@@ -797,7 +798,8 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const size_t oPr = al(oRep + sizeof(int32_t) * (size_t)h.N);
     c.fixed_bytes = al(oPr + (size_t)h.N);
     c.fixed = dev_alloc(c.fixed_bytes, s);
-    c.sets_bytes = sets_bytes(E);
+    const bool indexed = (h.flags & CAPT_INDEXED_SETS) != 0;
+    c.sets_bytes = sets_bytes(E, indexed);
     c.sets = dev_alloc(c.sets_bytes, s);
     if (!c.fixed || !c.sets) {
         destroy_forest(f);
@@ -814,7 +816,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
         float *qx, *qy, *qz;
         int32_t *qi;
         float4 *qb;
-        sets_layout(c.sets, E, &qx, &qy, &qz, &qi, &qb);
+        sets_layout(c.sets, E, indexed, &qx, &qy, &qz, &qi, &qb);
         c.dev.px = qx;
         c.dev.py = qy;
         c.dev.pz = qz;
@@ -834,11 +836,15 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     if (!st) st = cp(const_cast<float *>(c.dev.pts), pts, sizeof(float) * 3 * (size_t)h.n);
     if (!st) st = cp(c.rep, rep, sizeof(int32_t) * (size_t)h.N);
     if (!st) st = cp(c.pruned_flag, pr, (size_t)h.N);
-    if (!st) st = cp(const_cast<float *>(c.dev.px), px.data(), sizeof(float) * E);
-    if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);
-    if (!st) st = cp(const_cast<float *>(c.dev.pz), pz.data(), sizeof(float) * E);
+    if (!indexed) {
+        if (!st) st = cp(const_cast<float *>(c.dev.px), px.data(), sizeof(float) * E);
+        if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);
+        if (!st) st = cp(const_cast<float *>(c.dev.pz), pz.data(), sizeof(float) * E);
+    }
     if (!st) st = cp(const_cast<int32_t *>(c.dev.pidx), pidx.data(), sizeof(int32_t) * E);
-    if (!st) st = chunk_boxes(c.dev.px, c.dev.py, c.dev.pz, c.dev.pidx, padded, const_cast<float4 *>(c.dev.cbox), s);
+    if (!st)
+        st = chunk_boxes(c.dev.px, c.dev.py, c.dev.pz, c.dev.pidx, c.dev.pts, padded, const_cast<float4 *>(c.dev.cbox),
+                         s);
     if (!st) st = upload_views(f, s);
     if (st) {
         destroy_forest(f);

@@ -557,9 +557,11 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         const uint64_t m = __ballot(ok);
         if (FILL && ok) {
             const uint32_t pos = out0 + cnt + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            px[pos] = x;
-            py[pos] = y;
-            pz[pos] = z;
+            if (px) {   // not for indexed sets
+                px[pos] = x;
+                py[pos] = y;
+                pz[pos] = z;
+            }
             pidx[pos] = id;
             lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
             hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
@@ -673,9 +675,11 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         }
     const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
     for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
-        px[out0 + k] = INFINITY;
-        py[out0 + k] = INFINITY;
-        pz[out0 + k] = INFINITY;
+        if (px) {
+            px[out0 + k] = INFINITY;
+            py[out0 + k] = INFINITY;
+            pz[out0 + k] = INFINITY;
+        }
         pidx[out0 + k] = -1;
     }
     if (lane == 0) {
@@ -1013,7 +1017,8 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
         return CAPT_EUNSUPPORTED;
     }
     const size_t E = (size_t)(tot[1] > 0 ? tot[1] : CHUNK);
-    const size_t bytes = sets_bytes(E);
+    const bool indexed = (C.dev.flags & CAPT_INDEXED_SETS) != 0;
+    const size_t bytes = sets_bytes(E, indexed);
     C.sets = dev_alloc(bytes, s);
     if (!C.sets) {
         set_error("device allocation of %zu bytes for affordance sets failed", bytes);
@@ -1023,7 +1028,7 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     float *px, *py, *pz;
     int32_t *pidx;
     float4 *cbox;
-    sets_layout(C.sets, E, &px, &py, &pz, &pidx, &cbox);
+    sets_layout(C.sets, E, indexed, &px, &py, &pz, &pidx, &cbox);
     C.dev.px = px;
     C.dev.py = py;
     C.dev.pz = pz;
@@ -1032,7 +1037,7 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
                        py, pz, pidx, const_cast<Leaf *>(C.dev.leaf));
     CAPT_LAUNCH_CHECK();
-    return chunk_boxes(px, py, pz, pidx, (int64_t)tot[1], cbox, s);
+    return chunk_boxes(px, py, pz, pidx, C.dev.pts, (int64_t)tot[1], cbox, s);
 }
 
 }  // namespace
@@ -1117,16 +1122,24 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
 
 namespace {
 __global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restrict__ py, const float *__restrict__ pz,
-                              const int32_t *__restrict__ pidx, int64_t nchunk, float4 *__restrict__ cbox) {
+                              const int32_t *__restrict__ pidx, const float *__restrict__ pts, int64_t nchunk,
+                              float4 *__restrict__ cbox) {
     // CHUNK consecutive lanes share one chunk: one entry each, then a
     // butterfly min / max over the group (padding entries do not count)
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = e / CHUNK;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (k < nchunk && pidx[e] >= 0) {
-        lo[0] = hi[0] = px[e];
-        lo[1] = hi[1] = py[e];
-        lo[2] = hi[2] = pz[e];
+    const int32_t id = k < nchunk ? pidx[e] : -1;
+    if (id >= 0) {
+        if (px) {
+            lo[0] = hi[0] = px[e];
+            lo[1] = hi[1] = py[e];
+            lo[2] = hi[2] = pz[e];
+        } else {   // indexed sets
+            lo[0] = hi[0] = pts[3 * (int64_t)id];
+            lo[1] = hi[1] = pts[3 * (int64_t)id + 1];
+            lo[2] = hi[2] = pts[3 * (int64_t)id + 2];
+        }
     }
 #pragma unroll
     for (int off = CHUNK / 2; off >= 1; off >>= 1) {
@@ -1143,25 +1156,27 @@ __global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restr
 }
 }  // namespace
 
-size_t sets_bytes(size_t E) {
-    return align256(sizeof(float) * E) * 3 + align256(sizeof(int32_t) * E) + align256(sizeof(float4) * 2 * (E / CHUNK + 1));
+size_t sets_bytes(size_t E, bool indexed) {
+    return align256(sizeof(float) * E) * (indexed ? 0 : 3) + align256(sizeof(int32_t) * E) +
+           align256(sizeof(float4) * 2 * (E / CHUNK + 1));
 }
 
-void sets_layout(void *base, size_t E, float **px, float **py, float **pz, int32_t **pidx, float4 **cbox) {
+void sets_layout(void *base, size_t E, bool indexed, float **px, float **py, float **pz, int32_t **pidx,
+                 float4 **cbox) {
     char *P = static_cast<char *>(base);
-    const size_t a = align256(sizeof(float) * E);
-    *px = reinterpret_cast<float *>(P);
-    *py = reinterpret_cast<float *>(P + a);
-    *pz = reinterpret_cast<float *>(P + 2 * a);
+    const size_t a = indexed ? 0 : align256(sizeof(float) * E);
+    *px = indexed ? nullptr : reinterpret_cast<float *>(P);
+    *py = indexed ? nullptr : reinterpret_cast<float *>(P + a);
+    *pz = indexed ? nullptr : reinterpret_cast<float *>(P + 2 * a);
     *pidx = reinterpret_cast<int32_t *>(P + 3 * a);
     *cbox = reinterpret_cast<float4 *>(P + 3 * a + align256(sizeof(int32_t) * E));
 }
 
-capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, int64_t entries,
-                        float4 *cbox, hipStream_t s) {
+capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, const float *pts,
+                        int64_t entries, float4 *cbox, hipStream_t s) {
     const int64_t nchunk = entries / CHUNK;
     if (nchunk <= 0) return CAPT_OK;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(nblk(nchunk * CHUNK)), dim3(TB), 0, s, px, py, pz, pidx, nchunk, cbox);
+    hipLaunchKernelGGL(k_chunk_boxes, dim3(nblk(nchunk * CHUNK)), dim3(TB), 0, s, px, py, pz, pidx, pts, nchunk, cbox);
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }

@@ -218,11 +218,14 @@ void free_cloud(CloudHost &c, hipStream_t s);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)
 // Bounding box of every CHUNK-entry chunk of the stored sets (padding skipped).
-capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, int64_t entries,
-                        float4 *cbox, hipStream_t s);
+// With px == NULL (indexed sets) the coordinates come from pts[pidx].
+capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, const float *pts,
+                        int64_t entries, float4 *cbox, hipStream_t s);
 // Bytes of the sets block for `entries` padded entries and its sub-arrays.
-size_t sets_bytes(size_t entries);
-void sets_layout(void *base, size_t entries, float **px, float **py, float **pz, int32_t **pidx, float4 **cbox);
+// indexed: no coordinate arrays (px, py, pz come back NULL).
+size_t sets_bytes(size_t entries, bool indexed);
+void sets_layout(void *base, size_t entries, bool indexed, float **px, float **py, float **pz, int32_t **pidx,
+                 float4 **cbox);
 
 // query.hip
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,
@@ -281,5 +284,24 @@ __device__ __forceinline__ float box_sqdist(float x, float y, float z, const flo
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Coordinates of set entry e: from the set arrays, or (indexed sets) from the
+// forest's point table; padding entries read as +inf either way.
+__device__ __forceinline__ void set_point(const CloudDev &C, int64_t e, float &x, float &y, float &z) {
+    if (C.flags & CAPT_INDEXED_SETS) {
+        const int32_t id = C.pidx[e];
+        if (id < 0) {
+            x = y = z = INFINITY;
+        } else {
+            x = C.pts[3 * (int64_t)id];
+            y = C.pts[3 * (int64_t)id + 1];
+            z = C.pts[3 * (int64_t)id + 2];
+        }
+    } else {
+        x = C.px[e];
+        y = C.py[e];
+        z = C.pz[e];
+    }
+}
 
 }  // namespace capt

@@ -76,7 +76,9 @@ __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t 
             int32_t mi = INT_MAX;
             for (uint32_t k = lane; k < ct; k += WAVE) {
                 const uint32_t e = st + k;
-                const float d2 = sqdist(ox, oy, oz, C.px[e], C.py[e], C.pz[e]);
+                float x, y, z;
+                set_point(C, e, x, y, z);
+                const float d2 = sqdist(ox, oy, oz, x, y, z);
                 const int32_t id = C.pidx[e];
                 if (d2 < m || (d2 == m && id < mi)) {
                     m = d2;

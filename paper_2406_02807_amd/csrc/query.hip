@@ -177,7 +177,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // order, so a skipped chunk holds no hit and the answer equals a scan of every
 // entry.  A hit retires its configuration: its spheres' ring chunks are
 // skipped and the level-1 prefix is rebuilt over the spheres still open.
-template <int U>
+template <int U, bool IDX, bool SLOTS>
 __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L, float4 q, bool valid, int gg,
                                           bool single, WaveLds &W) {
     const int lane = lane_id();
@@ -211,6 +211,9 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     const float *__restrict__ PX = C.px;
     const float *__restrict__ PY = C.py;
     const float *__restrict__ PZ = C.pz;
+    const int32_t *__restrict__ PI = C.pidx;
+    const float *__restrict__ PT = C.pts;
+    constexpr bool indexed = IDX;   // sets of point indices (CAPT_INDEXED_SETS)
 
     // Entry scan of the next `nproc` <= U*CPS ring chunks; true if a hit retired
     // a configuration (then `done` and `dead` are up to date).
@@ -234,9 +237,20 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             own[u] = o;
             s[u] = W.sph[o];
             const uint32_t e = ch * CHUNK + ((uint32_t)lane & (CHUNK - 1));
-            px[u] = in[u] ? ld32(PX, 4u * e) : 0.f;
-            py[u] = in[u] ? ld32(PY, 4u * e) : 0.f;
-            pz[u] = in[u] ? ld32(PZ, 4u * e) : 0.f;
+            if (indexed) {
+                // the entry's point index, then its coordinates in the point
+                // table; padding entries (index -1) are skipped
+                const int32_t id = in[u] ? ld32(PI, 4u * e) : -1;
+                in[u] = id >= 0;
+                const int64_t p3 = 3 * (int64_t)(id >= 0 ? id : 0);
+                px[u] = in[u] ? PT[p3] : 0.f;
+                py[u] = in[u] ? PT[p3 + 1] : 0.f;
+                pz[u] = in[u] ? PT[p3 + 2] : 0.f;
+            } else {
+                px[u] = in[u] ? ld32(PX, 4u * e) : 0.f;
+                py[u] = in[u] ? ld32(PY, 4u * e) : 0.f;
+                pz[u] = in[u] ? ld32(PZ, 4u * e) : 0.f;
+            }
         }
         bool hit[U];
         bool any = false;
@@ -251,8 +265,8 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             done = valid;
             return true;
         }
-        if (gg == SLOT) {
-            // four groups of 16 lanes: one ballot per group
+        if (SLOTS) {
+            // four groups of SLOT lanes (gg == SLOT): one ballot per group
             uint32_t gm = 0;
 #pragma unroll
             for (int c = 0; c < WAVE / SLOT; ++c) {
@@ -341,7 +355,7 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
 constexpr int NXCD = 8;
 constexpr int CTR_STRIDE = 16;   // one 64-byte line per counter
 
-template <int U>
+template <int U, bool IDX>
 __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float4 lds4[];
@@ -377,7 +391,7 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
                 if (t + 1 < tb) qn = load(t + 1);
                 const int64_t c0 = t * cpt;
                 const int nc = (int)min<int64_t>(cpt, ncfg - c0);
-                const bool hit = wave_tile<U>(C, Tl, L, q, lane < nc * g, g, 2 * g > nc * g, W);
+                const bool hit = wave_tile<U, IDX, false>(C, Tl, L, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         } else {
@@ -386,7 +400,7 @@ __global__ void k_collide_cloud(CloudDev C, const float4 *__restrict__ sph, int6
                 for (int s0 = 0; s0 < g && !hit; s0 += WAVE) {
                     const int ns = min(WAVE, g - s0);
                     const float4 q = lane < ns ? sph[t * g + s0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    hit = wave_tile<U>(C, Tl, L, q, lane < ns, WAVE, true, W);
+                    hit = wave_tile<U, IDX, false>(C, Tl, L, q, lane < ns, WAVE, true, W);
                     hit = __shfl(hit, 0, WAVE);
                 }
                 if (lane == 0) out[t] = (uint8_t)hit;
@@ -452,7 +466,7 @@ struct PaddedSrc {
 // U <= 2 is held to 64 VGPRs, so that eight waves fit per SIMD (32 per CU):
 // the kernel is bound by memory latency and more resident waves hide more
 // of it; U = 4 would spill at that budget.
-template <int U, class Src>
+template <int U, class Src, bool IDX>
 __global__ void __attribute__((amdgpu_waves_per_eu(U <= 2 ? 8 : 1, 8))) k_collide_slots(CloudDev C, Src src, int64_t ncfg, int g,
                                 uint8_t *__restrict__ out, int L, unsigned int *__restrict__ ctr, int chunk) {
     extern __shared__ float4 lds4[];
@@ -502,7 +516,7 @@ __global__ void __attribute__((amdgpu_waves_per_eu(U <= 2 ? 8 : 1, 8))) k_collid
         const int si = s0 + j;
         const bool valid = active && si < g;
         const float4 q = valid ? src(cfg, si, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool hit = wave_tile<U>(C, Tl, L, q, valid, SLOT, false, W);
+        bool hit = wave_tile<U, IDX, true>(C, Tl, L, q, valid, SLOT, false, W);
         hit = __shfl(hit, lead, WAVE);   // the slot's first lane always holds a sphere
         if (active) {
             if (hit || s0 + SLOT >= g) {
@@ -533,7 +547,7 @@ __global__ void k_reset_counter(unsigned int *ctr) {
 
 // The slot scheme of k_collide_slots over one fixed range of configurations
 // [c0, c1) of one cloud (no LDS tree levels); returns when all are answered.
-template <int U>
+template <int U, bool IDX>
 __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ sph, int g, int64_t c0, int64_t c1,
                                  uint8_t *__restrict__ out, WaveLds &W) {
     const int lane = lane_id();
@@ -558,7 +572,7 @@ __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ s
         const int si = s0 + j;
         const bool valid = active && si < g;
         const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool hit = wave_tile<U>(C, nullptr, 0, q, valid, SLOT, false, W);
+        bool hit = wave_tile<U, IDX, true>(C, nullptr, 0, q, valid, SLOT, false, W);
         hit = __shfl(hit, lead, WAVE);
         if (active) {
             if (hit || s0 + SLOT >= g) {
@@ -571,7 +585,7 @@ __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ s
     }
 }
 
-template <int U>
+template <int U, bool IDX>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
                                   const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
@@ -586,14 +600,14 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
         const Tile tile = tiles[t];
         const CloudDev C = clouds[tile.cloud];
         if (g > SLOT) {
-            slots_over_range<U>(C, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
+            slots_over_range<U, IDX>(C, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
         } else {
             const int cpt = WAVE / g;
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const bool hit = wave_tile<U>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
+                const bool hit = wave_tile<U, IDX, false>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         }
@@ -678,7 +692,9 @@ __global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_
         for (uint32_t k = 0; k < L.count && !hit; ++k) {
             ++m;
             const uint32_t e = L.start + k;
-            hit = sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2;
+            float x, y, z;
+            set_point(C, e, x, y, z);
+            hit = sqdist(q.x, q.y, q.z, x, y, z) <= r2;
         }
     }
     if (leaf_out) leaf_out[s] = (int32_t)lf;
@@ -709,8 +725,11 @@ __global__ void k_chunk_stats(CloudDev C, const float4 *__restrict__ sph, int64_
             const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
             if (box_sqdist(q.x, q.y, q.z, lo, hi) > r2) continue;
             ++nc;
-            for (uint32_t e = c * CHUNK; e < (c + 1) * CHUNK && !hit; ++e)
-                hit = sqdist(q.x, q.y, q.z, C.px[e], C.py[e], C.pz[e]) <= r2;
+            for (uint32_t e = c * CHUNK; e < (c + 1) * CHUNK && !hit; ++e) {
+                float x, y, z;
+                set_point(C, e, x, y, z);
+                hit = sqdist(q.x, q.y, q.z, x, y, z) <= r2;
+            }
         }
     }
     if (boxes) boxes[s] = nb;
@@ -809,12 +828,12 @@ template <class K> bool allow_lds_once(K k) {
 }
 
 // Slot kernel over `nitem` items of `len` spheres each.
-template <class Src>
-capt_status launch_slots(const CloudDev &C, Src src, int64_t nitem, int len, uint8_t *out, unsigned int *ctr,
+template <class Src, bool IDX>
+capt_status launch_slots_t(const CloudDev &C, Src src, int64_t nitem, int len, uint8_t *out, unsigned int *ctr,
                          hipStream_t s) {
     if (nitem <= 0) return CAPT_OK;
-    static const bool lds_ok = allow_lds_once(k_collide_slots<4, Src>) && allow_lds_once(k_collide_slots<2, Src>) &&
-                               allow_lds_once(k_collide_slots<1, Src>);
+    static const bool lds_ok = allow_lds_once(k_collide_slots<4, Src, IDX>) && allow_lds_once(k_collide_slots<2, Src, IDX>) &&
+                               allow_lds_once(k_collide_slots<1, Src, IDX>);
     if (!lds_ok) {
         set_error("raising the dynamic LDS limit of the collision kernel failed");
         return CAPT_EHIP;
@@ -826,15 +845,15 @@ capt_status launch_slots(const CloudDev &C, Src src, int64_t nitem, int len, uin
     const dim3 grid((unsigned)sh.blocks), block(sh.threads);
     switch (tuning().scan_unroll) {
         case 4:
-            hipLaunchKernelGGL((k_collide_slots<4, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+            hipLaunchKernelGGL((k_collide_slots<4, Src, IDX>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
                                chunk);
             break;
         case 2:
-            hipLaunchKernelGGL((k_collide_slots<2, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+            hipLaunchKernelGGL((k_collide_slots<2, Src, IDX>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
                                chunk);
             break;
         default:
-            hipLaunchKernelGGL((k_collide_slots<1, Src>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
+            hipLaunchKernelGGL((k_collide_slots<1, Src, IDX>), grid, block, sh.lds, s, C, src, nitem, len, out, sh.L, ctr,
                                chunk);
             break;
     }
@@ -842,14 +861,22 @@ capt_status launch_slots(const CloudDev &C, Src src, int64_t nitem, int len, uin
     return CAPT_OK;
 }
 
-capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
+template <class Src>
+capt_status launch_slots(const CloudDev &C, Src src, int64_t nitem, int len, uint8_t *out, unsigned int *ctr,
+                         hipStream_t s) {
+    if (C.flags & CAPT_INDEXED_SETS) return launch_slots_t<Src, true>(C, src, nitem, len, out, ctr, s);
+    return launch_slots_t<Src, false>(C, src, nitem, len, out, ctr, s);
+}
+
+template <bool IDX>
+capt_status launch_cloud_t(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
                          unsigned int *ctr, hipStream_t s) {
     if (nsph <= 0) return CAPT_OK;
     const int64_t ncfg = nsph / g;
     const float4 *sp = reinterpret_cast<const float4 *>(spheres);
     if (g > SLOT) return launch_slots(C, SphereSrc{sp}, ncfg, g, out, ctr, s);   // slots: the queue holds configurations
-    static const bool lds_ok = allow_lds_once(k_collide_cloud<4>) && allow_lds_once(k_collide_cloud<2>) &&
-                               allow_lds_once(k_collide_cloud<1>);
+    static const bool lds_ok = allow_lds_once(k_collide_cloud<4, IDX>) && allow_lds_once(k_collide_cloud<2, IDX>) &&
+                               allow_lds_once(k_collide_cloud<1, IDX>);
     if (!lds_ok) {
         set_error("raising the dynamic LDS limit of the collision kernel failed");
         return CAPT_EHIP;
@@ -863,17 +890,23 @@ capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, 
     const dim3 grid((unsigned)sh.blocks), block(sh.threads);
     switch (tuning().scan_unroll) {
         case 4:
-            hipLaunchKernelGGL(k_collide_cloud<4>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
+            hipLaunchKernelGGL((k_collide_cloud<4, IDX>), grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
             break;
         case 2:
-            hipLaunchKernelGGL(k_collide_cloud<2>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
+            hipLaunchKernelGGL((k_collide_cloud<2, IDX>), grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
             break;
         default:
-            hipLaunchKernelGGL(k_collide_cloud<1>, grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
+            hipLaunchKernelGGL((k_collide_cloud<1, IDX>), grid, block, sh.lds, s, C, sp, nsph, g, out, sh.L, ctr, chunk);
             break;
     }
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
+}
+
+capt_status launch_cloud(const CloudDev &C, const float *spheres, int64_t nsph, int32_t g, uint8_t *out,
+                         unsigned int *ctr, hipStream_t s) {
+    if (C.flags & CAPT_INDEXED_SETS) return launch_cloud_t<true>(C, spheres, nsph, g, out, ctr, s);
+    return launch_cloud_t<false>(C, spheres, nsph, g, out, ctr, s);
 }
 
 capt_status make_plan(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, uint8_t *out,
@@ -919,7 +952,8 @@ capt_status make_plan(capt_forest_s *f, const float *spheres, const int64_t *qof
     return CAPT_OK;
 }
 
-capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
+template <bool IDX>
+capt_status enqueue_batched_t(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
     const capt_tuning &t = tuning();
     const int threads = WAVE * std::max(1, std::min(16, (int)t.waves_per_group));
     int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
@@ -932,21 +966,26 @@ capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
         const float4 *sp = reinterpret_cast<const float4 *>(p->spheres);
         switch (t.scan_unroll) {
             case 4:
-                hipLaunchKernelGGL(k_collide_batched<4>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
+                hipLaunchKernelGGL((k_collide_batched<4, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
             case 2:
-                hipLaunchKernelGGL(k_collide_batched<2>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
+                hipLaunchKernelGGL((k_collide_batched<2, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
             default:
-                hipLaunchKernelGGL(k_collide_batched<1>, dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
+                hipLaunchKernelGGL((k_collide_batched<1, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
                                    p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
                 break;
         }
         CAPT_LAUNCH_CHECK();
     }
     return CAPT_OK;
+}
+
+capt_status enqueue_batched(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
+    if (f->flags & CAPT_INDEXED_SETS) return enqueue_batched_t<true>(f, p, s);
+    return enqueue_batched_t<false>(f, p, s);
 }
 
 bool same_tuning(const capt_tuning &a, const capt_tuning &b) {

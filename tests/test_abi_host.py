@@ -85,7 +85,7 @@ def test_no_gpu_needed_for_validation(lib):
     assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, None) == capt.CAPT_EINVAL
     assert bf(P(1), 10, -0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     assert bf(P(1), 10, 0.01, None, 0.05, 0.01, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
-    assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0x10, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0x80, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     assert bf(None, 10, 0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     assert bf(P(1), 10, 0.01, bad_crop, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     # cropped filter: NULL / non-finite base / negative reach / NULL count

@@ -256,6 +256,48 @@ def test_collides_padded_radius_check_and_forest(capt, orc):
     assert e.value.status == capt.CAPT_EINVAL
 
 
+def test_indexed_sets_give_the_same_answers(capt, orc):
+    _say("case: indexed sets against plain sets")
+    cloud = synth.tabletop_cloud(50_000, 2001)
+    keep, _ = orc.filter(cloud, 0.01)
+    pts = cloud[keep]
+    x = dev(pts)
+    f = capt.capt_build(x, 0.015, 0.08)
+    fi = capt.capt_build(x, 0.015, 0.08, indexed=True)
+    assert fi.info()["bytes"] < 0.6 * f.info()["bytes"]
+    a, b = capt.parse_blob(capt.capt_export(f)), capt.parse_blob(capt.capt_export(fi))
+    assert b.flags == a.flags | capt.CAPT_INDEXED_SETS
+    assert np.array_equal(bits(a.T), bits(b.T)) and np.array_equal(a.off, b.off) and np.array_equal(a.idx, b.idx)
+    assert np.array_equal(a.aabb, b.aabb)
+    sph60 = synth.posed_spheres(synth.chain_template(2003), 3001, synth.WORKSPACE, 92)
+    for g, sp in ((1, synth.uniform_spheres(30_000, synth.WORKSPACE, 0.015, 0.08, 93)), (7, sph60[:7 * 3000]),
+                  (60, sph60)):
+        want = capt.capt_collides(f, dev(sp), g).cpu().numpy()
+        assert np.array_equal(capt.capt_collides(fi, dev(sp), g).cpu().numpy(), want), g
+        if g == 60:
+            assert np.array_equal(want, orc.brute_f32(pts, sp, 60))
+    assert np.array_equal(capt.capt_collides_padded(fi, dev(sph60), 60, 0.0).cpu().numpy(),
+                          capt.capt_collides(f, dev(sph60), 60).cpu().numpy())
+    for u, v in zip(capt.capt_query_stats(f, dev(sph60)), capt.capt_query_stats(fi, dev(sph60))):
+        assert torch.equal(u, v)
+    for u, v in zip(capt.capt_query_chunk_stats(f, dev(sph60)), capt.capt_query_chunk_stats(fi, dev(sph60))):
+        assert torch.equal(u, v)
+    # posed edges and an imported indexed forest
+    tm = synth.chain_template(2003).astype(np.float32)
+    poses = synth.pose_edges(500, 4, synth.WORKSPACE, 95)
+    assert torch.equal(capt.capt_collides_posed(fi, dev(tm), dev(poses), 4),
+                       capt.capt_collides_posed(f, dev(tm), dev(poses), 4))
+    fj = capt.capt_import(capt.capt_export(fi))
+    assert torch.equal(capt.capt_collides(fj, dev(sph60), 60), capt.capt_collides(f, dev(sph60), 60))
+    # clearance on unpruned forests
+    fu = capt.capt_build(x, 0.0, 0.08)
+    fui = capt.capt_build(x, 0.0, 0.08, indexed=True)
+    sc = dev(synth.uniform_spheres(20_000, synth.WORKSPACE, 0.015, 0.08, 96))
+    ca, wa = capt.capt_clearance(fu, sc)
+    cb, wb = capt.capt_clearance(fui, sc)
+    assert torch.equal(ca, cb) and torch.equal(wa, wb)
+
+
 def test_stream_ordered_release(capt, orc):
     # per-frame pattern: build, query and release in stream order without a
     # host wait; later builds reuse the released memory behind earlier queries
