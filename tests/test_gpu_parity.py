@@ -298,6 +298,42 @@ def test_indexed_sets_give_the_same_answers(capt, orc):
     assert torch.equal(ca, cb) and torch.equal(wa, wb)
 
 
+def test_edge_cases_of_the_frame_calls(capt, orc):
+    _say("case: frame-call edge cases")
+    pts = synth.tabletop_cloud(5000, 41)
+    x = dev(pts)
+    # a crop that removes every point: an empty forest that answers no
+    f, ki = capt.capt_build_filtered(x, 0.01, 0.015, 0.08, kept_index=True, base=(50.0, 50.0, 50.0), reach=1.0)
+    assert ki.numel() == 0 and f.info()["n"] == 0
+    sph = synth.uniform_spheres(600, synth.WORKSPACE, 0.015, 0.08, 42)
+    assert int(capt.capt_collides(f, dev(sph), 60).sum()) == 0
+    # reach 0 keeps exactly the points at the base (the duplicate goes to the filter)
+    one = np.array([[0.25, 0.5, 0.75], [0.25, 0.5, 0.75000006], [0.25, 0.5, 0.75]], np.float32)
+    fx, fi = capt.capt_filter(dev(one), 0.0, base=(0.25, 0.5, 0.75), reach=0.0)
+    want, _ = orc.filter(one, 0.0, base=(0.25, 0.5, 0.75), reach=0.0)
+    assert fi.cpu().numpy().tolist() == want.tolist() == [0]
+    # padded queries: no spheres, and group 1
+    fp = capt.capt_build(x, 0.015, 0.08)
+    assert capt.capt_collides_padded(fp, dev(np.zeros((0, 4), np.float32)), 1, 0.01).numel() == 0
+    sp1 = synth.uniform_spheres(5000, synth.WORKSPACE, 0.015, 0.06, 43)
+    assert np.array_equal(capt.capt_collides_padded(fp, dev(sp1), 1, 0.02).cpu().numpy(),
+                          orc.brute_f32(pts, sp1, 1, pad=0.02))
+    # indexed batched forest against plain, and stream-ordered release of a forest with a batched plan
+    clouds = [synth.tabletop_cloud(2000 + 1000 * c, 300 + c) for c in range(3)]
+    off = np.cumsum([0] + [len(c) for c in clouds]).tolist()
+    qs = [synth.uniform_spheres(60 * 400, synth.WORKSPACE, 0.015, 0.08, 310 + c) for c in range(3)]
+    qoff = np.cumsum([0] + [len(q) for q in qs]).tolist()
+    fa = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off)
+    fb = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off, indexed=True)
+    a = capt.capt_collides(fa, dev(np.concatenate(qs)), 60, query_off=qoff)
+    b = capt.capt_collides(fb, dev(np.concatenate(qs)), 60, query_off=qoff)
+    assert torch.equal(a, b)
+    assert np.array_equal(a.cpu().numpy(), np.concatenate([orc.brute_f32(c, q, 60) for c, q in zip(clouds, qs)]))
+    fa.release()
+    fb.release()
+    torch.cuda.synchronize()
+
+
 def test_stream_ordered_release(capt, orc):
     # per-frame pattern: build, query and release in stream order without a
     # host wait; later builds reuse the released memory behind earlier queries
