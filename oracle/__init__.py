@@ -16,7 +16,9 @@ Functions and what they follow:
   clearance_f64    nearest-point distance clamped at r_max, minus r, and its
                    gradient (not in the paper; defined for the differentiable
                    query)
-  build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning
+  build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning; split
+                   axis d mod 3, or a given axis per depth (the alternative
+                   to the cyclic rule that Sec. IV-A mentions)
   query            CollisionCheck (Alg. 3, Sec. IV-D) on a tree given as arrays
   morton_key       Z-order key (Sec. II-B, Sec. IV-C)
   filter           Filter (Alg. 2, Sec. IV-C), optionally after crop
@@ -65,12 +67,12 @@ def _load():
             "orc_pose_spheres": (None, [P, i32, P, i64, P]),
             "orc_brute_f64": (None, [P, i64, P, i64, P, P]),
             "orc_clearance_f64": (None, [P, i64, P, i64, f32, P, P, P]),
-            "orc_build": (P, [P, i64, f32, f32, C.c_int]),
+            "orc_build": (P, [P, i64, f32, f32, C.c_int, P]),
             "orc_tree_dims": (None, [P, P, P, P, P]),
             "orc_tree_copy": (None, [P, P, P, P, P, P, P, P]),
             "orc_tree_free": (None, [P]),
-            "orc_query": (None, [i64, i32, P, P, P, P, P, i64, P, P, P, P]),
-            "orc_query_serial": (None, [i64, i32, P, P, P, P, P, i64, i32, P]),
+            "orc_query": (None, [i64, i32, P, P, P, P, P, i64, P, P, P, P, P]),
+            "orc_query_serial": (None, [i64, i32, P, P, P, P, P, i64, i32, P, P]),
             "orc_morton_key": (C.c_uint64, [P, C.c_int]),
             "orc_morton_grid": (None, [P, i64, P, P]),
             "orc_morton_cell": (None, [P, P, C.c_double, P]),
@@ -163,15 +165,22 @@ class Tree:
     pruned: np.ndarray   # uint8 [N]
     off: np.ndarray      # int64 [N+1]
     idx: np.ndarray      # int32 [off[N]], each set sorted by original index
+    axes: np.ndarray = None   # uint8 [D] split axis per depth (None: d mod 3)
 
     def set_of(self, leaf: int) -> np.ndarray:
         return self.idx[self.off[leaf]:self.off[leaf + 1]]
 
 
-def build_tree(points, r_min: float, r_max: float, prune: bool = True) -> Tree:
+def _axes(axes):
+    return None if axes is None else np.ascontiguousarray(axes, dtype=np.uint8)
+
+
+def build_tree(points, r_min: float, r_max: float, prune: bool = True, axes=None) -> Tree:
+    """Construct; `axes` gives the split axis of each depth (default d mod 3)."""
     pts = _f32(points, 3)
     lib = _load()
-    h = lib.orc_build(_p(pts), len(pts), np.float32(r_min), np.float32(r_max), int(prune))
+    ax = _axes(axes)
+    h = lib.orc_build(_p(pts), len(pts), np.float32(r_min), np.float32(r_max), int(prune), _p(ax))
     try:
         n, N, D, tot = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
         lib.orc_tree_dims(h, C.byref(n), C.byref(N), C.byref(D), C.byref(tot))
@@ -188,12 +197,13 @@ def build_tree(points, r_min: float, r_max: float, prune: bool = True) -> Tree:
     finally:
         lib.orc_tree_free(h)
     return Tree(n.value, N_, D.value, float(np.float32(r_min)), float(np.float32(r_max)),
-                T, rep, cell, aabb, pruned, off, idx[:tot.value])
+                T, rep, cell, aabb, pruned, off, idx[:tot.value], None if ax is None else ax[:D.value].copy())
 
 
-def query(N: int, D: int, T, aabb, off, setxyz, spheres):
+def query(N: int, D: int, T, aabb, off, setxyz, spheres, axes=None):
     """CollisionCheck (Alg. 3) per sphere on a tree given as arrays.  Returns
-    (hit u8 [m], leaf i32 [m], aabb_rejected u8 [m], scanned i32 [m])."""
+    (hit u8 [m], leaf i32 [m], aabb_rejected u8 [m], scanned i32 [m]).
+    `axes`: split axis per depth (default d mod 3)."""
     sph = _f32(spheres, 4)
     m = len(sph)
     T = np.ascontiguousarray(T, dtype=np.float32)
@@ -206,17 +216,17 @@ def query(N: int, D: int, T, aabb, off, setxyz, spheres):
     scanned = np.zeros(m, dtype=np.int32)
     _load().orc_query(N, D, _p(T) if len(T) else None, _p(aabb), _p(off),
                       _p(setxyz) if len(setxyz) else None, _p(sph), m,
-                      _p(hit), _p(leaf), _p(rej), _p(scanned))
+                      _p(hit), _p(leaf), _p(rej), _p(scanned), _p(_axes(axes)))
     return hit, leaf, rej, scanned
 
 
 def query_tree(tree: Tree, points, spheres):
     """Alg. 3 on an oracle tree; set points are stored in sorted-index order."""
     pts = _f32(points, 3)
-    return query(tree.N, tree.D, tree.T, tree.aabb, tree.off, pts[tree.idx], spheres)
+    return query(tree.N, tree.D, tree.T, tree.aabb, tree.off, pts[tree.idx], spheres, tree.axes)
 
 
-def query_serial(N: int, D: int, T, aabb, off, setxyz, spheres, group: int) -> np.ndarray:
+def query_serial(N: int, D: int, T, aabb, off, setxyz, spheres, group: int, axes=None) -> np.ndarray:
     """Single-threaded Alg. 3 with per-configuration early exit."""
     sph = _f32(spheres, 4)
     T = np.ascontiguousarray(T, dtype=np.float32)
@@ -226,7 +236,7 @@ def query_serial(N: int, D: int, T, aabb, off, setxyz, spheres, group: int) -> n
     out = np.zeros(len(sph) // group, dtype=np.uint8)
     _load().orc_query_serial(N, D, _p(T) if len(T) else None, _p(aabb), _p(off),
                              _p(setxyz) if len(setxyz) else None, _p(sph), len(sph),
-                             group, _p(out))
+                             group, _p(out), _p(_axes(axes)))
     return out
 
 

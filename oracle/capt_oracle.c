@@ -181,6 +181,7 @@ typedef struct {
     int32_t D;
     float r_min, r_max;
     int prune;
+    uint8_t axes[64];      /* split axis of every depth (d mod 3 unless given) */
     const float *pts;      /* [n][3] input */
     float *T;              /* [N-1] test sequence, Eytzinger order */
     int32_t *rep;          /* [N] representative index per leaf (>= n: padding) */
@@ -266,7 +267,7 @@ static const float *point(const orc_tree *t, int32_t i)
 }
 
 static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
-                      int32_t *z, int64_t nz, int64_t i, int d)
+                      int32_t *z, int64_t nz, int64_t i, int depth)
 {
     double R2 = R_afford2(t->r_max);
     if (m == 1) {
@@ -296,7 +297,8 @@ static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
         t->sets[leaf] = set;
         return;
     }
-    /* median split along axis d under (coordinate, index) */
+    /* median split along the axis of this depth under (coordinate, index) */
+    const int d = t->axes[depth];
     sort_ctx sc = {t->pts, t->n, d};
     qsort_r(pc, (size_t)m, sizeof(int32_t), cmp_coord_index, &sc);
     int64_t h = m / 2;
@@ -322,20 +324,25 @@ static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
         if (B2[j] < t->n && affords(c1, point(t, B2[j]), R2)) z1[n1++] = B2[j];
         if (B1[j] < t->n && affords(c2, point(t, B1[j]), R2)) z2[n2++] = B1[j];
     }
-    int dn = (d + 1) % 3;
     /* each child re-sorts only its own half of pc */
-    construct(t, B1, h, c1, z1, n1, 2 * i + 1, dn);
+    construct(t, B1, h, c1, z1, n1, 2 * i + 1, depth + 1);
     free(z1);
-    construct(t, B2, h, c2, z2, n2, 2 * i + 2, dn);
+    construct(t, B2, h, c2, z2, n2, 2 * i + 2, depth + 1);
     free(z2);
 }
 
-ORC_API orc_tree *orc_build(const float *pts, int64_t n, float r_min, float r_max, int prune)
+/* axes: the split axis (0, 1, 2) of each depth 0 .. D-1, or NULL for the
+ * cyclic rule d mod 3 of Sec. IV-A (the paper names a random choice of axis
+ * as an alternative; here a sequence of axes per depth keeps the tree
+ * implicit). */
+ORC_API orc_tree *orc_build(const float *pts, int64_t n, float r_min, float r_max, int prune,
+                            const uint8_t *axes)
 {
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     int64_t N = 1;
     int D = 0;
     while (N < n) { N <<= 1; ++D; }
+    for (int d = 0; d < 64; ++d) t->axes[d] = (uint8_t)(axes && d < D ? axes[d] : d % 3);
     t->n = n; t->N = N; t->D = D;
     t->r_min = r_min; t->r_max = r_max; t->prune = prune;
     t->pts = pts;
@@ -424,17 +431,17 @@ static int aabb_rejects(const float *bb, const float *s)
 ORC_API void orc_query(int64_t N, int32_t D, const float *T, const float *aabb,
                        const int64_t *off, const float *setxyz,
                        const float *sph, int64_t m,
-                       uint8_t *hit, int32_t *leaf, uint8_t *rejected, int32_t *scanned)
+                       uint8_t *hit, int32_t *leaf, uint8_t *rejected, int32_t *scanned,
+                       const uint8_t *axes)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < m; ++s) {
         const float *q = sph + 4 * s;
         int64_t i = 0;
-        int d = 0;
         for (int lv = 0; lv < D; ++lv) {
+            const int d = axes ? axes[lv] : lv % 3;
             if (q[d] <= T[i]) i = 2 * i + 1;
             else i = 2 * i + 2;
-            d = (d + 1) % 3;
         }
         int64_t l = i - (N - 1);
         int h = 0, rej = 0;
@@ -458,18 +465,18 @@ ORC_API void orc_query(int64_t N, int32_t D, const float *T, const float *aabb,
  * figure; same arithmetic, no OpenMP. */
 ORC_API void orc_query_serial(int64_t N, int32_t D, const float *T, const float *aabb,
                               const int64_t *off, const float *setxyz,
-                              const float *sph, int64_t m, int32_t g, uint8_t *out)
+                              const float *sph, int64_t m, int32_t g, uint8_t *out,
+                              const uint8_t *axes)
 {
     for (int64_t c = 0; c < m / g; ++c) {
         int any = 0;
         for (int64_t s = c * g; s < (c + 1) * g && !any; ++s) {
             const float *q = sph + 4 * s;
             int64_t i = 0;
-            int d = 0;
             for (int lv = 0; lv < D; ++lv) {
+                const int d = axes ? axes[lv] : lv % 3;
                 if (q[d] <= T[i]) i = 2 * i + 1;
                 else i = 2 * i + 2;
-                d = (d + 1) % 3;
             }
             int64_t l = i - (N - 1);
             if (aabb_rejects(aabb + 6 * l, q)) continue;

@@ -238,3 +238,86 @@ def test_nonfinite_query_centres(orc):
     sph = np.array([[np.nan, 0.5, 0.5, 0.05], [0.5, np.nan, 0.5, 0.05], [np.inf, 0.5, 0.5, 0.05],
                     [-np.inf, -np.inf, -np.inf, 0.05], [0.5, 0.5, np.nan, 0.05]], np.float32)
     assert orc.query_tree(t, pts, sph)[0].tolist() == [0] * 5
+
+
+# ---------------------------------------------------------------------------
+# Split axis per depth (the alternative to the cyclic rule, Sec. IV-A)
+# ---------------------------------------------------------------------------
+AXES = {
+    "random": np.random.default_rng(71).integers(0, 3, 64).astype(np.uint8),
+    "x-only": np.zeros(64, np.uint8),
+    "z-y": np.tile(np.array([2, 1], np.uint8), 32),
+}
+
+
+def test_cyclic_axes_equal_the_default(orc):
+    for name in ("uniform-200", "dups-50", "pow2p1"):
+        pts = CLOUDS[name]
+        a = orc.build_tree(pts, 0.01, 0.05)
+        b = orc.build_tree(pts, 0.01, 0.05, axes=np.arange(64) % 3)
+        for f in ("T", "rep", "cell", "aabb", "pruned", "off", "idx"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), (name, f)
+
+
+@pytest.mark.parametrize("seq", sorted(AXES))
+@pytest.mark.parametrize("name", ["uniform-200", "uniform-37", "dups-50", "collinear-33", "coplanar-48", "pow2p1"])
+def test_structure_invariants_any_axes(orc, name, seq):
+    pts = CLOUDS[name]
+    n = len(pts)
+    axes = AXES[seq]
+    t = orc.build_tree(pts, 0.01, 0.05, axes=axes)
+    assert sorted(t.rep.tolist()) == list(range(t.N))
+    padded = np.concatenate([pts, np.full((t.N - n, 3), np.inf, np.float32)])
+    for i in range(t.N - 1):
+        ax = int(axes[int(np.floor(np.log2(i + 1)))])
+        left, right = _node_points(t, 2 * i + 1), _node_points(t, 2 * i + 2)
+        order = sorted(np.concatenate([left, right]).tolist(), key=lambda j: (padded[j, ax], j))
+        assert set(order[:len(left)]) == set(left.tolist())
+        assert t.T[i] == padded[order[len(left) - 1], ax]
+    for l in range(t.N):
+        p = padded[t.rep[l]]
+        assert (t.cell[l, :3] <= p).all() and (p <= t.cell[l, 3:]).all()
+
+
+@pytest.mark.parametrize("seq", sorted(AXES))
+@pytest.mark.parametrize("name", ["uniform-37", "lattice-64", "coplanar-48", "pow2p1"])
+def test_sets_match_direct_definition_any_axes(orc, name, seq):
+    pts = CLOUDS[name]
+    t = orc.build_tree(pts, 0.0, 0.05, axes=AXES[seq])
+    rmax = Fraction(float(np.float32(0.05)))
+    R = rmax * (1 + Fraction(1, 2 ** 20))
+    for l in range(t.N):
+        s = set(t.set_of(l).tolist())
+        for j in range(len(pts)):
+            d2 = _exact_cell_dist2(pts[j], t.cell[l])
+            if d2 is not None and d2 <= rmax ** 2:
+                assert j in s, (l, j)
+            if j in s:
+                assert d2 is not None and d2 <= R ** 2, (l, j)
+
+
+@pytest.mark.parametrize("seq", sorted(AXES))
+@pytest.mark.parametrize("name", ["uniform-200", "dups-50", "collinear-33", "lattice-64"])
+def test_lemma1_any_axes(orc, name, seq):
+    pts = CLOUDS[name]
+    rng = np.random.default_rng(17)
+    t = orc.build_tree(pts, 0.01, 0.05, axes=AXES[seq])
+    lo, hi = pts.min(0) - 0.1, pts.max(0) + 0.1
+    cen = lo + rng.random((4000, 3)) * (hi - lo)
+    # and centres on split planes of the given axes
+    planes = []
+    for i in rng.integers(0, max(t.N - 1, 1), 1000):
+        if t.N == 1 or not np.isfinite(t.T[i]):
+            continue
+        q = pts[rng.integers(0, len(pts))].astype(np.float64)
+        q[int(AXES[seq][int(np.floor(np.log2(i + 1)))])] = t.T[i]
+        planes.append(q)
+    cen = np.concatenate([cen, np.array(planes).reshape(-1, 3)])
+    rad = rng.uniform(0.01, 0.05, len(cen))
+    sph = np.concatenate([cen, rad[:, None]], 1).astype(np.float32)
+    hit = orc.query_tree(t, pts, sph)[0]
+    assert (hit == orc.brute_f32(pts, sph)).all()
+    # the wrong axes at query time send spheres to the wrong leaves
+    if seq != "random" and name in ("uniform-200", "lattice-64"):
+        wrong = orc.query(t.N, t.D, t.T, t.aabb, t.off, pts[t.idx], sph, axes=(AXES[seq] + 1) % 3)[0]
+        assert not (wrong == hit).all()
