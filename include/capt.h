@@ -129,6 +129,21 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
                        capt_forest *out);
 
 /*
+ * capt_build with the split axis of every depth given (Sec. IV-A names a
+ * random choice of axis as an alternative to the cyclic rule): depth d
+ * splits on axis axes[d] instead of d mod 3, the same axis across a depth,
+ * so the tree stays implicit; the caller draws the axes (for example at
+ * random).  Queries, clearance, counters and export follow the stored axes.
+ *   axes       host [30]; values 0 (x), 1 (y), 2 (z); entries past the
+ *              depth are ignored
+ * A forest of several clouds with non-cyclic axes answers capt_collides with
+ * one launch per cloud (the batched kernel takes cyclic forests only).
+ */
+capt_status capt_build_axes(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                            float r_min, float r_max, uint32_t flags, const uint8_t *axes,
+                            void *stream, capt_forest *out);
+
+/*
  * Per-frame rebuild (Sec. IV-C followed by Sec. IV-A/B): capt_filter (or,
  * with crop, capt_filter_crop) of one cloud, then capt_build of the kept
  * points, in one call with no host work between the two.  The forest equals

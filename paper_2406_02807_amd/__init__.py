@@ -27,7 +27,7 @@ CAPT_NO_GRAPH = 0x8
 CAPT_INDEXED_SETS = 0x10
 
 EXPORTS = [
-    "capt_filter", "capt_filter_crop", "capt_build", "capt_build_filtered", "capt_collides",
+    "capt_filter", "capt_filter_crop", "capt_build", "capt_build_axes", "capt_build_filtered", "capt_collides",
     "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
@@ -62,6 +62,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "capt_filter": [P, i64, f32, P, P, P, P],
         "capt_build": [P, P, i32, f32, f32, u32, P, P],
+        "capt_build_axes": [P, P, i32, f32, f32, u32, P, P, P],
         "capt_build_filtered": [P, i64, f32, P, f32, f32, u32, P, P, P, P],
         "capt_filter_crop": [P, i64, f32, P, P, P, P, P],
         "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
@@ -203,9 +204,10 @@ def capt_filter(xyz, r_filter: float, base=None, reach=None, stream=None):
 
 
 def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=None,
-               stream=None, indexed: bool = False) -> Forest:
+               stream=None, indexed: bool = False, axes=None) -> Forest:
     """Alg. 1 for one cloud (xyz [n, 3]) or several (cloud_off host [ncloud+1]).
-    indexed: the sets store point indices only (CAPT_INDEXED_SETS)."""
+    indexed: the sets store point indices only (CAPT_INDEXED_SETS).
+    axes: split axis of every depth (capt_build_axes), default d mod 3."""
     import torch
     lib = load_library()
     xyz = _dev(xyz, torch.float32, 3, "xyz")
@@ -216,8 +218,16 @@ def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=No
         raise ValueError("cloud_off[-1] must equal the number of points")
     h = C.c_void_p()
     flags = (0 if prune else CAPT_NO_PRUNE) | (CAPT_INDEXED_SETS if indexed else 0)
-    _check(lib.capt_build(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
-                          float(r_max), flags, _stream(stream), C.byref(h)))
+    if axes is None:
+        _check(lib.capt_build(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
+                              float(r_max), flags, _stream(stream), C.byref(h)))
+    else:
+        ax = np.zeros(32, np.uint8)
+        a = np.asarray(axes, np.uint8)[:32]
+        ax[:len(a)] = a
+        _check(lib.capt_build_axes(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
+                                   float(r_max), flags, ax.ctypes.data_as(C.c_void_p), _stream(stream),
+                                   C.byref(h)))
     return Forest(h.value, len(off) - 1, float(np.float32(r_min)), float(np.float32(r_max)),
                   clouds=(xyz, off))
 
@@ -435,13 +445,14 @@ class Blob:
     pruned: np.ndarray   # uint8 [N]
     off: np.ndarray      # int64 [N+1]
     idx: np.ndarray      # int32 [S]
+    axes: np.ndarray = None   # uint8 [D] split axis per depth (None: d mod 3)
 
     def set_of(self, leaf):
         return self.idx[self.off[leaf]:self.off[leaf + 1]]
 
 
-def _layout(n, N, S):
-    o = _a8(_HDR.size)
+def _layout(n, N, S, version=1):
+    o = _a8(_HDR.size + (8 if version >= 2 else 0))   # version 2: the axis code follows the header
     lay = {}
     for name, size in (("pts", 12 * n), ("T", 4 * (N - 1)), ("rep", 4 * N), ("aabb", 24 * N),
                        ("pruned", N), ("off", 8 * (N + 1)), ("idx", 4 * S)):
@@ -453,9 +464,13 @@ def _layout(n, N, S):
 
 def parse_blob(blob: bytes) -> Blob:
     magic, ver, n, N, D, flags, r_min, r_max, S = _HDR.unpack_from(blob, 0)
-    if magic != BLOB_MAGIC or ver != 1:
+    if magic != BLOB_MAGIC or ver not in (1, 2):
         raise ValueError("not a CAPT blob")
-    L = _layout(n, N, S)
+    L = _layout(n, N, S, ver)
+    axes = None
+    if ver >= 2:
+        code = struct.unpack_from("<Q", blob, _HDR.size)[0]
+        axes = np.array([(code >> (2 * d)) & 3 for d in range(D)], np.uint8)
     f = np.frombuffer
     return Blob(n, N, D, flags, r_min, r_max,
                 f(blob, np.float32, 3 * n, L["pts"]).reshape(n, 3).copy(),
@@ -464,21 +479,28 @@ def parse_blob(blob: bytes) -> Blob:
                 f(blob, np.float32, 6 * N, L["aabb"]).reshape(N, 6).copy(),
                 f(blob, np.uint8, N, L["pruned"]).copy(),
                 f(blob, np.int64, N + 1, L["off"]).copy(),
-                f(blob, np.int32, S, L["idx"]).copy())
+                f(blob, np.int32, S, L["idx"]).copy(), axes)
 
 
-def make_blob(points, T, rep, aabb, pruned, off, idx, r_min, r_max, flags=0) -> bytes:
+def make_blob(points, T, rep, aabb, pruned, off, idx, r_min, r_max, flags=0, axes=None) -> bytes:
     """Pack tree arrays (for example a tree built elsewhere) into the blob
-    format that capt_import reads."""
+    format that capt_import reads; `axes` (split axis per depth) gives a
+    version-2 blob."""
     points = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
     n = len(points)
     N = len(rep)
     D = N.bit_length() - 1
     idx = np.ascontiguousarray(idx, np.int32)
     S = len(idx)
-    L = _layout(n, N, S)
+    ver = 1 if axes is None else 2
+    L = _layout(n, N, S, ver)
     buf = bytearray(L["total"])
-    _HDR.pack_into(buf, 0, BLOB_MAGIC, 1, n, N, D, flags, float(r_min), float(r_max), S)
+    _HDR.pack_into(buf, 0, BLOB_MAGIC, ver, n, N, D, flags, float(r_min), float(r_max), S)
+    if axes is not None:
+        code = 0
+        for d in range(D):
+            code |= int(axes[d]) << (2 * d)
+        struct.pack_into("<Q", buf, _HDR.size, code)
     for name, arr in (("pts", points), ("T", np.asarray(T, np.float32)), ("rep", np.asarray(rep, np.int32)),
                       ("aabb", np.asarray(aabb, np.float32)), ("pruned", np.asarray(pruned, np.uint8)),
                       ("off", np.asarray(off, np.int64)), ("idx", idx)):

@@ -264,7 +264,7 @@ void destroy_forest_async(capt_forest_s *f, hipStream_t s) {
 
 // ---- blob layout --------------------------------------------------------
 constexpr uint32_t BLOB_MAGIC = 0x54504143u;   // "CAPT"
-constexpr uint32_t BLOB_VERSION = 1;
+constexpr uint32_t BLOB_VERSION = 2;
 
 struct BlobHeader {
     uint32_t magic;
@@ -281,10 +281,12 @@ static_assert(sizeof(BlobHeader) == 48, "blob header is 48 bytes");
 
 inline size_t a8(size_t x) { return (x + 7) & ~(size_t)7; }
 
+// Version 2 (a forest with a non-cyclic split axis per depth) carries the
+// 8-byte axis code right after the header.
 struct BlobLayout {
     size_t pts, T, rep, aabb, pruned, off, idx, total;
-    BlobLayout(int64_t n, int64_t N, int64_t S) {
-        size_t o = a8(sizeof(BlobHeader));
+    BlobLayout(int64_t n, int64_t N, int64_t S, uint32_t version) {
+        size_t o = a8(sizeof(BlobHeader) + (version >= 2 ? sizeof(uint64_t) : 0));
         pts = o;    o = a8(o + sizeof(float) * 3 * (size_t)n);
         T = o;      o = a8(o + sizeof(float) * (size_t)(N - 1));
         rep = o;    o = a8(o + sizeof(int32_t) * (size_t)N);
@@ -407,9 +409,35 @@ capt_status capt_filter_crop(const float *xyz, int64_t n, float r_filter, const 
     return filter(xyz, n, r_filter, crop, out_xyz, out_index, n_out, (hipStream_t)stream);
 }
 
+namespace {
+capt_status build_entry(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
+                        uint32_t flags, const uint8_t *axes, void *stream, capt_forest *out);
+}  // namespace
+
 capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
                        uint32_t flags, void *stream, capt_forest *out) {
     ApiGuard g;
+    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, nullptr, stream, out);
+}
+
+capt_status capt_build_axes(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
+                            uint32_t flags, const uint8_t *axes, void *stream, capt_forest *out) {
+    ApiGuard g;
+    if (!axes) {
+        set_error("axes is NULL");
+        return CAPT_EINVAL;
+    }
+    for (int d = 0; d < 30; ++d)
+        if (axes[d] > 2) {
+            set_error("axes[%d] = %u is not an axis (0, 1, 2)", d, (unsigned)axes[d]);
+            return CAPT_EINVAL;
+        }
+    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, stream, out);
+}
+
+namespace {
+capt_status build_entry(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
+                        uint32_t flags, const uint8_t *axes, void *stream, capt_forest *out) {
     if (!out) {
         set_error("out is NULL");
         return CAPT_EINVAL;
@@ -439,7 +467,7 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
         set_error("host allocation failed");
         return CAPT_ENOMEM;
     }
-    st = build_forest(xyz, cloud_off, ncloud, r_min, r_max, flags, (hipStream_t)stream, f);
+    st = build_forest(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, (hipStream_t)stream, f);
     if (st) {
         destroy_forest(f);
         return st;
@@ -447,6 +475,7 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
     *out = f;
     return CAPT_OK;
 }
+}  // namespace
 
 capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, const float *crop, float r_min,
                                 float r_max, uint32_t flags, int32_t *kept_index, int64_t *n_kept, void *stream,
@@ -499,7 +528,7 @@ capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, con
         return CAPT_ENOMEM;
     }
     const int64_t off[2] = {0, m};
-    st = build_forest(kept.as<float>(), off, 1, r_min, r_max, flags, s, f);
+    st = build_forest(kept.as<float>(), off, 1, r_min, r_max, flags, nullptr, s, f);
     if (st) {
         destroy_forest(f);
         return st;
@@ -643,7 +672,8 @@ capt_status capt_export(capt_forest f, int32_t cloud, void *host_blob, size_t *b
         return CAPT_EINVAL;
     }
     const CloudHost &c = f->clouds[cloud];
-    const BlobLayout L(c.n, c.N, c.set_total);
+    const uint32_t version = c.dev.cyclic ? 1u : 2u;
+    const BlobLayout L(c.n, c.N, c.set_total, version);
     if (!host_blob) {
         *bytes = L.total;
         return CAPT_OK;
@@ -654,8 +684,9 @@ capt_status capt_export(capt_forest f, int32_t cloud, void *host_blob, size_t *b
     }
     char *B = static_cast<char *>(host_blob);
     memset(B, 0, L.total);
-    BlobHeader h{BLOB_MAGIC, BLOB_VERSION, c.n, c.N, c.D, c.dev.flags, f->r_min, f->r_max, c.set_total};
+    BlobHeader h{BLOB_MAGIC, version, c.n, c.N, c.D, c.dev.flags, f->r_min, f->r_max, c.set_total};
     memcpy(B, &h, sizeof h);
+    if (version >= 2) memcpy(B + sizeof h, &c.dev.axes, sizeof(uint64_t));
     std::vector<Leaf> leaves((size_t)c.N);
     std::vector<float> px((size_t)std::max<int64_t>(c.set_padded, 1)), py(px.size()), pz(px.size());
     std::vector<int32_t> pidx(px.size());
@@ -693,14 +724,27 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const char *B = static_cast<const char *>(host_blob);
     BlobHeader h;
     memcpy(&h, B, sizeof h);
-    if (h.magic != BLOB_MAGIC || h.version != BLOB_VERSION || h.n < 0 || h.D < 0 || h.D > 30 ||
+    if (h.magic != BLOB_MAGIC || h.version < 1 || h.version > BLOB_VERSION || h.n < 0 || h.D < 0 || h.D > 30 ||
         h.N != ((int64_t)1 << h.D) || h.n > h.N || (h.n > 0 && h.N >= 2 * h.n) || h.set_total < 0 ||
         !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max ||
         (h.flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS))) {
         set_error("blob header is invalid");
         return CAPT_EINVAL;
     }
-    const BlobLayout L(h.n, h.N, h.set_total);
+    uint64_t axes = axes_code(nullptr, h.D);
+    if (h.version >= 2) {
+        if (bytes < sizeof h + sizeof axes) {
+            set_error("blob too short");
+            return CAPT_EINVAL;
+        }
+        memcpy(&axes, B + sizeof h, sizeof axes);
+        for (int d = 0; d < 32; ++d)
+            if (d < h.D ? axis_at(axes, d) > 2 : axis_at(axes, d) != 0) {
+                set_error("blob axis code is invalid");
+                return CAPT_EINVAL;
+            }
+    }
+    const BlobLayout L(h.n, h.N, h.set_total, h.version);
     if (bytes < L.total) {
         set_error("blob holds %zu bytes, layout needs %zu", bytes, L.total);
         return CAPT_EINVAL;
@@ -826,6 +870,8 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     c.dev.n = h.n;
     c.dev.D = h.D;
     c.dev.flags = h.flags;
+    c.dev.axes = axes;
+    c.dev.cyclic = axes == axes_code(nullptr, h.D) ? 1 : 0;
     auto cp = [&](void *dst, const void *src, size_t nb) -> capt_status {
         if (nb) CAPT_HIP(hipMemcpy(dst, src, nb, hipMemcpyHostToDevice));
         return CAPT_OK;

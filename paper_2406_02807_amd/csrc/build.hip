@@ -175,9 +175,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lw, ui
 // left" first), tiles of GTILE finding their offset inside the segment by
 // decoupled look-back over the segment's earlier tiles (a segment's first
 // tile publishes a prefix at once, so every wait ends; waits are also
-// bounded).  The first of the two lists is on the axis of level d + 1, and
-// its new order fixes that level: while scattering it the kernel writes level
-// d + 1's split values and "goes left" flags (when `next` is set).
+// bounded).  When level d + 1 splits on another axis, the first of the two
+// lists is on that axis (`an`) and its new order fixes that level: while
+// scattering it the kernel writes level d + 1's split values and "goes left"
+// flags (when `next` is set).
 constexpr uint32_t LB_AGG = 1u << 30;
 constexpr uint32_t LB_PRE = 2u << 30;
 constexpr uint32_t LB_VAL = (1u << 30) - 1u;
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(TB) k_glevel(const uint32_t *__restrict__ Lb1,
                                                uint32_t *__restrict__ Ob1, uint32_t *__restrict__ Ob2,
                                                const uint8_t *__restrict__ left, uint8_t *__restrict__ left_next,
                                                const float *__restrict__ xyz, int64_t n, int64_t N, int d, int next,
-                                               float *__restrict__ T, uint32_t *__restrict__ status,
+                                               int an, float *__restrict__ T, uint32_t *__restrict__ status,
                                                uint32_t *__restrict__ ctr, int64_t ntile, uint32_t *__restrict__ err) {
     __shared__ uint32_t lw[TB / WAVE];
     __shared__ uint32_t s_tile, s_excl;
@@ -242,7 +243,6 @@ __global__ void __launch_bounds__(TB) k_glevel(const uint32_t *__restrict__ Lb1,
     const int64_t seg = base & ~(s - 1);
     const int64_t s2 = s >> 1, h2 = s2 >> 1;
     const int lg2 = 62 - __builtin_clzll((unsigned long long)s);   // log2(s / 2)
-    const int an = (d + 1) % 3;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int64_t q = base + i;
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(LTB) k_local_levels(const uint32_t *__restrict
                                                      const uint32_t *__restrict__ L2,
                                                      const uint32_t *__restrict__ inv,
                                                      const float *__restrict__ xyz, int64_t n,
-                                                     int64_t N, int D, int d0,
+                                                     int64_t N, int D, int d0, uint64_t axes,
                                                      float *__restrict__ T,
                                                      int32_t *__restrict__ rep) {
     __shared__ uint32_t ids[LMAX];
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(LTB) k_local_levels(const uint32_t *__restrict
     }
     __syncthreads();
     for (int d = d0; d < D; ++d) {
-        const int s = (int)(N >> d), h = s >> 1, a = d % 3;
+        const int s = (int)(N >> d), h = s >> 1, a = axis_at(axes, d);
         const int64_t node0 = ((int64_t)1 << d) - 1 + (int64_t)blockIdx.x * (S0 / s);
         for (int j = threadIdx.x; j < S0 / s; j += LTB) T[node0 + j] = cx[a][lst[a][j * s + h - 1]];
         for (int k = threadIdx.x; k < S0; k += LTB) flag[lst[a][k]] = (uint8_t)((k & (s - 1)) < h);
@@ -345,7 +345,7 @@ __device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a,
 // r_min pruning of the leaf (Sec. IV-B): a bounded cell whose farthest corner
 // is within r_min of the representative (float64, margin 2^-18).  Pruned
 // leaves are counted per block (prp[b]).
-__global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T, int64_t N, int D,
+__global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T, int64_t N, int D, uint64_t axes,
                                                     float *__restrict__ cells, const int32_t *__restrict__ rep,
                                                     const float *__restrict__ xyz, int64_t n, int prune, double thr,
                                                     uint8_t *__restrict__ pruned, uint32_t *__restrict__ prp) {
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T,
         float c[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
         int64_t i = 0;
         for (int d = 0; d < D; ++d) {
-            const int a = d % 3;
+            const int a = axis_at(axes, d);
             const int bit = (int)((l >> (D - 1 - d)) & 1);
             if (bit) c[a] = T[i];
             else c[3 + a] = T[i];
@@ -786,7 +786,7 @@ struct CloudWork {
 };
 
 capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, uint32_t flags,
-                         hipStream_t s, CloudHost &C, CloudWork &W) {
+                         const uint8_t *axes, hipStream_t s, CloudHost &C, CloudWork &W) {
     int64_t N = 1;
     int D = 0;
     while (N < n) {
@@ -824,6 +824,9 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     C.dev.n = n;
     C.dev.D = D;
     C.dev.flags = flags;
+    C.dev.axes = axes_code(axes, D);
+    C.dev.cyclic = C.dev.axes == axes_code(nullptr, D) ? 1 : 0;
+    const uint64_t ax = C.dev.axes;
 
     // scratch
     const size_t wN = (size_t)N;
@@ -947,34 +950,45 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         hipLaunchKernelGGL(k_fill_u32_b, dim3((unsigned)std::min<size_t>((words + TB - 1) / TB, 1024)), dim3(TB), 0,
                            s, sums, (int64_t)words, 0u);
         CAPT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], xyz, n, N, 0, 0, T, left);
+        const int a0 = axis_at(ax, 0);
+        hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[a0][cur[a0]], xyz, n, N, 0, a0, T, left);
         CAPT_LAUNCH_CHECK();
     }
     uint8_t *lf_cur = left, *lf_next = left + wN;
     for (; d < D && (N >> d) > LMAX; ++d) {
-        const int a = d % 3;
-        const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+        // the two lists off the split axis a are partitioned; the list on a
+        // is in order for both halves already
+        const int a = axis_at(ax, d);
+        const int an = d + 1 < D ? axis_at(ax, d + 1) : (a + 1) % 3;
+        const int b1 = an != a ? an : (a + 1) % 3;
+        const int b2 = 3 - a - b1;
         const int64_t nt = N / GTILE;
         uint32_t *lv = sums + lvl_words * (size_t)d;
         const int next = (N >> (d + 1)) > LMAX ? 1 : 0;
+        const int fused = next && an != a;   // level d + 1 written while scattering its list
         hipLaunchKernelGGL(k_glevel, dim3((unsigned)nt, 2), dim3(TB), 0, s, L[b1][cur[b1]], L[b2][cur[b2]],
-                           L[b1][cur[b1] ^ 1], L[b2][cur[b2] ^ 1], lf_cur, lf_next, xyz, n, N, d, next, T, lv,
-                           lv + 2 * nt, nt, rad);
+                           L[b1][cur[b1] ^ 1], L[b2][cur[b2] ^ 1], lf_cur, lf_next, xyz, n, N, d, fused, an, T,
+                           lv, lv + 2 * nt, nt, rad);
         CAPT_LAUNCH_CHECK();
         cur[b1] ^= 1;
         cur[b2] ^= 1;
+        if (next && !fused) {   // level d + 1 splits on axis a again: from its list as it stands
+            hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[a][cur[a]], xyz, n, N, d + 1, a, T,
+                               lf_next);
+            CAPT_LAUNCH_CHECK();
+        }
         std::swap(lf_cur, lf_next);
     }
     hipLaunchKernelGGL(k_inverse, dim3(nblk(N)), dim3(TB), 0, s, L[0][cur[0]], N, inv);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(LTB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]],
-                       inv, xyz, n, N, D, d, T, C.rep);
+                       inv, xyz, n, N, D, d, ax, T, C.rep);
     CAPT_LAUNCH_CHECK();
 
     // 3. leaf cells and pruning
     const int prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
     const double thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
-    hipLaunchKernelGGL(k_cells_prune, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, cells, C.rep, xyz, n, prune, thr,
+    hipLaunchKernelGGL(k_cells_prune, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, ax, cells, C.rep, xyz, n, prune, thr,
                        C.pruned_flag, prp);
     CAPT_LAUNCH_CHECK();
 
@@ -1063,7 +1077,7 @@ capt_status upload_views(capt_forest_s *f, hipStream_t s) {
 }
 
 capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min,
-                         float r_max, uint32_t flags, hipStream_t s, capt_forest_s *f) {
+                         float r_max, uint32_t flags, const uint8_t *axes, hipStream_t s, capt_forest_s *f) {
     f->clouds.resize(ncloud);
     f->r_min = r_min;
     f->r_max = r_max;
@@ -1071,7 +1085,8 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     std::vector<CloudWork> work(ncloud);
     for (int c = 0; c < ncloud; ++c) {
         const int64_t n = cloud_off[c + 1] - cloud_off[c];
-        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, s, f->clouds[c], work[c]);
+        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, s, f->clouds[c],
+                                      work[c]);
         if (st) return st;
     }
     // every cloud's totals and error word straight into pinned host memory,

@@ -39,7 +39,18 @@ struct CloudDev {
     int64_t n;
     int32_t D;
     uint32_t flags;
+    uint64_t axes;         // split axis of depth d in bits 2d, 2d+1
+    int32_t cyclic;        // axes follow d mod 3 (the kernels' fast descent)
 };
+
+// Split-axis code of a forest: bits 2d, 2d+1 hold the axis of depth d.
+// axes == NULL gives the cyclic rule d mod 3.
+inline uint64_t axes_code(const uint8_t *axes, int D) {
+    uint64_t c = 0;
+    for (int d = 0; d < D && d < 32; ++d) c |= (uint64_t)(axes ? axes[d] : (uint8_t)(d % 3)) << (2 * d);
+    return c;
+}
+__host__ __device__ __forceinline__ int axis_at(uint64_t code, int d) { return (int)((code >> (2 * d)) & 3u); }
 
 // Stored-set alignment: every set starts at a multiple of this many entries
 // and is padded with +inf entries up to one.  A chunk of SET_ALIGN entries is
@@ -211,8 +222,9 @@ struct capt_forest_s {
 namespace capt {
 
 // build.hip
+// axes: host [D] split axis per depth (0, 1, 2) or NULL for d mod 3
 capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
-                         float r_min, float r_max, uint32_t flags, hipStream_t s,
+                         float r_min, float r_max, uint32_t flags, const uint8_t *axes, hipStream_t s,
                          capt_forest_s *f);
 void free_cloud(CloudHost &c, hipStream_t s);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);

@@ -22,14 +22,13 @@ namespace capt {
 namespace {
 
 __device__ __forceinline__ uint32_t descend_c(const float4 &q, const float *Tl, int L,
-                                              const float *__restrict__ Tg, int D) {
+                                              const float *__restrict__ Tg, int D, uint64_t axes) {
     uint32_t i = 0;
-    int a = 0;
     for (int lv = 0; lv < D; ++lv) {
         const float t = lv < L ? Tl[i] : Tg[i];
+        const int a = axis_at(axes, lv);
         const float x = a == 0 ? q.x : (a == 1 ? q.y : q.z);
         i = 2 * i + 1 + (x > t ? 1u : 0u);
-        a = (a == 2) ? 0 : a + 1;
     }
     return i;
 }
@@ -49,7 +48,7 @@ __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t 
         const int64_t s = t * WAVE + lane;
         const bool valid = s < nsph;
         const float4 q = valid ? sph[s] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const uint32_t lf = descend_c(q, Tl, L, C.T, C.D) - (uint32_t)(N - 1);
+        const uint32_t lf = descend_c(q, Tl, L, C.T, C.D, C.axes) - (uint32_t)(N - 1);
         uint32_t start = 0, count = 0;
         bool need = false;
         if (valid) {

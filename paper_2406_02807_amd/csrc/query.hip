@@ -60,22 +60,33 @@ __device__ __forceinline__ float axis_of(const float4 &q, int a) {
 
 // Branch-free descent: i <- 2i + 1 + (x_d > T_i), ties go left.  The first
 // `L` levels read T from LDS.
+// The split axis of depth lv comes from the forest's axis code.
 __device__ __forceinline__ uint32_t descend(const float4 &q, const float *Tl, int L,
-                                            const float *__restrict__ Tg, int D) {
+                                            const float *__restrict__ Tg, int D, uint64_t axes) {
     uint32_t i = 0;
-    int a = 0;
     int lv = 0;
     for (; lv < L; ++lv) {
         const float t = Tl[i];
-        i = 2 * i + 1 + (axis_of(q, a) > t ? 1u : 0u);
-        a = (a == 2) ? 0 : a + 1;
+        i = 2 * i + 1 + (axis_of(q, axis_at(axes, lv)) > t ? 1u : 0u);
     }
     for (; lv < D; ++lv) {
         const float t = Tg[i];
-        i = 2 * i + 1 + (axis_of(q, a) > t ? 1u : 0u);
-        a = (a == 2) ? 0 : a + 1;
+        i = 2 * i + 1 + (axis_of(q, axis_at(axes, lv)) > t ? 1u : 0u);
     }
     return i;
+}
+
+// descend_leaf for a forest whose split axes do not follow d mod 3: one level
+// per step.
+__device__ __forceinline__ Leaf descend_leaf_any(const float4 &q, const float *Tl, int L,
+                                                 const float *__restrict__ Tg, const Leaf *__restrict__ leaves,
+                                                 int D, uint64_t axes, uint32_t *lf) {
+    uint32_t i = 0;
+    int lv = 0;
+    for (; lv < L; ++lv) i = 2 * i + 1 + (axis_of(q, axis_at(axes, lv)) > Tl[i] ? 1u : 0u);
+    for (; lv < D; ++lv) i = 2 * i + 1 + (axis_of(q, axis_at(axes, lv)) > ld32(Tg, 4u * i) ? 1u : 0u);
+    *lf = i - ((1u << D) - 1u);
+    return leaves[*lf];
 }
 
 // The same descent, shaped for latency: the LDS levels are taken three per
@@ -177,14 +188,17 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // order, so a skipped chunk holds no hit and the answer equals a scan of every
 // entry.  A hit retires its configuration: its spheres' ring chunks are
 // skipped and the level-1 prefix is rebuilt over the spheres still open.
-template <int U, bool IDX, bool SLOTS>
+template <int U, bool IDX, bool SLOTS, bool AXES = true>
 __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, int L, float4 q, bool valid, int gg,
                                           bool single, WaveLds &W) {
     const int lane = lane_id();
     const float r2 = __fmul_rn(q.w, q.w);
     Leaf leaf;
     uint32_t lf;
-    leaf = descend_leaf(q, Tl, L, C.T, C.leaf, C.D, &lf);
+    if (AXES && !C.cyclic)   // uniform; the batched kernel takes cyclic forests only
+        leaf = descend_leaf_any(q, Tl, L, C.T, C.leaf, C.D, C.axes, &lf);
+    else
+        leaf = descend_leaf(q, Tl, L, C.T, C.leaf, C.D, &lf);
     if (!valid) leaf.count = 0;
     bool alive = leaf.count > 0;
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
@@ -572,7 +586,7 @@ __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ s
         const int si = s0 + j;
         const bool valid = active && si < g;
         const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool hit = wave_tile<U, IDX, true>(C, nullptr, 0, q, valid, SLOT, false, W);
+        bool hit = wave_tile<U, IDX, true, false>(C, nullptr, 0, q, valid, SLOT, false, W);
         hit = __shfl(hit, lead, WAVE);
         if (active) {
             if (hit || s0 + SLOT >= g) {
@@ -607,7 +621,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const bool hit = wave_tile<U, IDX, false>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
+                const bool hit = wave_tile<U, IDX, false, false>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         }
@@ -682,7 +696,7 @@ __global__ void k_query_stats(CloudDev C, const float4 *__restrict__ sph, int64_
     const float4 q = sph[s];
     const float r2 = __fmul_rn(q.w, q.w);
     const int64_t N = (int64_t)1 << C.D;
-    const uint32_t node = descend(q, nullptr, 0, C.T, C.D);
+    const uint32_t node = descend(q, nullptr, 0, C.T, C.D, C.axes);
     const uint32_t lf = node - (uint32_t)(N - 1);
     const Leaf L = C.leaf[lf];
     const bool rej = L.count == 0 || box_sqdist(q.x, q.y, q.z, L.lo, L.hi) > r2;
@@ -713,7 +727,7 @@ __global__ void k_chunk_stats(CloudDev C, const float4 *__restrict__ sph, int64_
     const float4 q = sph[s];
     const float r2 = __fmul_rn(q.w, q.w);
     const int64_t N = (int64_t)1 << C.D;
-    const uint32_t lf = descend(q, nullptr, 0, C.T, C.D) - (uint32_t)(N - 1);
+    const uint32_t lf = descend(q, nullptr, 0, C.T, C.D, C.axes) - (uint32_t)(N - 1);
     const Leaf L = C.leaf[lf];
     int32_t nb = 0, nc = 0;
     if (L.count > 0 && box_sqdist(q.x, q.y, q.z, L.lo, L.hi) <= r2) {
@@ -1025,7 +1039,9 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
         capt_status st = check_radii(spheres, qoff[nc], f->r_min, f->r_max, s);
         if (st) return st;
     }
-    if (nc == 1 || (flags & CAPT_PER_CLOUD)) {
+    bool cyclic = true;   // the batched kernel takes forests with the cyclic split axes only
+    for (int c = 0; c < nc; ++c) cyclic = cyclic && f->clouds[c].dev.cyclic;
+    if (nc == 1 || (flags & CAPT_PER_CLOUD) || !cyclic) {
         // queue counters, one set per cloud so launches on the stream never share them
         Scratch ctr;
         if (!ctr.alloc(sizeof(unsigned int) * NXCD * CTR_STRIDE * (size_t)nc, s)) {

@@ -88,6 +88,11 @@ def test_no_gpu_needed_for_validation(lib):
     assert bf(P(1), 10, 0.01, None, 0.01, 0.05, 0x80, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     assert bf(None, 10, 0.01, None, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
     assert bf(P(1), 10, 0.01, bad_crop, 0.01, 0.05, 0, None, C.byref(m), None, C.byref(h)) == capt.CAPT_EINVAL
+    # split axes: NULL, not an axis
+    ax = (C.c_uint8 * 32)(*([0] * 32))
+    assert lib.capt_build_axes(P(1), offp, 1, 0.0, 0.05, 0, None, None, C.byref(h)) == capt.CAPT_EINVAL
+    ax[3] = 3
+    assert lib.capt_build_axes(P(1), offp, 1, 0.0, 0.05, 0, ax, None, C.byref(h)) == capt.CAPT_EINVAL
     # cropped filter: NULL / non-finite base / negative reach / NULL count
     fc = lib.capt_filter_crop
     assert fc(P(1), 10, 0.01, None, P(1), None, C.byref(m), None) == capt.CAPT_EINVAL
@@ -130,6 +135,13 @@ def test_blob_roundtrip_pack_parse():
     assert (p.n, p.N, p.D) == (5, 8, 3)
     assert np.array_equal(p.points, pts) and np.array_equal(p.T, T) and np.array_equal(p.idx, idx)
     assert np.array_equal(p.aabb, aabb) and np.array_equal(p.off, off)
+    assert p.axes is None
+    # version 2 carries the split axis of every depth
+    b2 = capt.make_blob(pts, T, rep, aabb, pr, off, idx, 0.01, 0.05, axes=[2, 0, 1])
+    p2 = capt.parse_blob(b2)
+    assert p2.axes.tolist() == [2, 0, 1]
+    assert np.array_equal(p2.points, pts) and np.array_equal(p2.T, T) and np.array_equal(p2.idx, idx)
+    assert len(b2) == len(b) + 8
 
 
 def test_product_does_not_import_the_oracle():

@@ -49,10 +49,10 @@ def canonical_sets(off, idx):
     return sizes, idx[order]
 
 
-def compare_build(capt, orc, pts, r_min, r_max, prune=True):
-    f = capt.capt_build(dev(pts), r_min, r_max, prune=prune)
+def compare_build(capt, orc, pts, r_min, r_max, prune=True, axes=None):
+    f = capt.capt_build(dev(pts), r_min, r_max, prune=prune, axes=axes)
     b = capt.parse_blob(capt.capt_export(f))
-    t = orc.build_tree(pts, r_min, r_max, prune=prune)
+    t = orc.build_tree(pts, r_min, r_max, prune=prune, axes=axes)
     assert (b.n, b.N, b.D) == (t.n, t.N, t.D)
     assert np.array_equal(bits(b.T), bits(t.T)), "split values differ"
     assert np.array_equal(b.rep, t.rep), "representatives differ"
@@ -332,6 +332,59 @@ def test_edge_cases_of_the_frame_calls(capt, orc):
     fa.release()
     fb.release()
     torch.cuda.synchronize()
+
+
+AXES = {"random": np.random.default_rng(71).integers(0, 3, 32).astype(np.uint8),
+        "x-only": np.zeros(32, np.uint8), "z-y": np.tile(np.array([2, 1], np.uint8), 16)}
+
+
+@pytest.mark.parametrize("seq", sorted(AXES))
+@pytest.mark.parametrize("name", ["uniform-3000", "tabletop-filtered", "dups-300"])
+def test_build_and_query_any_axes(capt, orc, seq, name):
+    _say(f"case: split axes {seq} on {name}")
+    if name == "uniform-3000":
+        pts = synth.uniform_cube_cloud(3000, 51)
+    elif name == "dups-300":
+        pts = np.repeat(synth.uniform_cube_cloud(60, 52), 5, axis=0)
+    else:
+        c = synth.tabletop_cloud(50_000, 2001)
+        pts = c[orc.filter(c, 0.01)[0]]
+    axes = AXES[seq]
+    r_min, r_max = (0.015, 0.08) if name == "tabletop-filtered" else (0.01, 0.05)
+    f, b, t = compare_build(capt, orc, pts, r_min, r_max, axes=axes)
+    assert np.array_equal(b.axes, axes[:b.D]) or b.D == 0 or np.array_equal(axes[:b.D], np.arange(b.D) % 3)
+    lo, hi = pts.min(0) - 0.1, pts.max(0) + 0.1
+    rng = np.random.default_rng(53)
+    cen = lo + rng.random((60 * 500, 3)) * (hi - lo)
+    sph = np.concatenate([cen, rng.uniform(r_min, r_max, (len(cen), 1))], 1).astype(np.float32)
+    for g in (1, 60):
+        assert np.array_equal(capt.capt_collides(f, dev(sph), g).cpu().numpy(), orc.brute_f32(pts, sph, g)), g
+    leaf, rej, scanned, hit = (x.cpu().numpy() for x in capt.capt_query_stats(f, dev(sph)))
+    hit_o, leaf_o, rej_o, sc_o = orc.query_tree(t, pts, sph)
+    assert np.array_equal(leaf, leaf_o) and np.array_equal(rej, rej_o) and np.array_equal(hit, hit_o)
+    # export / import keeps the axes
+    g2 = capt.capt_import(capt.capt_export(f))
+    assert torch.equal(capt.capt_collides(g2, dev(sph), 60), capt.capt_collides(f, dev(sph), 60))
+
+
+def test_clearance_and_batches_any_axes(capt, orc):
+    _say("case: split axes: clearance and forests of several clouds")
+    axes = AXES["random"]
+    c = synth.tabletop_cloud(50_000, 2001)
+    pts = c[orc.filter(c, 0.01)[0]]
+    f = capt.capt_build(dev(pts), 0.0, 0.08, axes=axes)
+    sph = synth.uniform_spheres(4000, synth.WORKSPACE, 0.015, 0.08, 54)
+    clr, wit = capt.capt_clearance(f, dev(sph))
+    clr_o, wit_o, _ = orc.clearance_f64(pts, sph, 0.08)
+    c64 = clr.cpu().numpy().astype(np.float64)
+    assert (np.abs(c64 - clr_o) <= 1e-4 * np.maximum(np.abs(clr_o), 0.08)).all()
+    clouds = [synth.tabletop_cloud(2000 + 1000 * k, 400 + k) for k in range(3)]
+    off = np.cumsum([0] + [len(x) for x in clouds]).tolist()
+    qs = [synth.uniform_spheres(60 * 300, synth.WORKSPACE, 0.015, 0.08, 410 + k) for k in range(3)]
+    qoff = np.cumsum([0] + [len(q) for q in qs]).tolist()
+    fb = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off, axes=axes)
+    got = capt.capt_collides(fb, dev(np.concatenate(qs)), 60, query_off=qoff).cpu().numpy()
+    assert np.array_equal(got, np.concatenate([orc.brute_f32(x, q, 60) for x, q in zip(clouds, qs)]))
 
 
 def test_stream_ordered_release(capt, orc):
