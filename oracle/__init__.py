@@ -25,6 +25,9 @@ Functions and what they follow:
   crop             reach crop for fixed-base arms (Sec. IV-C)
   pad_radii        query padding r + r_filter (Sec. V-B, after the filter
                    lemma)
+  shard_tree       one shard of a tree (Sec. VII: CAPTs each responsible for
+                   a neighbourhood of a large cloud): the whole tree with the
+                   sets of every leaf outside the shard's subtree emptied
 """
 from __future__ import annotations
 
@@ -218,6 +221,32 @@ def query(N: int, D: int, T, aabb, off, setxyz, spheres, axes=None):
                       _p(setxyz) if len(setxyz) else None, _p(sph), m,
                       _p(hit), _p(leaf), _p(rej), _p(scanned), _p(_axes(axes)))
     return hit, leaf, rej, scanned
+
+
+def shard_leaves(N: int, bits: int, shard: int) -> range:
+    """Leaves l of a tree with N leaves that shard `shard` of 2**bits answers
+    for: floor(l * 2**bits / N) == shard.  For bits <= log2 N they are the
+    leaves under the depth-`bits` node `shard`; for more bits, every leaf
+    is its own shard and the other shards hold none."""
+    return range(-(-shard * N // 2 ** bits), -(-(shard + 1) * N // 2 ** bits))
+
+
+def shard_tree(tree: Tree, bits: int, shard: int) -> Tree:
+    """Shard `shard` of 2**bits of `tree`: splits, cells and representatives
+    unchanged; every leaf outside shard_leaves keeps no set (count 0, the
+    empty box lo = +inf, hi = -inf) and no pruning mark."""
+    mine = np.zeros(tree.N, dtype=bool)
+    mine[shard_leaves(tree.N, bits, shard)] = True
+    cnt = np.where(mine, np.diff(tree.off), 0)
+    off = np.zeros(tree.N + 1, dtype=np.int64)
+    off[1:] = np.cumsum(cnt)
+    idx = np.concatenate([tree.set_of(l) for l in range(tree.N) if mine[l]] + [np.zeros(0, np.int32)])
+    aabb = tree.aabb.copy()
+    aabb[~mine, :3] = np.inf
+    aabb[~mine, 3:] = -np.inf
+    pruned = np.where(mine, tree.pruned, 0).astype(np.uint8)
+    return Tree(tree.n, tree.N, tree.D, tree.r_min, tree.r_max, tree.T.copy(), tree.rep.copy(),
+                tree.cell.copy(), aabb, pruned, off, idx.astype(np.int32), tree.axes)
 
 
 def query_tree(tree: Tree, points, spheres):
