@@ -221,7 +221,10 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
 def bench_indexed(capt, torch, reps=5):
     """Indexed affordance sets (point indices only) against plain sets on the
     room scene (1.2M points filtered at 5 mm, r_max = 0.1 m): forest bytes and
-    the time of 10,000,000 single-sphere queries, with equal answers."""
+    the time of 10,000,000 single-sphere queries, with equal answers.  Then
+    the same forest as 4 shards (the subtrees of the depth-2 nodes) built and
+    queried one after the other: bytes, build and query time per shard, and
+    the OR of the shards' answers against the whole forest's."""
     import synth
     w = synth.workload(5)
     xyz = torch.from_numpy(w.cloud).cuda()
@@ -243,8 +246,15 @@ def bench_indexed(capt, torch, reps=5):
 
     rows = {}
     outs = {}
+    def build(**kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max, **kw)
+        torch.cuda.synchronize()
+        return f, (time.perf_counter() - t0) * 1e3
+
     for name, ix in (("plain", False), ("indexed", True)):
-        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max, indexed=ix)
+        f, rows[name + "_build_ms"] = build(indexed=ix)
         out = capt.capt_collides(f, sph, 1)
         torch.cuda.synchronize()
         rows[name + "_ms"] = timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps)
@@ -252,6 +262,19 @@ def bench_indexed(capt, torch, reps=5):
         outs[name] = out.clone()
         f.close()
     rows["same_answers"] = bool(torch.equal(outs["plain"], outs["indexed"]))
+    bits = 2
+    acc = torch.zeros_like(outs["plain"])
+    sh = {"bytes": [], "build_ms": [], "query_ms": []}
+    for k in range(2 ** bits):
+        f, ms = build(shard=(bits, k))
+        out = capt.capt_collides(f, sph, 1)
+        sh["query_ms"].append(timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps))
+        sh["build_ms"].append(ms)
+        sh["bytes"].append(int(f.info()["bytes"]))
+        acc |= out
+        f.close()
+    sh["same_answers_or"] = bool(torch.equal(acc, outs["plain"]))
+    rows["shards_4"] = sh
     rows["workload"] = "room scene, 1.2M points -> 5 mm filter, r_max = 0.1, 10,000,000 single-sphere queries"
     return rows
 

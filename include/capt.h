@@ -50,6 +50,8 @@ typedef int32_t capt_status;
 #define CAPT_EUNSUPPORTED 6   /* size beyond the library's limits */
 
 /* Build flags */
+#define CAPT_MAX_SHARD_BITS 20 /* capt_build_shard: at most 2^20 shards */
+
 #define CAPT_NO_PRUNE     0x1u  /* never apply r_min pruning (Sec. IV-B) */
 #define CAPT_INDEXED_SETS 0x10u /* sets hold point indices only; queries gather the
                                    coordinates from the forest's point table */
@@ -142,6 +144,31 @@ capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t nclou
 capt_status capt_build_axes(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
                             float r_min, float r_max, uint32_t flags, const uint8_t *axes,
                             void *stream, capt_forest *out);
+
+/*
+ * One shard of a forest too large to hold at once (Sec. VII: a set of CAPTs,
+ * each responsible for one neighbourhood of a large cloud).  Shard s of
+ * 2^shard_bits is capt_build's forest of the same cloud in which only the
+ * leaves l with floor(l 2^shard_bits / N) = s keep their affordance sets;
+ * for shard_bits <= D these are the leaves under depth-shard_bits node s,
+ * the subtree of the cell that shard s answers for.  The splits, cells and
+ * representatives are the whole cloud's; every other leaf holds no points,
+ * no box and is never pruned, so a sphere that descends into another shard's
+ * subtree is rejected on the leaf box.  Set memory is the shard's share.
+ * Every query call takes a shard forest, and the answers combine exactly:
+ *   capt_collides   the whole forest's answer = OR over the 2^shard_bits shards
+ *   capt_clearance  the whole forest's clearance = min over the shards (a
+ *                   sphere outside a shard gets r_max - r and witness -1)
+ * Each cloud of a batch is sharded with the same (shard_bits, shard).
+ *   shard_bits  0 .. CAPT_MAX_SHARD_BITS; 0 gives capt_build's forest
+ *   shard       0 .. 2^shard_bits - 1
+ * Other arguments, synchronisation and errors as capt_build; a shard_bits or
+ * shard out of range gives CAPT_EINVAL.  A shard exports and imports as any
+ * forest.
+ */
+capt_status capt_build_shard(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
+                             float r_min, float r_max, uint32_t flags, int32_t shard_bits,
+                             int32_t shard, void *stream, capt_forest *out);
 
 /*
  * Per-frame rebuild (Sec. IV-C followed by Sec. IV-A/B): capt_filter (or,

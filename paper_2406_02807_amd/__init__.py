@@ -25,9 +25,10 @@ CAPT_CHECK_RADII = 0x2
 CAPT_PER_CLOUD = 0x4
 CAPT_NO_GRAPH = 0x8
 CAPT_INDEXED_SETS = 0x10
+CAPT_MAX_SHARD_BITS = 20
 
 EXPORTS = [
-    "capt_filter", "capt_filter_crop", "capt_build", "capt_build_axes", "capt_build_filtered", "capt_collides",
+    "capt_filter", "capt_filter_crop", "capt_build", "capt_build_axes", "capt_build_shard", "capt_build_filtered", "capt_collides",
     "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
@@ -63,6 +64,7 @@ def load_library(path: str = LIB_PATH):
         "capt_filter": [P, i64, f32, P, P, P, P],
         "capt_build": [P, P, i32, f32, f32, u32, P, P],
         "capt_build_axes": [P, P, i32, f32, f32, u32, P, P, P],
+        "capt_build_shard": [P, P, i32, f32, f32, u32, i32, i32, P, P],
         "capt_build_filtered": [P, i64, f32, P, f32, f32, u32, P, P, P, P],
         "capt_filter_crop": [P, i64, f32, P, P, P, P, P],
         "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
@@ -204,10 +206,11 @@ def capt_filter(xyz, r_filter: float, base=None, reach=None, stream=None):
 
 
 def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=None,
-               stream=None, indexed: bool = False, axes=None) -> Forest:
+               stream=None, indexed: bool = False, axes=None, shard=None) -> Forest:
     """Alg. 1 for one cloud (xyz [n, 3]) or several (cloud_off host [ncloud+1]).
     indexed: the sets store point indices only (CAPT_INDEXED_SETS).
-    axes: split axis of every depth (capt_build_axes), default d mod 3."""
+    axes: split axis of every depth (capt_build_axes), default d mod 3.
+    shard: (shard_bits, s) builds shard s of 2^shard_bits (capt_build_shard)."""
     import torch
     lib = load_library()
     xyz = _dev(xyz, torch.float32, 3, "xyz")
@@ -218,7 +221,13 @@ def capt_build(xyz, r_min: float, r_max: float, prune: bool = True, cloud_off=No
         raise ValueError("cloud_off[-1] must equal the number of points")
     h = C.c_void_p()
     flags = (0 if prune else CAPT_NO_PRUNE) | (CAPT_INDEXED_SETS if indexed else 0)
-    if axes is None:
+    if shard is not None:
+        if axes is not None:
+            raise ValueError("shard and axes cannot be combined")
+        bits, sid = shard
+        _check(lib.capt_build_shard(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
+                                    float(r_max), flags, int(bits), int(sid), _stream(stream), C.byref(h)))
+    elif axes is None:
         _check(lib.capt_build(_ptr(xyz), off.ctypes.data_as(C.c_void_p), len(off) - 1, float(r_min),
                               float(r_max), flags, _stream(stream), C.byref(h)))
     else:

@@ -411,13 +411,14 @@ capt_status capt_filter_crop(const float *xyz, int64_t n, float r_filter, const 
 
 namespace {
 capt_status build_entry(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
-                        uint32_t flags, const uint8_t *axes, void *stream, capt_forest *out);
+                        uint32_t flags, const uint8_t *axes, int shard_bits, int shard, void *stream,
+                        capt_forest *out);
 }  // namespace
 
 capt_status capt_build(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
                        uint32_t flags, void *stream, capt_forest *out) {
     ApiGuard g;
-    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, nullptr, stream, out);
+    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, nullptr, 0, 0, stream, out);
 }
 
 capt_status capt_build_axes(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
@@ -432,12 +433,28 @@ capt_status capt_build_axes(const float *xyz, const int64_t *cloud_off, int32_t 
             set_error("axes[%d] = %u is not an axis (0, 1, 2)", d, (unsigned)axes[d]);
             return CAPT_EINVAL;
         }
-    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, stream, out);
+    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, 0, 0, stream, out);
+}
+
+capt_status capt_build_shard(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
+                             uint32_t flags, int32_t shard_bits, int32_t shard, void *stream, capt_forest *out) {
+    ApiGuard g;
+    if (out) *out = nullptr;
+    if (shard_bits < 0 || shard_bits > CAPT_MAX_SHARD_BITS) {
+        set_error("shard_bits = %d must lie in [0, %d]", shard_bits, CAPT_MAX_SHARD_BITS);
+        return CAPT_EINVAL;
+    }
+    if (shard < 0 || shard >= (1 << shard_bits)) {
+        set_error("shard = %d must lie in [0, 2^%d)", shard, shard_bits);
+        return CAPT_EINVAL;
+    }
+    return build_entry(xyz, cloud_off, ncloud, r_min, r_max, flags, nullptr, shard_bits, shard, stream, out);
 }
 
 namespace {
 capt_status build_entry(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min, float r_max,
-                        uint32_t flags, const uint8_t *axes, void *stream, capt_forest *out) {
+                        uint32_t flags, const uint8_t *axes, int shard_bits, int shard, void *stream,
+                        capt_forest *out) {
     if (!out) {
         set_error("out is NULL");
         return CAPT_EINVAL;
@@ -467,7 +484,7 @@ capt_status build_entry(const float *xyz, const int64_t *cloud_off, int32_t nclo
         set_error("host allocation failed");
         return CAPT_ENOMEM;
     }
-    st = build_forest(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, (hipStream_t)stream, f);
+    st = build_forest(xyz, cloud_off, ncloud, r_min, r_max, flags, axes, shard_bits, shard, (hipStream_t)stream, f);
     if (st) {
         destroy_forest(f);
         return st;
@@ -528,7 +545,7 @@ capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, con
         return CAPT_ENOMEM;
     }
     const int64_t off[2] = {0, m};
-    st = build_forest(kept.as<float>(), off, 1, r_min, r_max, flags, nullptr, s, f);
+    st = build_forest(kept.as<float>(), off, 1, r_min, r_max, flags, nullptr, 0, 0, s, f);
     if (st) {
         destroy_forest(f);
         return st;

@@ -344,11 +344,13 @@ __device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a,
 // left descent, lower bound from a right one, +-inf where unbounded), then the
 // r_min pruning of the leaf (Sec. IV-B): a bounded cell whose farthest corner
 // is within r_min of the representative (float64, margin 2^-18).  Pruned
-// leaves are counted per block (prp[b]).
+// leaves are counted per block (prp[b]).  Only leaves in [l0, l1) (a shard's
+// subtree) may be pruned; the others keep empty sets.
 __global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T, int64_t N, int D, uint64_t axes,
                                                     float *__restrict__ cells, const int32_t *__restrict__ rep,
                                                     const float *__restrict__ xyz, int64_t n, int prune, double thr,
-                                                    uint8_t *__restrict__ pruned, uint32_t *__restrict__ prp) {
+                                                    int64_t l0, int64_t l1, uint8_t *__restrict__ pruned,
+                                                    uint32_t *__restrict__ prp) {
     __shared__ uint32_t sc[TB / WAVE];
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool pr = false;
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T,
         }
         for (int k = 0; k < 6; ++k) cells[6 * l + k] = c[k];
         const int64_t id = rep[l];
-        pr = prune && id < n;
+        pr = prune && id < n && l >= l0 && l < l1;
         for (int k = 0; k < 6 && pr; ++k) pr = isfinite(c[k]);
         if (pr) {
             double far2 = 0.0;
@@ -535,6 +537,7 @@ struct AffArgs {
     const float *sx, *sy, *sz; // points sorted by bin
     const uint32_t *sid;       // original index of each sorted point
     int64_t n, N;
+    int64_t l0, l1;            // leaves that get sets (a shard's subtree); the others stay empty
     double R2;                 // (r_max (1 + 2^-20))^2
     double R;
 };
@@ -572,7 +575,7 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
     if (A.pruned[l]) {
         const float x = A.xyz[3 * rid], y = A.xyz[3 * rid + 1], z = A.xyz[3 * rid + 2];
         emit(lane == 0, x, y, z, (int32_t)rid);
-    } else if (A.n > 0) {
+    } else if (A.n > 0 && l >= A.l0 && l < A.l1) {
         const Grid g = *A.grid;
         const float *c = A.cells + 6 * l;
         double cl[3], ch[3];
@@ -786,7 +789,8 @@ struct CloudWork {
 };
 
 capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, uint32_t flags,
-                         const uint8_t *axes, hipStream_t s, CloudHost &C, CloudWork &W) {
+                         const uint8_t *axes, int shard_bits, int shard, hipStream_t s, CloudHost &C,
+                         CloudWork &W) {
     int64_t N = 1;
     int D = 0;
     while (N < n) {
@@ -988,8 +992,11 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     // 3. leaf cells and pruning
     const int prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
     const double thr = ((double)r_min * (double)r_min) * (1.0 - 0x1p-18);
+    // leaves of the shard: floor(l 2^bits / N) = shard
+    const int64_t l0 = ((int64_t)shard * N + ((int64_t)1 << shard_bits) - 1) >> shard_bits;
+    const int64_t l1 = ((int64_t)(shard + 1) * N + ((int64_t)1 << shard_bits) - 1) >> shard_bits;
     hipLaunchKernelGGL(k_cells_prune, dim3(nblk(N)), dim3(TB), 0, s, T, N, D, ax, cells, C.rep, xyz, n, prune, thr,
-                       C.pruned_flag, prp);
+                       l0, l1, C.pruned_flag, prp);
     CAPT_LAUNCH_CHECK();
 
     // 4. join the grid branch (bins of side >= R / 2, points sorted by bin)
@@ -1010,6 +1017,8 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     A.sid = sid;
     A.n = n;
     A.N = N;
+    A.l0 = l0;
+    A.l1 = l1;
     A.R = R;
     A.R2 = R * R;
     hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
@@ -1077,7 +1086,8 @@ capt_status upload_views(capt_forest_s *f, hipStream_t s) {
 }
 
 capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud, float r_min,
-                         float r_max, uint32_t flags, const uint8_t *axes, hipStream_t s, capt_forest_s *f) {
+                         float r_max, uint32_t flags, const uint8_t *axes, int shard_bits, int shard,
+                         hipStream_t s, capt_forest_s *f) {
     f->clouds.resize(ncloud);
     f->r_min = r_min;
     f->r_max = r_max;
@@ -1085,8 +1095,8 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     std::vector<CloudWork> work(ncloud);
     for (int c = 0; c < ncloud; ++c) {
         const int64_t n = cloud_off[c + 1] - cloud_off[c];
-        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, s, f->clouds[c],
-                                      work[c]);
+        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, shard_bits, shard, s,
+                                      f->clouds[c], work[c]);
         if (st) return st;
     }
     // every cloud's totals and error word straight into pinned host memory,

@@ -222,10 +222,12 @@ struct capt_forest_s {
 namespace capt {
 
 // build.hip
-// axes: host [D] split axis per depth (0, 1, 2) or NULL for d mod 3
+// axes: host [D] split axis per depth (0, 1, 2) or NULL for d mod 3.
+// shard_bits, shard: only the leaves l with floor(l 2^shard_bits / N) = shard
+// get affordance sets (0, 0: every leaf).
 capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncloud,
-                         float r_min, float r_max, uint32_t flags, const uint8_t *axes, hipStream_t s,
-                         capt_forest_s *f);
+                         float r_min, float r_max, uint32_t flags, const uint8_t *axes, int shard_bits,
+                         int shard, hipStream_t s, capt_forest_s *f);
 void free_cloud(CloudHost &c, hipStream_t s);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)

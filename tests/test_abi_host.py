@@ -93,6 +93,15 @@ def test_no_gpu_needed_for_validation(lib):
     assert lib.capt_build_axes(P(1), offp, 1, 0.0, 0.05, 0, None, None, C.byref(h)) == capt.CAPT_EINVAL
     ax[3] = 3
     assert lib.capt_build_axes(P(1), offp, 1, 0.0, 0.05, 0, ax, None, C.byref(h)) == capt.CAPT_EINVAL
+    # shards: bits or shard out of range, then the radii checks of capt_build
+    bs = lib.capt_build_shard
+    assert bs(P(1), offp, 1, 0.0, 0.05, 0, -1, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bs(P(1), offp, 1, 0.0, 0.05, 0, capt.CAPT_MAX_SHARD_BITS + 1, 0, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bs(P(1), offp, 1, 0.0, 0.05, 0, 3, 8, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bs(P(1), offp, 1, 0.0, 0.05, 0, 3, -1, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bs(P(1), offp, 1, 0.06, 0.05, 0, 3, 7, None, C.byref(h)) == capt.CAPT_EINVAL
+    assert bs(P(1), offp, 1, 0.0, 0.05, 0, 3, 7, None, None) == capt.CAPT_EINVAL
+    assert h.value is None
     # cropped filter: NULL / non-finite base / negative reach / NULL count
     fc = lib.capt_filter_crop
     assert fc(P(1), 10, 0.01, None, P(1), None, C.byref(m), None) == capt.CAPT_EINVAL

@@ -53,6 +53,12 @@ def compare_build(capt, orc, pts, r_min, r_max, prune=True, axes=None):
     f = capt.capt_build(dev(pts), r_min, r_max, prune=prune, axes=axes)
     b = capt.parse_blob(capt.capt_export(f))
     t = orc.build_tree(pts, r_min, r_max, prune=prune, axes=axes)
+    same_tree(b, t)
+    return f, b, t
+
+
+def same_tree(b, t):
+    """A parsed blob against an oracle tree, array by array."""
     assert (b.n, b.N, b.D) == (t.n, t.N, t.D)
     assert np.array_equal(bits(b.T), bits(t.T)), "split values differ"
     assert np.array_equal(b.rep, t.rep), "representatives differ"
@@ -63,7 +69,6 @@ def compare_build(capt, orc, pts, r_min, r_max, prune=True, axes=None):
     assert np.array_equal(ig, io), "set members differ"
     # AABBs are min / max by value; the sign of a zero bound is not fixed
     assert np.array_equal(b.aabb, t.aabb), "AABBs differ"
-    return f, b, t
 
 
 # ---------------------------------------------------------------------------
@@ -573,6 +578,99 @@ def test_clearance_rejects_pruned_forest(capt):
     with pytest.raises(capt.CaptError) as e:
         capt.capt_clearance(f, dev(np.zeros((4, 4), np.float32) + 0.05))
     assert e.value.status == capt.CAPT_EPRUNED
+
+
+# ---------------------------------------------------------------------------
+# Shards: a forest built for one depth-k subtree's leaves
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prune", [True, False])
+def test_shard_build_matches_oracle(capt, orc, prune):
+    pts = synth.tabletop_cloud(6000, 2101)
+    t = orc.build_tree(pts, 0.015, 0.08, prune=prune)
+    x = dev(pts)
+    for bits, s in ((0, 0), (1, 0), (1, 1), (3, 5), (t.D, 77), (t.D + 2, 8), (t.D + 2, 9)):
+        _say(f"case: shard {s} of 2^{bits}, prune {prune}")
+        f = capt.capt_build(x, 0.015, 0.08, prune=prune, shard=(bits, s))
+        b = capt.parse_blob(capt.capt_export(f))
+        same_tree(b, orc.shard_tree(t, bits, s))
+        assert f.info()["set_total"] == int(orc.shard_tree(t, bits, s).off[-1])
+
+
+def test_shard_answers_combine_to_the_whole_forest(capt, orc):
+    _say("case: 4 shards of the filtered tabletop-50k, groups 1 and 60")
+    cloud = synth.tabletop_cloud(50_000, 2001)
+    pts = cloud[orc.filter(cloud, 0.01)[0]]
+    x = dev(pts)
+    t = orc.build_tree(pts, 0.015, 0.08)
+    whole = capt.capt_build(x, 0.015, 0.08)
+    sph = synth.posed_spheres(synth.chain_template(2003), 2000, synth.WORKSPACE, 2102)
+    sd = dev(sph)
+    bits = 2
+    acc1 = torch.zeros(len(sph), dtype=torch.uint8, device="cuda")
+    acc60 = torch.zeros(len(sph) // 60, dtype=torch.uint8, device="cuda")
+    size = 0
+    for s in range(2 ** bits):
+        f = capt.capt_build(x, 0.015, 0.08, shard=(bits, s))
+        size += f.info()["set_total"]
+        hit_o = orc.query_tree(orc.shard_tree(t, bits, s), pts, sph)[0]
+        g1 = capt.capt_collides(f, sd, 1)
+        g60 = capt.capt_collides(f, sd, 60)
+        assert np.array_equal(g1.cpu().numpy(), hit_o)
+        assert np.array_equal(g60.cpu().numpy(), hit_o.reshape(-1, 60).any(1).astype(np.uint8))
+        assert torch.equal(capt.capt_collides_padded(f, sd, 60, 0.0), g60)
+        acc1 |= g1
+        acc60 |= g60
+    assert size == whole.info()["set_total"]
+    assert torch.equal(acc1, capt.capt_collides(whole, sd, 1))
+    assert torch.equal(acc60, capt.capt_collides(whole, sd, 60))
+    assert np.array_equal(acc60.cpu().numpy(), orc.brute_f32(pts, sph, 60))
+
+
+def test_shard_clearance_combines_by_min(capt, orc):
+    _say("case: clearance over 2 shards of an unpruned forest")
+    cloud = synth.tabletop_cloud(50_000, 2001)
+    pts = cloud[orc.filter(cloud, 0.01)[0]]
+    x = dev(pts)
+    r_max = 0.08
+    t = orc.build_tree(pts, 0.0, r_max)
+    sph = synth.uniform_spheres(8000, synth.WORKSPACE, 0.015, 0.08, 2103)
+    sd = dev(sph)
+    leaf = orc.query_tree(t, pts, sph)[1]
+    clr_o, _, _ = orc.clearance_f64(pts, sph, r_max)
+    cw, ww = capt.capt_clearance(capt.capt_build(x, 0.0, r_max), sd)
+    best = torch.full_like(cw, np.inf)
+    for s in range(2):
+        f = capt.capt_build(x, 0.0, r_max, shard=(1, s))
+        c, w = capt.capt_clearance(f, sd)
+        mine = np.isin(leaf, np.array(orc.shard_leaves(t.N, 1, s)))
+        c64 = c.cpu().numpy().astype(np.float64)
+        assert (np.abs(c64[mine] - clr_o[mine]) <= 1e-4 * np.maximum(np.abs(clr_o[mine]), r_max)).all()
+        clamp = (np.float32(r_max) - sph[~mine, 3]).astype(np.float32)
+        assert np.array_equal(c.cpu().numpy()[~mine], clamp)
+        assert (w.cpu().numpy()[~mine] == -1).all()
+        m = torch.from_numpy(mine).cuda()
+        assert torch.equal(w[m], ww[m])
+        best = torch.minimum(best, c)
+    assert torch.equal(best, cw)
+
+
+def test_shard_of_batched_indexed_clouds_and_blob(capt, orc):
+    _say("case: shard 1 of 2 over 3 clouds with indexed sets, export and import")
+    clouds = [synth.tabletop_cloud(2000 + 1500 * k, 420 + k) for k in range(3)]
+    off = np.cumsum([0] + [len(c) for c in clouds]).tolist()
+    qs = [synth.uniform_spheres(60 * 400, synth.WORKSPACE, 0.015, 0.08, 430 + k) for k in range(3)]
+    qoff = np.cumsum([0] + [len(q) for q in qs]).tolist()
+    f = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off, indexed=True, shard=(1, 1))
+    want = []
+    for c, (pts, q) in enumerate(zip(clouds, qs)):
+        t = orc.shard_tree(orc.build_tree(pts, 0.015, 0.08), 1, 1)
+        same_tree(capt.parse_blob(capt.capt_export(f, c)), t)
+        want.append(orc.query_tree(t, pts, q)[0].reshape(-1, 60).any(1).astype(np.uint8))
+    sq = dev(np.concatenate(qs))
+    got = capt.capt_collides(f, sq, 60, query_off=qoff).cpu().numpy()
+    assert np.array_equal(got, np.concatenate(want))
+    fi = capt.capt_import(capt.capt_export(f, 2))
+    assert np.array_equal(capt.capt_collides(fi, dev(qs[2]), 60).cpu().numpy(), want[2])
 
 
 # ---------------------------------------------------------------------------
