@@ -135,8 +135,15 @@ __global__ void k_clearance_bwd(const float *__restrict__ pts, const float4 *__r
     gout[s] = r;
 }
 
+// Launch shape: four 512-thread blocks per CU fill its 32 wave slots, which
+// hides the set gathers far better than more tree levels in LDS at fewer
+// blocks (the 12 levels take 16 KB per block; 14 levels, 64 KB, would allow
+// only two blocks).
+constexpr int CLR_LDS_LEVELS = 12;
+constexpr int CLR_BLOCKS_PER_CU = 4;
+
 int lds_levels_c(int D) {
-    int L = std::min(D, 14);
+    int L = std::min(D, CLR_LDS_LEVELS);
     const size_t cap = (size_t)device_info().lds_per_block;
     while (L > 0 && sizeof(float) * (size_t)((1 << L) - 1) > cap) --L;
     return L;
@@ -154,7 +161,7 @@ capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t 
         const int L = lds_levels_c(C.D);
         const int threads = 512;
         const int64_t ntiles = (m + WAVE - 1) / WAVE;
-        int64_t blocks = std::min<int64_t>((ntiles + 7) / 8, (int64_t)device_info().cus * 2);
+        int64_t blocks = std::min<int64_t>((ntiles + 7) / 8, (int64_t)device_info().cus * CLR_BLOCKS_PER_CU);
         blocks = std::max<int64_t>(blocks, 1);
         const size_t lds = sizeof(float) * (size_t)((1 << L) - 1);
         hipLaunchKernelGGL(k_clearance, dim3((unsigned)blocks), dim3(threads), lds, s, C,
