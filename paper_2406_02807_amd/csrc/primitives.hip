@@ -245,13 +245,23 @@ __global__ void k_os_hist(const K *__restrict__ keys, int64_t len, int nseg, int
 }
 
 // ghist[pass][seg][256] = sum over blocks of part[block][seg][pass][256].
-__global__ void k_os_hist_sum(const uint32_t *__restrict__ part, int nblocks, int nseg, int npass,
-                              uint32_t *__restrict__ ghist) {
+// A block takes HS_BINS bins; its TB / HS_BINS thread groups each add a
+// strided share of the partials, then the shares are added in LDS.
+constexpr int HS_BINS = 32;
+__global__ void __launch_bounds__(TB) k_os_hist_sum(const uint32_t *__restrict__ part, int nblocks, int nseg,
+                                                    int npass, uint32_t *__restrict__ ghist) {
+    constexpr int NG = TB / HS_BINS;
+    __shared__ uint32_t acc[NG][HS_BINS];
     const int nh = nseg * npass * 256;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nh) return;
+    const int bl = threadIdx.x % HS_BINS, grp = threadIdx.x / HS_BINS;
+    const int i = blockIdx.x * HS_BINS + bl;
     uint32_t t = 0;
-    for (int b = 0; b < nblocks; ++b) t += part[(size_t)b * nh + i];
+    if (i < nh)
+        for (int b = grp; b < nblocks; b += NG) t += part[(size_t)b * nh + i];
+    acc[grp][bl] = t;
+    __syncthreads();
+    if (grp != 0 || i >= nh) return;
+    for (int q = 1; q < NG; ++q) t += acc[q][bl];
     const int g = i / (npass * 256), r = i % (npass * 256);
     const int p = r / 256, d = r % 256;
     ghist[((size_t)p * nseg + g) * 256 + d] = t;
@@ -407,8 +417,8 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
                            hpart);
         CAPT_LAUNCH_CHECK();
         const int nh = nseg * npass * 256;
-        hipLaunchKernelGGL(k_os_hist_sum, dim3((unsigned)((nh + TB - 1) / TB)), dim3(TB), 0, s, hpart, hblocks, nseg,
-                           npass, ghist);
+        hipLaunchKernelGGL(k_os_hist_sum, dim3((unsigned)((nh + HS_BINS - 1) / HS_BINS)), dim3(TB), 0, s, hpart,
+                           hblocks, nseg, npass, ghist);
         CAPT_LAUNCH_CHECK();
     }
     K *ki = k0, *ko = k1;
