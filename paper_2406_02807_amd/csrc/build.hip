@@ -1150,17 +1150,22 @@ __global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restr
                               const int32_t *__restrict__ pidx, const float *__restrict__ pts, int64_t nchunk,
                               float4 *__restrict__ cbox) {
     // CHUNK consecutive lanes share one chunk: one entry each, then a
-    // butterfly min / max over the group (padding entries do not count)
+    // butterfly min / max over the group (padding entries do not count).
+    // Stored points are finite and padding holds x = +inf, so plain sets
+    // need no index read; indexed sets mark padding with index -1.
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = e / CHUNK;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    const int32_t id = k < nchunk ? pidx[e] : -1;
-    if (id >= 0) {
-        if (px) {
-            lo[0] = hi[0] = px[e];
+    if (px) {
+        const float x = k < nchunk ? px[e] : INFINITY;
+        if (x < INFINITY) {
+            lo[0] = hi[0] = x;
             lo[1] = hi[1] = py[e];
             lo[2] = hi[2] = pz[e];
-        } else {   // indexed sets
+        }
+    } else {   // indexed sets
+        const int32_t id = k < nchunk ? pidx[e] : -1;
+        if (id >= 0) {
             lo[0] = hi[0] = pts[3 * (int64_t)id];
             lo[1] = hi[1] = pts[3 * (int64_t)id + 1];
             lo[2] = hi[2] = pts[3 * (int64_t)id + 2];
