@@ -50,8 +50,6 @@ typedef int32_t capt_status;
 #define CAPT_EUNSUPPORTED 6   /* size beyond the library's limits */
 
 /* Build flags */
-#define CAPT_MAX_SHARD_BITS 20 /* capt_build_shard: at most 2^20 shards */
-
 #define CAPT_NO_PRUNE     0x1u  /* never apply r_min pruning (Sec. IV-B) */
 #define CAPT_INDEXED_SETS 0x10u /* sets hold point indices only; queries gather the
                                    coordinates from the forest's point table */
@@ -59,6 +57,9 @@ typedef int32_t capt_status;
 #define CAPT_CHECK_RADII  0x2u  /* validate radii first (one device-to-host sync) */
 #define CAPT_PER_CLOUD    0x4u  /* forests: one launch per cloud, not one batched launch */
 #define CAPT_NO_GRAPH     0x8u  /* forests: launch the batched kernel directly, no hipGraph */
+
+/* Limits */
+#define CAPT_MAX_SHARD_BITS 20  /* capt_build_shard: at most 2^20 shards */
 
 /*
  * Filter (Alg. 2, Sec. IV-C).  For each of the six axis permutations, in the
