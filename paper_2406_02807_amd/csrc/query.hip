@@ -91,10 +91,11 @@ __device__ __forceinline__ Leaf descend_leaf_any(const float4 &q, const float *T
 
 // The same descent, shaped for latency: the LDS levels are taken three per
 // round trip (the node, both children and all four grandchildren are read
-// together, then three comparisons pick the path), and the last three (or
-// two) global levels are read together the same way, so the leaf record
-// arrives two memory round trips after the LDS part.  Returns the leaf
-// record; *lf gets its index.
+// together, then three comparisons pick the path), and so are the global
+// levels, the last one or two of them together when D - L is not a multiple
+// of three; so a tree with g global levels reaches its leaf record after
+// ceil(g / 3) + 1 memory round trips.  Returns the leaf record; *lf gets its
+// index.
 __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, int L, const float *__restrict__ Tg,
                                              const Leaf *__restrict__ leaves, int D, uint32_t *lf) {
     const float xs[3] = {q.x, q.y, q.z};
@@ -115,27 +116,24 @@ __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, i
         i = 2 * i + 1 + (xs[a] > Tl[i] ? 1u : 0u);
         a = (a == 2) ? 0 : a + 1;
     }
-    for (; lv + 3 < D; ++lv) {
-        i = 2 * i + 1 + (xs[a] > ld32(Tg, 4u * i) ? 1u : 0u);
-        a = (a == 2) ? 0 : a + 1;
-    }
-    if (D - lv == 3) {
-        // the last three levels in one round trip: the node, both children
-        // and all four grandchildren
+    // global levels three per round trip: the node, both children and all
+    // four grandchildren are read together, then three comparisons pick the
+    // path (after three levels the cyclic axis is back to `a`)
+    const int a1 = (a == 2) ? 0 : a + 1;
+    const int a2 = (a1 == 2) ? 0 : a1 + 1;
+    for (; lv + 3 <= D; lv += 3) {
         const float t0 = ld32(Tg, 4u * i);
         const float t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
         const float t2a = ld32(Tg, 16u * i + 12u), t2b = ld32(Tg, 16u * i + 16u);
         const float t2c = ld32(Tg, 16u * i + 20u), t2d = ld32(Tg, 16u * i + 24u);
-        const int a1 = (a == 2) ? 0 : a + 1;
-        const int a2 = (a1 == 2) ? 0 : a1 + 1;
         const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
         const uint32_t b1 = xs[a1] > (b0 ? t1b : t1a) ? 1u : 0u;
         const float t2 = b0 ? (b1 ? t2d : t2c) : (b1 ? t2b : t2a);
         const uint32_t b2 = xs[a2] > t2 ? 1u : 0u;
         i = 8 * i + 7 + 4 * b0 + 2 * b1 + b2;
-    } else if (D - lv == 2) {
+    }
+    if (D - lv == 2) {
         const float t0 = ld32(Tg, 4u * i), t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
-        const int a1 = (a == 2) ? 0 : a + 1;
         const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
         const uint32_t b1 = xs[a1] > (b0 ? t1b : t1a) ? 1u : 0u;
         i = 4 * i + 3 + 2 * b0 + b1;
