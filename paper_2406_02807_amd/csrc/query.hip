@@ -560,8 +560,8 @@ __global__ void k_reset_counter(unsigned int *ctr) {
 // The slot scheme of k_collide_slots over one fixed range of configurations
 // [c0, c1) of one cloud (no LDS tree levels); returns when all are answered.
 template <int U, bool IDX>
-__device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ sph, int g, int64_t c0, int64_t c1,
-                                 uint8_t *__restrict__ out, WaveLds &W) {
+__device__ void slots_over_range(const CloudDev &C, const float *Tl, int L, const float4 *__restrict__ sph, int g,
+                                 int64_t c0, int64_t c1, uint8_t *__restrict__ out, WaveLds &W) {
     const int lane = lane_id();
     const int j = lane & (SLOT - 1);
     const int lead = lane & ~(SLOT - 1);
@@ -584,7 +584,7 @@ __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ s
         const int si = s0 + j;
         const bool valid = active && si < g;
         const float4 q = valid ? sph[cfg * g + si] : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool hit = wave_tile<U, IDX, true, false>(C, nullptr, 0, q, valid, SLOT, false, W);
+        bool hit = wave_tile<U, IDX, true, false>(C, Tl, L, q, valid, SLOT, false, W);
         hit = __shfl(hit, lead, WAVE);
         if (active) {
             if (hit || s0 + SLOT >= g) {
@@ -597,13 +597,22 @@ __device__ void slots_over_range(const CloudDev &C, const float4 *__restrict__ s
     }
 }
 
+// Tree levels of the batched kernel's per-wave LDS copy (2^9 - 1 = 511 split
+// values).
+constexpr int BATCH_TOP = 9;
+
 template <int U, bool IDX>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
                                   const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
     extern __shared__ float4 lds4[];
     WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
+    // the top BATCH_TOP levels of the current tile's tree, one copy per wave,
+    // reloaded when a tile of another cloud comes
+    float *Tl = reinterpret_cast<float *>(reinterpret_cast<WaveLds *>(lds4) + blockDim.x / WAVE) +
+                (threadIdx.x / WAVE) * (1 << BATCH_TOP);
     const int lane = lane_id();
+    int cur = -1, L = 0;
     while (true) {
         unsigned int t = 0;
         if (lane == 0) t = atomicAdd(ctr, 1u);
@@ -611,15 +620,22 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
         if ((int64_t)t >= ntiles) break;
         const Tile tile = tiles[t];
         const CloudDev C = clouds[tile.cloud];
+        if (tile.cloud != cur) {
+            cur = tile.cloud;
+            L = min(C.D, BATCH_TOP);
+            wave_lds_sync();   // the last tile's descents are done with the old copy
+            for (int k = lane; k < (1 << L) - 1; k += WAVE) Tl[k] = C.T[k];
+            wave_lds_sync();
+        }
         if (g > SLOT) {
-            slots_over_range<U, IDX>(C, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
+            slots_over_range<U, IDX>(C, Tl, L, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
         } else {
             const int cpt = WAVE / g;
             for (int c = 0; c < tile.ncfg; c += cpt) {
                 const int64_t c0 = tile.cfg0 + c;
                 const int nc = min(cpt, tile.ncfg - c);
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-                const bool hit = wave_tile<U, IDX, false, false>(C, nullptr, 0, q, lane < nc * g, g, 2 * g > nc * g, W);
+                const bool hit = wave_tile<U, IDX, false, false>(C, Tl, L, q, lane < nc * g, g, 2 * g > nc * g, W);
                 if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
             }
         }
@@ -971,7 +987,7 @@ capt_status enqueue_batched_t(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
     int64_t blocks = (int64_t)device_info().cus * std::max(1, (int)t.groups_per_cu);
     const int64_t wpb = threads / WAVE;
     blocks = std::max<int64_t>(1, std::min(blocks, (p->ntiles + wpb - 1) / wpb));
-    const size_t lds = sizeof(WaveLds) * (size_t)wpb;
+    const size_t lds = (sizeof(WaveLds) + sizeof(float) * ((size_t)1 << BATCH_TOP)) * (size_t)wpb;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, p->d_ctr);
     CAPT_LAUNCH_CHECK();
     if (p->ntiles > 0) {
