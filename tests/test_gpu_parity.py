@@ -530,6 +530,29 @@ def test_batched_matches_per_cloud_and_oracle(capt, orc):
         assert np.array_equal(x, want)
 
 
+@pytest.mark.parametrize("group", [60, 7])
+def test_batched_tiny_and_empty_clouds(capt, orc, group):
+    # depths 0 .. 12 in one forest: an empty cloud, one point, two, five, and
+    # clouds deeper than the batched kernel's per-wave tree copy
+    sizes = [0, 1, 2, 5, 300, 3000]
+    _say(f"case: batched tiny and empty clouds, group {group}")
+    clouds = [synth.tabletop_cloud(n, 440 + k) if n else np.zeros((0, 3), np.float32)
+              for k, n in enumerate(sizes)]
+    qs = [synth.uniform_spheres(group * (50 + 30 * k), synth.WORKSPACE, 0.015, 0.08, 450 + k)
+          for k in range(len(sizes))]
+    off = np.cumsum([0] + [len(c) for c in clouds]).tolist()
+    qoff = np.cumsum([0] + [len(q) for q in qs]).tolist()
+    f = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off)
+    assert [f.info(c)["D"] for c in range(len(sizes))] == [0, 0, 1, 3, 9, 12]
+    want = np.concatenate([orc.brute_f32(c, q, group) if len(c) else np.zeros(len(q) // group, np.uint8)
+                           for c, q in zip(clouds, qs)])
+    sq = dev(np.concatenate(qs))
+    for flags in (0, capt.CAPT_NO_GRAPH, capt.CAPT_PER_CLOUD):
+        got = capt.capt_collides(f, sq, group, query_off=qoff, flags=flags).cpu().numpy()
+        assert np.array_equal(got, want), flags
+    assert want.any() and not want.all()
+
+
 # ---------------------------------------------------------------------------
 # Clearance and its gradient
 # ---------------------------------------------------------------------------
