@@ -33,6 +33,41 @@ __device__ __forceinline__ uint32_t descend_c(const float4 &q, const float *Tl, 
     return i;
 }
 
+// The nearest point as one 64-bit key: the bits of the float32 squared
+// distance (never negative, so its bit pattern orders like its value) above
+// the point's original index, so the minimum key is the nearest point with
+// ties to the smallest index.  A NaN distance orders above every key that
+// can win, as a NaN never compares below a distance.
+constexpr uint64_t KEY_NONE = ((uint64_t)0x7f800000u << 32) | 0x7fffffffu;   // (+inf, INT_MAX)
+
+__device__ __forceinline__ uint64_t key_min(uint64_t a, uint64_t b) { return b < a ? b : a; }
+
+// Minimum over one DPP-permuted copy of v: ctrl picks the source lane inside
+// each row of 16.
+template <int CTRL> __device__ __forceinline__ uint64_t dpp_min(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+    return key_min(v, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t lane_key(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Minimum key over the wave (every lane active): swaps of neighbours and of
+// pairs inside each quad, then the mirror images inside each half row and
+// each row leave every lane of a row with the row's minimum; the four rows
+// are then combined from one lane each.
+__device__ __forceinline__ uint64_t wave_min_key(uint64_t v) {
+    v = dpp_min<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_min<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_min<0x141>(v);   // row_half_mirror
+    v = dpp_min<0x140>(v);   // row_mirror
+    return key_min(key_min(lane_key(v, 0), lane_key(v, 16)), key_min(lane_key(v, 32), lane_key(v, 48)));
+}
+
 __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t nsph, float r_max,
                             float *__restrict__ clr, int32_t *__restrict__ wit, int L) {
     extern __shared__ float Tl[];
@@ -60,8 +95,7 @@ __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t 
                 need = !(sqrtf(b2) >= r_max);
             }
         }
-        float best = INFINITY;
-        int32_t besti = INT_MAX;
+        uint64_t best = KEY_NONE;   // the key of this lane's sphere
         uint64_t todo = __ballot(need);
         while (todo) {
             const int o = __builtin_ctzll(todo);
@@ -71,38 +105,23 @@ __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t 
             const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.z), o));
             const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)start, o);
             const uint32_t ct = (uint32_t)__builtin_amdgcn_readlane((int)count, o);
-            float m = INFINITY;
-            int32_t mi = INT_MAX;
+            uint64_t m = KEY_NONE;
             for (uint32_t k = lane; k < ct; k += WAVE) {
                 const uint32_t e = st + k;
                 float x, y, z;
                 set_point(C, e, x, y, z);
                 const float d2 = sqdist(ox, oy, oz, x, y, z);
-                const int32_t id = C.pidx[e];
-                if (d2 < m || (d2 == m && id < mi)) {
-                    m = d2;
-                    mi = id;
-                }
+                const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)C.pidx[e];
+                m = key < m ? key : m;
             }
-#pragma unroll
-            for (int off = WAVE / 2; off >= 1; off >>= 1) {
-                const float om = __shfl_xor(m, off, WAVE);
-                const int32_t oi = __shfl_xor(mi, off, WAVE);
-                if (om < m || (om == m && oi < mi)) {
-                    m = om;
-                    mi = oi;
-                }
-            }
-            if (lane == o) {
-                best = m;
-                besti = mi;
-            }
+            m = wave_min_key(m);
+            if (lane == o) best = m;
         }
         if (valid) {
-            const float d = need ? sqrtf(best) : INFINITY;
+            const float d = need ? sqrtf(__uint_as_float((uint32_t)(best >> 32))) : INFINITY;
             if (d < r_max) {
                 clr[s] = __fsub_rn(d, q.w);
-                wit[s] = besti;
+                wit[s] = (int32_t)(uint32_t)best;
             } else {
                 clr[s] = __fsub_rn(r_max, q.w);
                 wit[s] = -1;
