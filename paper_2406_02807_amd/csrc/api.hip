@@ -54,6 +54,11 @@ void keep_pool_cached() {
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
         uint64_t thr = UINT64_MAX;
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        // never reuse a block whose free on another stream has not completed
+        // yet: the pool would make this allocation's stream wait for that
+        // stream's work (a frame's build behind the previous frame's query)
+        int no = 0;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &no);
     }
     (void)hipGetLastError();
     done[dev] = true;
