@@ -6,9 +6,10 @@
 // away, the clamp is active and no point needs reading).  The remaining
 // spheres are then processed one after another by the whole wave: the 64
 // lanes stream the sphere's set in coalesced 64-entry steps keeping a running
-// (squared distance, index) minimum, and one butterfly reduction per sphere
-// yields the argmin (ties -> smallest original index).  Sets here are full
-// scans, so lanes across the set keep loads contiguous and every lane busy.
+// minimum of one 64-bit key per entry (squared distance above index), and one
+// branch-free wave minimum of the keys per sphere yields the argmin (ties ->
+// smallest original index).  Sets here are full scans, so lanes across the
+// set keep loads contiguous and every lane busy.
 //
 // Backward: thread per sphere; reads the witness point from the cloud copy
 // kept in the forest, 48 bytes of traffic per sphere.
