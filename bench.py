@@ -20,8 +20,9 @@ step (60,000,000 spheres / step time).  Printed as one JSON line, with:
 and, unless --no-extras, the batched ragged workload (64 clouds, one
 persistent launch vs one launch per cloud vs GPU brute force), the
 clearance forward/backward workload, the per-frame rebuild latency
-(filter -> build) of a 307,200-point synthetic depth frame, and motion-edge
-validation with posed template spheres.
+(filter -> build) of a 307,200-point synthetic depth frame, motion-edge
+validation with posed template spheres, and the room scan (1.2M points): build
+time, all 100,000,000 single-sphere queries, indexed sets and four shards.
 """
 from __future__ import annotations
 
@@ -226,7 +227,8 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
 def bench_indexed(capt, torch, reps=5):
     """Indexed affordance sets (point indices only) against plain sets on the
     room scene (1.2M points filtered at 5 mm, r_max = 0.1 m): forest bytes and
-    the time of 10,000,000 single-sphere queries, with equal answers.  Then
+    the time of 10,000,000 single-sphere queries, with equal answers, and of
+    all 100,000,000 queries of the workload on the plain forest.  Then
     the same forest as 4 shards (the subtrees of the depth-2 nodes) built and
     queried one after the other: bytes, build and query time per shard, and
     the OR of the shards' answers against the whole forest's."""
@@ -265,6 +267,16 @@ def bench_indexed(capt, torch, reps=5):
         rows[name + "_ms"] = timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps)
         rows[name + "_bytes"] = int(f.info()["bytes"])
         outs[name] = out.clone()
+        if not ix:
+            # the whole 100,000,000-sphere query set of the room workload
+            full = torch.from_numpy(w.spheres).cuda()
+            out_full = torch.empty(len(full), dtype=torch.uint8, device="cuda")
+            ms = timed(lambda: capt.capt_collides(f, full, 1, out=out_full), 3)
+            rows["full_queries"] = int(len(full))
+            rows["full_query_ms"] = ms
+            rows["full_queries_per_s"] = len(full) / (ms * 1e-3)
+            rows["full_first_10m_agree"] = bool(torch.equal(out_full[:len(sph)], out))
+            del full, out_full
         f.close()
     rows["same_answers"] = bool(torch.equal(outs["plain"], outs["indexed"]))
     bits = 2
@@ -280,7 +292,8 @@ def bench_indexed(capt, torch, reps=5):
         f.close()
     sh["same_answers_or"] = bool(torch.equal(acc, outs["plain"]))
     rows["shards_4"] = sh
-    rows["workload"] = "room scene, 1.2M points -> 5 mm filter, r_max = 0.1, 10,000,000 single-sphere queries"
+    rows["workload"] = ("room scene, 1.2M points -> 5 mm filter, r_max = 0.1, 10,000,000 single-sphere queries "
+                        "(full_*: all 100,000,000)")
     return rows
 
 
