@@ -324,14 +324,23 @@ def bench_posed(capt, torch, forest, reps=5):
             ts.append(a.elapsed_time(b))
         return float(np.median(ts))
 
+    # the project autotuner picks this workload's launch shape (posing the
+    # spheres in the kernel shifts the balance of the slot kernel); both forms
+    # are timed under it and the caller's shape is restored afterwards
+    from paper_2406_02807_amd import autotune
+    prev = capt.capt_get_tuning()
+    out = torch.empty(n_edges, dtype=torch.uint8, device="cuda")
+    tuned, _ = autotune.autotune_step(lambda: capt.capt_collides_posed(forest, td, pd, steps, out=out),
+                                      lambda: out)
     t_posed = timed(lambda: capt.capt_collides_posed(forest, td, pd, steps))
     t_mat = timed(lambda: capt.capt_collides(forest, sph, G))
     same = bool(torch.equal(capt.capt_collides_posed(forest, td, pd, steps), capt.capt_collides(forest, sph, G)))
     hit = capt.capt_collides_posed(forest, td, pd, steps).float().mean().item()
+    capt.capt_set_tuning(**prev)
     return {"workload": "tabletop forest; 100,000 motion edges x 10 rigid poses of the 60-sphere template",
             "edges": n_edges, "configurations": n_edges * steps, "edge_collision_rate": hit,
             "posed_ms": t_posed, "materialised_ms": t_mat, "input_bytes_posed": int(poses.nbytes + tmpl.nbytes),
-            "input_bytes_materialised": int(sph.numel() * 4), "same_answers": same}
+            "input_bytes_materialised": int(sph.numel() * 4), "same_answers": same, "tuning": tuned}
 
 
 def bench_frame(capt, torch, reps=10):
