@@ -143,7 +143,12 @@ def bench_batched(capt, torch, reps=5):
     query_off = np.concatenate([[0], np.cumsum([len(s) for s in w.spheres])])
     xyz = torch.from_numpy(np.concatenate(w.cloud)).cuda()
     sph = torch.from_numpy(np.concatenate(w.spheres)).cuda()
+    capt.capt_build(xyz, w.r_min, w.r_max, cloud_off=cloud_off).close()   # warm the pool
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     f = capt.capt_build(xyz, w.r_min, w.r_max, cloud_off=cloud_off)
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) * 1e3
     out = torch.empty(len(sph) // 60, dtype=torch.uint8, device="cuda")
 
     def timed(fn, n):
@@ -182,6 +187,7 @@ def bench_batched(capt, torch, reps=5):
                     "configurations, r_min = 0.015, r_max = 0.08",
         "spheres": m,
         "cloud_points": int(cloud_off[-1]),
+        "build_ms": t_build,
         "batched_ms": t_batch,
         "per_cloud_ms": t_per,
         "brute_per_cloud_ms": t_brute,

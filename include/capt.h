@@ -325,8 +325,11 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
 
 /*
  * Device memory hooks for forests and scratch.  alloc returns NULL on failure.
- * Passing NULL for both restores hipMalloc / hipFree.  Not thread-safe with
- * respect to concurrent entry points.
+ * Passing NULL for both restores the default, the device's stream-ordered pool
+ * (hipMallocAsync / hipFreeAsync).  The stream handed to the hooks is the one
+ * the memory is used on in order: the caller's stream, or a side stream the
+ * library forks from it (a build's grid binning runs on one) and joins back
+ * into it before the entry point's work ends on the caller's stream.  Not thread-safe with respect to concurrent entry points.
  */
 capt_status capt_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
                                void (*release)(void *ptr, void *stream, void *ctx),
