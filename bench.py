@@ -423,7 +423,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(queries shard by configuration with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(across GPUs the queries would shard by configuration, with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
