@@ -11,7 +11,7 @@
  * (contraction off so every float/double product and sum rounds on its own;
  * x86-64 SSE arithmetic has FLT_EVAL_METHOD == 0).
  *
- * Readings the paper leaves open (each is also listed in the design doc):
+ * Readings the paper leaves open:
  *  - distance test (Alg. 3 and Sec. IV-D): a sphere (x, r) touches p iff
  *    fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)) <= fl(r*r) in float32, with
  *    dx = fl(x_x - p_x) etc.: closed ball, no square root, no fused multiply-add.
