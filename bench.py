@@ -45,6 +45,7 @@ SPHERE_BYTES = 16
 ENTRY_BYTES = 12     # x, y, z of one set entry
 BOX_BYTES = 32       # one chunk box (two float4)
 CHUNK = 16           # set entries per chunk
+EXTRAS = ("batched", "clearance", "frame", "posed", "indexed_sets")
 
 
 def log(*a):
@@ -403,6 +404,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="configurations timed on the CPU")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all", metavar="LIST",
+                    help="comma-separated extras to run (" + ", ".join(EXTRAS) + "), or all")
     ap.add_argument("--no-brute", action="store_true")
     ap.add_argument("--tune-query", default=None, metavar="JSON",
                     help="launch shape for the serial frames instead of autotuning (e.g. for profiling)")
@@ -421,6 +424,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
         return
+    if args.extras != "all" and not set(args.extras.split(",")) <= set(EXTRAS):
+        print(f"unknown extras {args.extras!r}; choose from {', '.join(EXTRAS)} or all", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(across GPUs the queries would shard by configuration, with no exchange)", file=sys.stderr)
@@ -623,18 +629,25 @@ def main():
         log(f"brute force {tb:.1f} ms, exact {result['brute']['exact']}")
     forest.close()
 
-    if not args.no_extras:
-        capt.capt_set_tuning(**tuned)   # the extras run under the query's own tuned shape
+    extras = set(EXTRAS if args.extras == "all" else args.extras.split(","))
+    if args.no_extras:
+        extras = set()
+    capt.capt_set_tuning(**tuned)   # the extras run under the query's own tuned shape
+    if "batched" in extras:
         result["batched"] = bench_batched(capt, torch)
         log(f"batched: {result['batched']}")
+    if "clearance" in extras:
         result["clearance"] = bench_clearance(capt, torch, fx.contiguous())
         log(f"clearance: {result['clearance']}")
+    if "frame" in extras:
         result["frame"] = bench_frame(capt, torch)
         log(f"frame: {result['frame']}")
+    if "posed" in extras:
         f_posed = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
         result["posed"] = bench_posed(capt, torch, f_posed)
         f_posed.close()
         log(f"posed: {result['posed']}")
+    if "indexed_sets" in extras:
         result["indexed_sets"] = bench_indexed(capt, torch)
         log(f"indexed sets: {result['indexed_sets']}")
 

@@ -13,3 +13,10 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_unknown_extra_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--extras", "frame,nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "unknown extras" in r.stderr
