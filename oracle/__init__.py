@@ -16,6 +16,7 @@ Functions and what they follow:
   clearance_f64    nearest-point distance clamped at r_max, minus r, and its
                    gradient (not in the paper; defined for the differentiable
                    query)
+  prunable         Construct's r_min pruning test for one leaf (Sec. IV-B)
   build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning; split
                    axis d mod 3, or a given axis per depth (the alternative
                    to the cyclic rule that Sec. IV-A mentions)
@@ -80,6 +81,7 @@ def _load():
             "orc_morton_grid": (None, [P, i64, P, P]),
             "orc_morton_cell": (None, [P, P, C.c_double, P]),
             "orc_filter": (i64, [P, i64, f32, C.c_int, P, P]),
+            "orc_prunable": (C.c_int, [P, P, f32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -121,6 +123,16 @@ def brute_f32(points, spheres, group: int = 1, pad: float = 0.0) -> np.ndarray:
     out = np.zeros(len(sph) // group, dtype=np.uint8)
     _load().orc_brute_f32(_p(pts), len(pts), _p(sph), len(sph), group, _p(out))
     return out
+
+
+def prunable(cell, rep, r_min: float) -> bool:
+    """The r_min pruning test of Construct (Alg. 1, Sec. IV-B) for one leaf:
+    closed cell [lo xyz, hi xyz] (float32, all finite) and representative t:
+    the float64 squared distance from t to the cell's farthest corner is at
+    most r_min^2 (1 - 2^-18), r_min > 0."""
+    c = np.ascontiguousarray(cell, dtype=np.float32).reshape(6)
+    t = np.ascontiguousarray(rep, dtype=np.float32).reshape(3)
+    return bool(_load().orc_prunable(_p(c), _p(t), np.float32(r_min)))
 
 
 def pose_spheres(template, poses) -> np.ndarray:

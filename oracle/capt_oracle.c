@@ -232,6 +232,11 @@ static int prunable(const float *c, const float *t, float r_min)
     return far2 <= thr;
 }
 
+ORC_API int orc_prunable(const float *cell, const float *t, float r_min)
+{
+    return prunable(cell, t, r_min);
+}
+
 typedef struct {
     const float *pts;
     int64_t n;
