@@ -267,18 +267,28 @@ capt_status capt_clearance(capt_forest f, const float *spheres, const int64_t *q
                            float *clearance, int32_t *witness, void *stream);
 
 /*
- * Backward of capt_clearance: for each sphere,
- *   grad_spheres[s] = (g * (x - p*) / |x - p*|, -g)   if witness >= 0 and x != p*
- *                     (0, 0, 0, -g)                    otherwise
- * with g = grad_clearance[s] and p* the witness point of its cloud.
- *   witness       [M] from capt_clearance
+ * Backward of capt_clearance (the clearance is c = min(d, r_max) - r): for
+ * each sphere, with g = grad_clearance[s] and p* the witness point of its
+ * cloud,
+ *   grad_center[s] = g * (x - p*) / |x - p*|   if witness >= 0 and x != p*
+ *                    (0, 0, 0)                  otherwise (clamped, or x = p*)
+ *   grad_radius[s] = -g
+ * The direction is computed in float32: d = x - p* per axis, |d| as the
+ * correctly rounded square root of ((dx*dx + dy*dy) + dz*dz).
+ *   spheres        [M][4];  query_off  host [ncloud + 1]
+ *   witness        [M] int32 from capt_clearance on the same spheres and forest
+ *                  (-1 or an index into that cloud's capt_build input)
  *   grad_clearance [M] float32
- *   grad_spheres  [M][4] float32 (d/dx, d/dy, d/dz, d/dr)
+ *   grad_center    [M][3] float32 (d/dx, d/dy, d/dz)
+ *   grad_radius    [M] float32, or NULL to skip it
+ * Asynchronous on `stream`.  CAPT_EPRUNED on a forest with pruned leaves;
+ * CAPT_EINVAL for NULL buffers with M > 0.  A witness outside the cloud's
+ * index range is not detected (it comes from capt_clearance).
  */
 capt_status capt_clearance_backward(capt_forest f, const float *spheres,
                                     const int64_t *query_off, const int32_t *witness,
-                                    const float *grad_clearance, float *grad_spheres,
-                                    void *stream);
+                                    const float *grad_clearance, float *grad_center,
+                                    float *grad_radius, void *stream);
 
 /* Release a forest's device memory (waits for the device first).  NULL is a no-op. */
 void capt_destroy(capt_forest f);
@@ -307,9 +317,15 @@ capt_status capt_forest_info(capt_forest f, int32_t cloud, int64_t *n, int32_t *
  * forest from one.  With host_blob == NULL, capt_export only writes the
  * required size to *bytes.  Export synchronises.  Blob layout (little endian,
  * every section starts at a multiple of 8 bytes):
- *   header   uint32 magic 0x54504143 ("CAPT"), uint32 version 1,
+ *   header   uint32 magic 0x54504143 ("CAPT"), uint32 version (1 or 2),
  *            int64 n, int64 N, int32 D, uint32 flags, float r_min, float r_max,
- *            int64 set_total (S)
+ *            int64 set_total (S)                                  (48 bytes)
+ *   uint64   axes                version 2 only: bits 2d, 2d+1 hold the split
+ *                                axis (0 x, 1 y, 2 z) of depth d < D, all
+ *                                higher bits 0.  Export writes version 2 for a
+ *                                forest from capt_build_axes whose axes are
+ *                                not the cyclic d mod 3, version 1 otherwise
+ *                                (version 1 means d mod 3)
  *   float    points [n][3]       the cloud as given to capt_build
  *   float    T [N-1]             test sequence (Eytzinger order)
  *   int32    rep [N]             representative index per leaf (>= n: padding)
@@ -317,8 +333,12 @@ capt_status capt_forest_info(capt_forest f, int32_t cloud, int64_t *n, int32_t *
  *   uint8    pruned [N]
  *   int64    set_off [N+1]       set of leaf l is entries set_off[l] .. set_off[l+1]
  *   int32    set_idx [S]         original point indices in stored (scan) order
- * capt_import checks sizes, ranges and that every AABB is the bounding box of
- * its set (CAPT_EINVAL otherwise); it does not re-derive the sets.
+ * capt_import checks the header (D <= 30, N = 2^D, n <= N < 2n, S < 2^30),
+ * the blob size, that the N + 1 set offsets start at 0, never decrease and
+ * end at S before any set is read, that every set entry and representative is
+ * in range, every point is finite and every AABB is the bounding box of its
+ * set (CAPT_EINVAL otherwise); it does not re-derive the sets.  Import
+ * synchronises.
  */
 capt_status capt_export(capt_forest f, int32_t cloud, void *host_blob, size_t *bytes);
 capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_forest *out);

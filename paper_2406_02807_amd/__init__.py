@@ -70,7 +70,7 @@ def load_library(path: str = LIB_PATH):
         "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
         "capt_collides": [P, P, P, i32, P, u32, P],
         "capt_clearance": [P, P, P, P, P, P],
-        "capt_clearance_backward": [P, P, P, P, P, P, P],
+        "capt_clearance_backward": [P, P, P, P, P, P, P, P],
         "capt_forest_info": [P, i32, P, P, P, P, P],
         "capt_export": [P, i32, P, P],
         "capt_import": [P, C.c_size_t, P, P],
@@ -335,7 +335,8 @@ def capt_clearance(forest: Forest, spheres, query_off=None, stream=None):
 
 
 def capt_clearance_backward(forest: Forest, spheres, witness, grad_clearance, query_off=None,
-                            stream=None):
+                            radius: bool = True, stream=None):
+    """Returns (grad_center [M, 3], grad_radius [M] or None when radius is False)."""
     import torch
     lib = load_library()
     spheres = _dev(spheres, torch.float32, 4, "spheres")
@@ -343,10 +344,12 @@ def capt_clearance_backward(forest: Forest, spheres, witness, grad_clearance, qu
     grad_clearance = _dev(grad_clearance.contiguous(), torch.float32, None, "grad_clearance")
     M = spheres.shape[0]
     off = _offsets([0, M] if query_off is None else query_off, forest.ncloud)
-    g = torch.empty((M, 4), dtype=torch.float32, device=spheres.device)
+    gc = torch.empty((M, 3), dtype=torch.float32, device=spheres.device)
+    gr = torch.empty((M,), dtype=torch.float32, device=spheres.device) if radius else None
     _check(lib.capt_clearance_backward(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p),
-                                       _ptr(witness), _ptr(grad_clearance), _ptr(g), _stream(stream)))
-    return g
+                                       _ptr(witness), _ptr(grad_clearance), _ptr(gc), _ptr(gr),
+                                       _stream(stream)))
+    return gc, gr
 
 
 def capt_bruteforce_collides(xyz, spheres, group: int = 1, cloud_off=None, query_off=None,
@@ -539,8 +542,9 @@ def _clearance_fn():
         @staticmethod
         def backward(ctx, grad_clr, grad_wit):
             spheres, wit = ctx.saved_tensors
-            g = capt_clearance_backward(ctx.forest, spheres, wit, grad_clr, ctx.query_off)
-            return g, None, None
+            gc, gr = capt_clearance_backward(ctx.forest, spheres, wit, grad_clr, ctx.query_off)
+            # the two kernel outputs side by side in the layout of `spheres`
+            return torch.cat([gc, gr[:, None]], 1), None, None
 
     return Clearance
 

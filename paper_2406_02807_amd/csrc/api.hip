@@ -649,14 +649,14 @@ capt_status capt_clearance(capt_forest f, const float *spheres, const int64_t *q
 }
 
 capt_status capt_clearance_backward(capt_forest f, const float *spheres, const int64_t *query_off,
-                                    const int32_t *witness, const float *grad_clearance, float *grad_spheres,
-                                    void *stream) {
+                                    const int32_t *witness, const float *grad_clearance, float *grad_center,
+                                    float *grad_radius, void *stream) {
     ApiGuard g;
     capt_status st = check_queries(f, spheres, query_off, 1);
     if (st) return st;
     const int64_t M = query_off[f->clouds.size()];
-    if (M > 0 && (!witness || !grad_clearance || !grad_spheres)) {
-        set_error("witness, grad_clearance or grad_spheres is NULL");
+    if (M > 0 && (!witness || !grad_clearance || !grad_center)) {
+        set_error("witness, grad_clearance or grad_center is NULL");
         return CAPT_EINVAL;
     }
     if (f->pruned_total > 0) {
@@ -664,7 +664,8 @@ capt_status capt_clearance_backward(capt_forest f, const float *spheres, const i
         return CAPT_EPRUNED;
     }
     if (M == 0) return CAPT_OK;
-    return clearance_bwd(f, spheres, query_off, witness, grad_clearance, grad_spheres, (hipStream_t)stream);
+    return clearance_bwd(f, spheres, query_off, witness, grad_clearance, grad_center, grad_radius,
+                         (hipStream_t)stream);
 }
 
 void capt_destroy(capt_forest f) { destroy_forest(f); }
@@ -746,10 +747,12 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const char *B = static_cast<const char *>(host_blob);
     BlobHeader h;
     memcpy(&h, B, sizeof h);
+    // every size is bounded here, before the layout is computed from them, so
+    // the section offsets below cannot wrap
     if (h.magic != BLOB_MAGIC || h.version < 1 || h.version > BLOB_VERSION || h.n < 0 || h.D < 0 || h.D > 30 ||
         h.N != ((int64_t)1 << h.D) || h.n > h.N || (h.n > 0 && h.N >= 2 * h.n) || h.set_total < 0 ||
-        !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max ||
-        (h.flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS))) {
+        h.set_total >= (int64_t)MAX_SET_ENTRIES || !(h.r_max > 0.0f) || !(h.r_min >= 0.0f) || h.r_min > h.r_max ||
+        !std::isfinite(h.r_max) || (h.flags & ~(CAPT_NO_PRUNE | CAPT_INDEXED_SETS))) {
         set_error("blob header is invalid");
         return CAPT_EINVAL;
     }
@@ -776,10 +779,17 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const int64_t *off = reinterpret_cast<const int64_t *>(B + L.off);
     const int32_t *idx = reinterpret_cast<const int32_t *>(B + L.idx);
     const uint8_t *pr = reinterpret_cast<const uint8_t *>(B + L.pruned);
+    // all N + 1 offsets before any set is read: start at 0, never decrease,
+    // end at S (so every set lies inside the idx section)
     if (off[0] != 0 || off[h.N] != h.set_total) {
         set_error("blob set offsets are invalid");
         return CAPT_EINVAL;
     }
+    for (int64_t l = 0; l < h.N; ++l)
+        if (off[l + 1] < off[l] || off[l + 1] > h.set_total) {
+            set_error("blob set offsets of leaf %lld are invalid", (long long)l);
+            return CAPT_EINVAL;
+        }
     for (int64_t j = 0; j < 3 * h.n; ++j)
         if (!std::isfinite(pts[j])) {
             set_error("blob point %lld is not finite", (long long)(j / 3));

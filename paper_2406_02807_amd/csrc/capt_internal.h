@@ -263,7 +263,7 @@ capt_tuning &tuning();
 capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t *query_off,
                           float *clr, int32_t *witness, hipStream_t s);
 capt_status clearance_bwd(capt_forest_s *f, const float *spheres, const int64_t *query_off,
-                          const int32_t *witness, const float *grad, float *grad_sph,
+                          const int32_t *witness, const float *grad, float *grad_center, float *grad_radius,
                           hipStream_t s);
 
 // filter.hip

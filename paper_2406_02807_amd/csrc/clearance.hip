@@ -12,7 +12,8 @@
 // set keep loads contiguous and every lane busy.
 //
 // Backward: thread per sphere; reads the witness point from the cloud copy
-// kept in the forest, 48 bytes of traffic per sphere.
+// kept in the forest: 16 (sphere) + 4 (witness) + 4 (incoming gradient) + 12
+// (witness point) read, 12 (d/dx, d/dy, d/dz) + 4 (d/dr, optional) written.
 #include <climits>
 #include <cmath>
 
@@ -133,12 +134,13 @@ __global__ void k_clearance(CloudDev C, const float4 *__restrict__ sph, int64_t 
 
 __global__ void k_clearance_bwd(const float *__restrict__ pts, const float4 *__restrict__ sph,
                                 int64_t nsph, const int32_t *__restrict__ wit,
-                                const float *__restrict__ grad, float4 *__restrict__ gout) {
+                                const float *__restrict__ grad, float *__restrict__ gc,
+                                float *__restrict__ gr) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nsph) return;
     const float g = grad[s];
     const int32_t w = wit[s];
-    float4 r = make_float4(0.f, 0.f, 0.f, -g);
+    float rx = 0.f, ry = 0.f, rz = 0.f;
     if (w >= 0) {
         const float4 q = sph[s];
         const float dx = __fsub_rn(q.x, pts[3 * (int64_t)w]);
@@ -147,12 +149,15 @@ __global__ void k_clearance_bwd(const float *__restrict__ pts, const float4 *__r
         const float d = sqrtf(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz)));
         if (d > 0.0f) {
             const float k = g / d;
-            r.x = k * dx;
-            r.y = k * dy;
-            r.z = k * dz;
+            rx = k * dx;
+            ry = k * dy;
+            rz = k * dz;
         }
     }
-    gout[s] = r;
+    gc[3 * s] = rx;
+    gc[3 * s + 1] = ry;
+    gc[3 * s + 2] = rz;
+    if (gr) gr[s] = -g;
 }
 
 // Launch shape: four 512-thread blocks per CU fill its 32 wave slots, which
@@ -193,14 +198,15 @@ capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t 
 }
 
 capt_status clearance_bwd(capt_forest_s *f, const float *spheres, const int64_t *qoff, const int32_t *witness,
-                          const float *grad, float *grad_sph, hipStream_t s) {
+                          const float *grad, float *grad_center, float *grad_radius, hipStream_t s) {
     const int nc = (int)f->clouds.size();
     for (int c = 0; c < nc; ++c) {
         const int64_t m = qoff[c + 1] - qoff[c];
         if (m <= 0) continue;
         hipLaunchKernelGGL(k_clearance_bwd, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                            f->clouds[c].dev.pts, reinterpret_cast<const float4 *>(spheres + 4 * qoff[c]), m,
-                           witness + qoff[c], grad + qoff[c], reinterpret_cast<float4 *>(grad_sph + 4 * qoff[c]));
+                           witness + qoff[c], grad + qoff[c], grad_center + 3 * qoff[c],
+                           grad_radius ? grad_radius + qoff[c] : nullptr);
         CAPT_LAUNCH_CHECK();
     }
     return CAPT_OK;

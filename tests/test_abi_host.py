@@ -164,3 +164,40 @@ def test_product_does_not_import_the_oracle():
         if f.endswith((".py", ".c", ".h")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2406_02807_amd" not in txt and "capt_internal" not in txt, f
+
+
+def test_import_rejects_bad_offsets_before_reading_sets(lib):
+    """A blob whose set offsets run past the idx section (or wrap) is refused
+    on the host, before any set entry is read."""
+    import paper_2406_02807_amd as capt
+    rng = np.random.default_rng(1)
+    pts = rng.random((5, 3)).astype(np.float32)
+    N = 8
+    T = np.sort(rng.random(N - 1)).astype(np.float32)
+    rep = np.arange(N, dtype=np.int32)
+    aabb = np.tile(np.array([np.inf] * 3 + [-np.inf] * 3, np.float32), (N, 1))
+    pr = np.zeros(N, np.uint8)
+    idx = np.zeros(0, np.int32)
+    h = C.c_void_p()
+    for off in ([0, 1_000_000_000, 0, 0, 0, 0, 0, 0, 0],        # far past S, then back
+                [0, 0, 0, 0, 0, 0, 0, 2 ** 40, 0],                # huge, would wrap an index
+                [0, 0, 0, 0, 0, 0, 0, 0, 1]):                     # ends past S = 0
+        b = capt.make_blob(pts, T, rep, aabb, pr, np.array(off, np.int64), idx, 0.01, 0.05)
+        buf = C.create_string_buffer(b, len(b))
+        assert lib.capt_import(buf, len(b), None, C.byref(h)) == capt.CAPT_EINVAL
+        assert b"offset" in lib.capt_last_error()
+        assert h.value is None
+    # a set_total of 2^30 or more is refused from the header alone
+    b = bytearray(capt.make_blob(pts, T, rep, aabb, pr, np.zeros(N + 1, np.int64), idx, 0.01, 0.05))
+    b[40:48] = (1 << 31).to_bytes(8, "little")
+    buf = C.create_string_buffer(bytes(b), len(b))
+    assert lib.capt_import(buf, len(b), None, C.byref(h)) == capt.CAPT_EINVAL
+    assert b"header" in lib.capt_last_error()
+
+
+def test_clearance_backward_validation(lib):
+    import paper_2406_02807_amd as capt
+    P = C.c_void_p
+    q = np.array([0, 4], np.int64)
+    assert lib.capt_clearance_backward(None, P(1), q.ctypes.data_as(P), P(1), P(1), P(1), None,
+                                       None) == capt.CAPT_EINVAL

@@ -860,3 +860,27 @@ def test_posed_edges_match_oracle(capt, orc, edge):
     assert np.array_equal(got, want)
     assert np.array_equal(capt.capt_collides(f, dev(sph), edge * len(tmpl)).cpu().numpy(), want)
     assert 0 < want.sum() < len(want) or edge > 1
+
+
+def test_clearance_backward_boundary(capt, orc):
+    """capt_clearance_backward writes grad_center [M, 3] and, unless NULL,
+    grad_radius [M]; both against the float64 oracle's analytic gradient."""
+    _say("case: clearance backward outputs, grad_radius NULL and not")
+    pts = synth.tabletop_cloud(8000, 2203)
+    f = capt.capt_build(dev(pts), 0.0, 0.08)
+    sph = synth.uniform_spheres(5000, synth.WORKSPACE, 0.015, 0.08, 2204)
+    s = dev(sph)
+    clr, wit = capt.capt_clearance(f, s)
+    g = torch.linspace(-2.0, 3.0, len(sph), device="cuda", dtype=torch.float32)
+    gc, gr = capt.capt_clearance_backward(f, s, wit, g)
+    gc2, none = capt.capt_clearance_backward(f, s, wit, g, radius=False)
+    assert none is None and torch.equal(gc, gc2)
+    assert torch.equal(gr, -g)
+    _, wit_o, grad_o = orc.clearance_f64(pts, sph, 0.08)
+    w = wit.cpu().numpy()
+    same = w == wit_o
+    assert same.mean() > 0.99
+    ref = grad_o * g.cpu().numpy().astype(np.float64)[:, None]
+    err = np.linalg.norm(gc.cpu().numpy().astype(np.float64) - ref, axis=1)
+    assert (err[same] <= 1e-4 * np.linalg.norm(ref[same], axis=1) + 1e-6).all()
+    assert (gc.cpu().numpy()[w < 0] == 0).all()
