@@ -212,6 +212,25 @@ capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *qu
                           int32_t group, uint8_t *out, uint32_t flags, void *stream);
 
 /*
+ * capt_collides that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and answers as capt_collides, always
+ * one launch per cloud (the kernels of capt_collides with CAPT_PER_CLOUD).  The
+ * work-queue counters of the launches live in a library-owned device array of
+ * CAPT_NOALLOC_MAX_CLOUDS x 8 counters (128 KiB per GPU, held until the
+ * process ends), found once per device; every launch clears its cloud's
+ * counters with a fill kernel first.
+ *   flags      0 (CAPT_CHECK_RADII needs a host read-back and is refused)
+ * A forest of more than CAPT_NOALLOC_MAX_CLOUDS clouds gives
+ * CAPT_EUNSUPPORTED.  Every call on one GPU shares that array: calls on one
+ * stream are ordered and safe, calls that overlap on one GPU (different
+ * streams, different threads) race on the counters and give wrong answers.
+ */
+#define CAPT_NOALLOC_MAX_CLOUDS 256
+capt_status capt_collides_noalloc(capt_forest f, const float *spheres, const int64_t *query_off,
+                                  int32_t group, uint8_t *out, uint32_t flags, void *stream);
+
+/*
  * capt_collides with query padding (Sec. V-B, after the filter lemma): every
  * radius r becomes fl(r + pad) before the test, so that a forest built from a
  * filtered cloud answers conservatively (pad = r_filter per filter pass that

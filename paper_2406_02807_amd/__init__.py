@@ -26,9 +26,11 @@ CAPT_PER_CLOUD = 0x4
 CAPT_NO_GRAPH = 0x8
 CAPT_INDEXED_SETS = 0x10
 CAPT_MAX_SHARD_BITS = 20
+CAPT_NOALLOC_MAX_CLOUDS = 256
 
 EXPORTS = [
     "capt_filter", "capt_filter_crop", "capt_build", "capt_build_axes", "capt_build_shard", "capt_build_filtered", "capt_collides",
+    "capt_collides_noalloc",
     "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
@@ -69,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "capt_filter_crop": [P, i64, f32, P, P, P, P, P],
         "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
         "capt_collides": [P, P, P, i32, P, u32, P],
+        "capt_collides_noalloc": [P, P, P, i32, P, u32, P],
         "capt_clearance": [P, P, P, P, P, P],
         "capt_clearance_backward": [P, P, P, P, P, P, P, P],
         "capt_forest_info": [P, i32, P, P, P, P, P],
@@ -276,6 +279,27 @@ def capt_collides(forest: Forest, spheres, group: int = 1, query_off=None, flags
         out = torch.empty((M // group,), dtype=torch.uint8, device=spheres.device)
     _check(lib.capt_collides(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
                              _ptr(out), flags, _stream(stream)))
+    return out
+
+
+def capt_collides_noalloc(forest: Forest, spheres, group: int, out, query_off=None, stream=None):
+    """capt_collides without any device allocation inside the library: the
+    caller passes `out` (uint8 [M / group]); the queue counters live in the
+    library's own device array.  Returns `out`."""
+    import torch
+    lib = load_library()
+    spheres = _dev(spheres, torch.float32, 4, "spheres")
+    out = _dev(out, torch.uint8, None, "out")
+    M = spheres.shape[0]
+    if query_off is None:
+        if forest.ncloud != 1:
+            raise ValueError("query_off is required for a forest of several clouds")
+        query_off = [0, M]
+    off = _offsets(query_off, forest.ncloud)
+    if out.numel() < M // group:
+        raise ValueError(f"out holds {out.numel()} bytes, {M // group} needed")
+    _check(lib.capt_collides_noalloc(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
+                                     _ptr(out), 0, _stream(stream)))
     return out
 
 

@@ -577,6 +577,24 @@ capt_status capt_collides(capt_forest f, const float *spheres, const int64_t *qu
     return collides(f, spheres, query_off, group, out, flags, (hipStream_t)stream);
 }
 
+capt_status capt_collides_noalloc(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
+                                  uint8_t *out, uint32_t flags, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, group);
+    if (st) return st;
+    if (flags != 0) {
+        set_error("capt_collides_noalloc takes flags 0 (got 0x%x)", flags);
+        return CAPT_EINVAL;
+    }
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && !out) {
+        set_error("out is NULL");
+        return CAPT_EINVAL;
+    }
+    if (M == 0) return CAPT_OK;
+    return collides_noalloc(f, spheres, query_off, group, out, (hipStream_t)stream);
+}
+
 capt_status capt_collides_padded(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
                                  float pad, uint8_t *out, uint32_t flags, void *stream) {
     ApiGuard g;

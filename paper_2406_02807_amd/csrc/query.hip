@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "capt_internal.h"
@@ -1102,6 +1103,60 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
         CAPT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     }
     CAPT_HIP(hipGraphLaunch(p->exec, s));
+    return CAPT_OK;
+}
+
+// Queue counters of capt_collides_noalloc: one set of NXCD counters (a
+// 64-byte line each) per cloud.  Host code never passes this array's name to a
+// kernel (on the host it is only a stand-in for the symbol); the launches take
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned int scratch[CAPT_NOALLOC_MAX_CLOUDS * NXCD * CTR_STRIDE];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned int *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+capt_status scratch_address(unsigned int **out) {
+    int dev = 0;
+    CAPT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("device ordinal %d beyond the %d the library tracks", dev, MAX_DEVICES);
+        return CAPT_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the query counters failed: %s", hipGetErrorString(e));
+            return CAPT_EHIP;
+        }
+        g_scratch_dev[dev] = static_cast<unsigned int *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return CAPT_OK;
+}
+}  // namespace
+
+capt_status collides_noalloc(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, uint8_t *out,
+                             hipStream_t s) {
+    const int nc = (int)f->clouds.size();
+    if (nc > CAPT_NOALLOC_MAX_CLOUDS) {
+        set_error("forest of %d clouds: the allocation-free query takes at most %d", nc, CAPT_NOALLOC_MAX_CLOUDS);
+        return CAPT_EUNSUPPORTED;
+    }
+    unsigned int *ctr = nullptr;
+    capt_status st = scratch_address(&ctr);
+    if (st) return st;
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = qoff[c + 1] - qoff[c];
+        st = launch_cloud(f->clouds[c].dev, spheres + 4 * qoff[c], m, g, out + qoff[c] / g,
+                          ctr + (size_t)c * NXCD * CTR_STRIDE, s);
+        if (st) return st;
+    }
     return CAPT_OK;
 }
 
