@@ -1,28 +1,35 @@
 """Benchmark of the CAPT hot path on one MI355X.
 
-Workload (the tabletop scene): 50,000 points on 24 boxes and 8 cylinders in a
-2 x 2 x 1.5 m workspace with 2 mm noise, Morton filter at r_filter = 1 cm,
-CAPT with r_min = 0.015, r_max = 0.08, then 1,000,000 robot configurations of
-60 spheres each (rigid random poses of a seeded chain template), one boolean
-per configuration with early exit.
+Headline workload (the room scan, the largest single-GPU workload): 1,200,000
+points of a 6 x 6 x 3 m room (floor, four walls, 20 boxes and 20 cylinders,
+3 mm noise, 10% uniform outliers), Morton filter at r_filter = 5 mm, CAPT with
+r_min = 0.01, r_max = 0.1, then 100,000,000 single-sphere queries (centres
+uniform in the room, radii uniform in [0.01, 0.1]), one boolean per sphere.
 
-One step = filter -> build -> collide, the whole collision path, on inputs
-already resident in HBM.  `value` is sphere queries per second over the whole
-step (60,000,000 spheres / step time).  Printed as one JSON line, with:
-  roofline      the query kernel's algorithmic bytes (per configuration: the
-                spheres, leaf records, chunk boxes and surviving 16-entry
-                chunks that a sequential two-level scan in stored order reads
-                up to the first colliding sphere) over its HIP-event-timed
-                duration, against 8 TB/s
-  cpu_baseline  the oracle's filter + build + CollisionCheck (one thread, early
-                exit per configuration) on the same workload
-  brute         the GPU brute force on the same spheres (answers compared)
-and, unless --no-extras, the batched ragged workload (64 clouds, one
-persistent launch vs one launch per cloud vs GPU brute force), the
-clearance forward/backward workload, the per-frame rebuild latency
-(filter -> build) of a 307,200-point synthetic depth frame, motion-edge
-validation with posed template spheres, and the room scan (1.2M points): build
-time, all 100,000,000 single-sphere queries, indexed sets and four shards.
+One step = one capt_collides over all 100,000,000 spheres on the room's
+forest, inputs resident in HBM; `value` is sphere queries per second over the
+timed steps.  The filter and the build are timed separately (phase_ms) and
+the rate of the whole path (filter + build + query) is reported beside it.
+The JSON line also carries:
+  roofline      the query kernel's algorithmic bytes per launch (per sphere:
+                16 B sphere + 32 B leaf record + 12 B per set entry scanned
+                up to the first hit in stored order, nothing past the record
+                when the leaf box rejects, + 1 B answer) over its
+                HIP-event-timed duration in the timed steps, against 8 TB/s
+  achievable    yardsticks measured on the same chip: a streaming HBM read,
+                re-reads of L2- and MALL-sized buffers, and the query's own
+                gather pattern without its arithmetic (same records, same
+                runs of entries); gather_frac = the query's rate of
+                algorithmic bytes over the gather yardstick's
+  cpu_baseline  the oracle's CollisionCheck on the exported forest, on one
+                thread and on all host cores (bounded samples)
+  brute         the GPU brute force on a sample of the spheres
+and, unless --no-extras, the tabletop frame loop (filter -> build -> 1,000,000
+60-sphere configurations, double-buffered), the batched ragged workload (64
+clouds in one persistent launch), the clearance forward/backward workload,
+the per-frame rebuild latency of a 307,200-point depth frame, motion-edge
+validation with posed template spheres, and indexed sets / four shards of the
+room forest.
 """
 from __future__ import annotations
 
@@ -30,6 +37,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -45,57 +53,170 @@ SPHERE_BYTES = 16
 ENTRY_BYTES = 12     # x, y, z of one set entry
 BOX_BYTES = 32       # one chunk box (two float4)
 CHUNK = 16           # set entries per chunk
-EXTRAS = ("batched", "clearance", "frame", "posed", "indexed_sets")
+EXTRAS = ("tabletop", "batched", "clearance", "frame", "posed", "indexed_sets")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(capt, forest, spheres_dev, group):
-    """Sum over configurations of the bytes a sequential two-level scan in
-    stored order reads up to (and including) the first colliding sphere: per
-    sphere its 16 bytes and leaf record, then, unless the leaf AABB rejects
-    it, the chunk boxes it tests and the 16 entries of every chunk whose box
-    is within reach, up to the chunk holding its first hit; plus one output
-    byte per configuration."""
-    import torch
-    leaf, rej, scanned, hit = capt.capt_query_stats(forest, spheres_dev)
-    boxes, chunks = capt.capt_query_chunk_stats(forest, spheres_dev)
+def event_ms(torch, fn, reps, warm=1):
+    """Median duration of fn() from HIP events on the current stream."""
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
-    rej = rej.cpu().numpy().astype(np.int64)
-    sc = scanned.cpu().numpy().astype(np.int64)
-    hit = hit.cpu().numpy().astype(bool)
-    nb = boxes.cpu().numpy().astype(np.int64)
-    nc = chunks.cpu().numpy().astype(np.int64)
-    per = SPHERE_BYTES + LEAF_BYTES + BOX_BYTES * nb + CHUNK * ENTRY_BYTES * nc
-    per = per.reshape(-1, group)
-    h = hit.reshape(-1, group)
-    first = np.where(h.any(1), h.argmax(1), group - 1)
-    mask = np.arange(group)[None, :] <= first[:, None]
-    canonical = int((per * mask).sum()) + h.shape[0]
-    m = mask.reshape(-1)
-    return canonical, {
-        "aabb_reject_rate": float(rej.mean()),
-        "mean_scanned_per_sphere": float(sc.mean()),
-        "spheres_read_canonical": int(mask.sum()),
-        "one_level_bytes_canonical": int(((SPHERE_BYTES + LEAF_BYTES + ENTRY_BYTES * np.where(rej == 1, 0, sc))
-                                          * m).sum()) + h.shape[0],
-        "mean_boxes_per_read_sphere": float(nb[m].mean()) if m.any() else 0.0,
-        "mean_chunks_per_read_sphere": float(nc[m].mean()) if m.any() else 0.0,
-    }
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
 
 
-def query_kernel(group):
-    """The kernel capt_collides launches for one cloud: configurations above 16
-    spheres run in 16-lane slots."""
-    return "k_collide_slots" if group > 16 else "k_collide_cloud"
+def query_work(capt, torch, forest, sph, group, query_off=None):
+    """Per-sphere work of the collision query, from the library's counters
+    (capt_query_stats: leaf, box rejection, entries scanned to the first hit in
+    stored order; capt_query_chunk_stats: chunk boxes and chunks of the
+    two-level scan).  Spheres count in canonical order up to the first
+    colliding sphere of their configuration (every sphere when group = 1).
+    Returns the totals and the per-sphere tensors the gather yardstick needs."""
+    leaf, rej, sc, hit = capt.capt_query_stats(forest, sph, query_off=query_off)
+    boxes, chunks = capt.capt_query_chunk_stats(forest, sph, query_off=query_off)
+    ms = torch.where(rej.bool(), torch.zeros_like(sc), sc).long()
+    h = hit.bool().view(-1, group)
+    first = torch.where(h.any(1), h.int().argmax(1), torch.full_like(h[:, 0], group - 1, dtype=torch.long))
+    mask = (torch.arange(group, device=sph.device)[None, :] <= first[:, None]).view(-1)
+    ncfg = h.shape[0]
+    one_level = int(((SPHERE_BYTES + LEAF_BYTES + ENTRY_BYTES * ms) * mask).sum().item()) + ncfg
+    two_level = int(((SPHERE_BYTES + LEAF_BYTES + BOX_BYTES * boxes.long() + CHUNK * ENTRY_BYTES * chunks.long())
+                     * mask).sum().item()) + ncfg
+    nread = int(mask.sum().item())
+    return {
+        "algorithmic_bytes_per_launch": one_level,
+        "two_level_bytes_per_launch": two_level,
+        "spheres_read": nread,
+        "aabb_reject_rate": float(rej[mask].float().mean().item()) if nread else 0.0,
+        "mean_scanned_per_read_sphere": float(ms[mask].float().mean().item()) if nread else 0.0,
+        "mean_scanned_per_unrejected_sphere": float(ms[mask & ~rej.bool()].float().mean().item())
+        if bool((mask & ~rej.bool()).any()) else 0.0,
+        "mean_boxes_per_read_sphere": float(boxes[mask].float().mean().item()) if nread else 0.0,
+        "mean_chunks_per_read_sphere": float(chunks[mask].float().mean().item()) if nread else 0.0,
+    }, (leaf, ms, mask)
 
 
-def traffic_from_profiles(kernel, kernel_src_hash):
+def set_sizes(capt, forest, cloud=0):
+    """Per-leaf set sizes of one cloud (from its export)."""
+    b = capt.parse_blob(capt.capt_export(forest, cloud))
+    return np.diff(b.off).astype(np.int64), b
+
+
+def gather_yardstick(capt, torch, sizes_per_cloud, leaf_base, leaf, ms, mask, reps=5):
+    """The query's memory pattern without its arithmetic: per read sphere a
+    16-byte descriptor, its 32-byte leaf record, then its scanned entries of
+    three float32 arrays laid out like the forest's sets (each set starts at a
+    multiple of 16 entries).  Returns (best ms, lanes per item, bytes)."""
+    recs, entries = [], 0
+    for a in sizes_per_cloud:
+        start = entries + np.concatenate([[0], np.cumsum((a + CHUNK - 1) // CHUNK * CHUNK)[:-1]])
+        entries = int(start[-1] + (a[-1] + CHUNK - 1) // CHUNK * CHUNK) if len(a) else entries
+        r = np.zeros((len(a), 8), np.int32)
+        r[:, 6] = start.astype(np.uint32).view(np.int32)
+        r[:, 7] = a.astype(np.int32)
+        recs.append(r)
+    rec = torch.from_numpy(np.concatenate(recs)).cuda()
+    sel = mask.nonzero().squeeze(1)
+    items = torch.zeros((len(sel), 4), dtype=torch.int32, device=leaf.device)
+    items[:, 0] = (leaf.long() + leaf_base)[sel].int()
+    items[:, 1] = ms[sel].int()
+    del sel
+    x = torch.ones(max(entries, 1), dtype=torch.float32, device=leaf.device)
+    y, z = torch.ones_like(x), torch.ones_like(x)
+    out = torch.empty(items.shape[0], dtype=torch.uint8, device=leaf.device)
+    best = None
+    for lpi in (16, 64):
+        t = event_ms(torch, lambda: capt.capt_probe_gather(items, rec, x, y, z, lanes_per_item=lpi, out=out), reps)
+        if best is None or t < best[0]:
+            best = (t, lpi)
+    nbytes = int(items.shape[0]) * (SPHERE_BYTES + LEAF_BYTES + 1) + ENTRY_BYTES * int(items[:, 1].long().sum().item())
+    del items, x, y, z, out, rec
+    return best[0], best[1], nbytes
+
+
+def read_yardsticks(capt, torch):
+    """Streaming read of 4 GiB (HBM) and re-reads of 16 MiB (L2-resident:
+    4 MB per XCD) and 128 MiB (MALL-resident) buffers, in GB/s."""
+    res = {}
+    for name, size, passes in (("hbm_stream_read", 4 << 30, 1), ("l2_reread", 16 << 20, 256),
+                               ("mall_reread", 128 << 20, 32)):
+        buf = torch.ones(size // 4, dtype=torch.float32, device="cuda")
+        t = event_ms(torch, lambda: capt.capt_probe_read(buf, passes), 5)
+        res[name + "_gbs"] = size * passes / (t * 1e-3) / 1e9
+        del buf
+    return res
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline_room(blob, spheres, got_dev, target_s=8.0):
+    """The oracle's CollisionCheck (Alg. 3) on the exported room forest: one
+    thread, then all the threads OpenMP gives it, each on a bounded prefix of
+    the query spheres sized for about `target_s` seconds."""
+    import oracle
+    setxyz = blob.points[blob.idx]
+    T, aabb, off = blob.T, blob.aabb, blob.off
+    model, nproc = cpu_info()
+    threads_all = oracle.max_threads()
+
+    def run(m):
+        t0 = time.perf_counter()
+        h, _, _, _ = oracle.query(blob.N, blob.D, T, aabb, off, setxyz, spheres[:m])
+        return time.perf_counter() - t0, h
+
+    try:
+        oracle.set_threads(1)
+        dt, _ = run(100_000)
+        m1 = int(min(len(spheres), max(100_000, 100_000 * target_s / max(dt, 1e-6))))
+        dt1, h1 = run(m1)
+    finally:
+        oracle.set_threads(threads_all)
+    dt, _ = run(1_000_000)
+    mall = int(min(len(spheres), max(1_000_000, 1_000_000 * target_s / max(dt, 1e-6))))
+    dta, ha = run(mall)
+    got = got_dev[:mall].cpu().numpy()
+    agree = bool(np.array_equal(ha, got) and np.array_equal(h1, got[:m1]))
+    del setxyz
+    return {
+        "value": mall / dta,
+        "unit": "queries/s",
+        "cores": threads_all,
+        "kind": "oracle",
+        "sample": (f"oracle CollisionCheck (per sphere, OpenMP over spheres) on the exported room forest: the "
+                   f"first {mall:,} of {len(spheres):,} spheres on {threads_all} threads ({dta:.1f} s); "
+                   f"single thread on the first {m1:,} ({dt1:.1f} s); answers equal the GPU's"),
+        "single_thread_queries_per_s": m1 / dt1,
+        "single_thread_ns_per_query": dt1 / m1 * 1e9,
+        "cpu_model": model,
+        "nproc": nproc,
+    }, agree
+
+
+def traffic_from_profiles(name, kernel_src_hash):
     """HBM bytes per launch measured with rocprofv3 counters (committed under
     profiles/), or None when missing or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", f"{kernel}_tabletop_traffic.json")
+    p = os.path.join(ROOT, "profiles", name)
     try:
         d = json.load(open(p))
     except Exception:
@@ -112,33 +233,296 @@ def src_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(w, group, n_cfg_sample):
-    import oracle
+def query_kernel(group):
+    """The kernel capt_collides launches for one cloud: configurations above 16
+    spheres run in 16-lane slots."""
+    return "k_collide_slots" if group > 16 else "k_collide_cloud"
+
+
+# ---------------------------------------------------------------------------
+# Headline: the room scan
+# ---------------------------------------------------------------------------
+def bench_room(capt, torch, args):
+    import synth
+    from paper_2406_02807_amd import autotune
     t0 = time.perf_counter()
-    keep, _ = oracle.filter(w.cloud, w.r_filter)
-    pts = w.cloud[keep]
-    tree = oracle.build_tree(pts, w.r_min, w.r_max)
-    t1 = time.perf_counter()
-    sph = w.spheres[: n_cfg_sample * group]
-    out = oracle.query_serial(tree.N, tree.D, tree.T, tree.aabb, tree.off, pts[tree.idx], sph, group)
-    t2 = time.perf_counter()
-    total_cfg = len(w.spheres) // group
-    est = (t1 - t0) + (t2 - t1) * total_cfg / n_cfg_sample
-    return {
-        "value": len(w.spheres) / est,
-        "unit": "queries/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle filter + build on the full 50,000-point cloud ({t1 - t0:.2f} s) and "
-                   f"single-thread CollisionCheck with per-configuration early exit on the first "
-                   f"{n_cfg_sample:,} of {total_cfg:,} configurations ({t2 - t1:.2f} s), scaled to the "
-                   f"full workload"),
-        "ns_per_query_query_only": (t2 - t1) / len(sph) * 1e9,
-    }, out
+    w = synth.workload(5)
+    log(f"room workload generated in {time.perf_counter() - t0:.1f} s: {len(w.cloud)} points, "
+        f"{len(w.spheres)} spheres")
+    xyz = torch.from_numpy(w.cloud).cuda()
+    sph = torch.from_numpy(w.spheres).cuda()
+    m = len(w.spheres)
+    out = torch.empty(m, dtype=torch.uint8, device="cuda")
+
+    # filter and build, each timed on its own (HIP events, median of 3)
+    fx = None
+
+    def do_filter():
+        nonlocal fx
+        fx, _ = capt.capt_filter(xyz, w.r_filter)
+
+    filter_ms = event_ms(torch, do_filter, 3)
+    pts = fx.contiguous()
+    forests = []
+
+    def do_build():
+        forests.append(capt.capt_build(pts, w.r_min, w.r_max))
+        if len(forests) > 1:
+            forests.pop(0).release()
+
+    build_ms = event_ms(torch, do_build, 3)
+    f = forests[-1]
+    info = f.info()
+    log(f"room: filter {filter_ms:.2f} ms -> {info['n']} points, build {build_ms:.2f} ms "
+        f"(D = {info['D']}, {info['set_total']} set entries, {info['bytes'] / 1e9:.2f} GB)")
+
+    if args.tune_query:
+        tuned = json.loads(args.tune_query)
+        capt.capt_set_tuning(**tuned)
+    else:
+        tuned, _ = autotune.autotune(f, sph, 1)
+    log(f"room tuning: {tuned}")
+
+    def step():
+        capt.capt_collides(f, sph, 1, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_step = t_total / args.steps * 1e3
+    q_ms = float(np.mean(step_ms))
+    log(f"room: {ms_step:.2f} ms per step ({m / (ms_step * 1e-3):.3g} queries/s), kernel events "
+        f"{min(step_ms):.2f}-{max(step_ms):.2f} ms")
+    if args.query_only:
+        return {"value": m / (ms_step * 1e-3), "ms_per_step": ms_step, "step_query_ms": step_ms,
+                "phase_ms": {"filter": filter_ms, "build": build_ms, "query": q_ms}, "tuning": tuned}, \
+            f, None, w, out, pts
+
+    work, (leaf, ms, mask) = query_work(capt, torch, f, sph, 1)
+    alg = work["algorithmic_bytes_per_launch"]
+    achieved = alg / (q_ms * 1e-3) / 1e9
+    sizes, blob = set_sizes(capt, f)
+    g_ms, g_lpi, g_bytes = gather_yardstick(capt, torch, [sizes], 0, leaf, ms, mask)
+    del leaf, ms, mask
+    gather_gbs = g_bytes / (g_ms * 1e-3) / 1e9
+    achievable = read_yardsticks(capt, torch)
+    achievable.update({
+        "gather_gbs": gather_gbs,
+        "gather_ms": g_ms,
+        "gather_lanes_per_item": g_lpi,
+        "gather_pattern": "the room query's own records and runs (every sphere: 16 B descriptor, its leaf's "
+                          "32 B record, its scanned entries of three float32 arrays, 1 B out)",
+        "gather_frac": achieved / gather_gbs,
+        "gather_frac_target": 0.40,
+        "gather_frac_target_met": bool(achieved / gather_gbs >= 0.40),
+    })
+    log(f"room roofline: {achieved:.0f} GB/s of algorithmic bytes; yardsticks {achievable}")
+
+    # GPU brute force on a sample (all 10^8 would take minutes)
+    nb = min(m, args.brute_sample)
+    sub = sph[:nb].contiguous()
+    br_ms = event_ms(torch, lambda: capt.capt_bruteforce_collides(pts, sub, 1), 1, warm=0)
+    br = capt.capt_bruteforce_collides(pts, sub, 1)
+    brute = {
+        "sample_spheres": nb,
+        "ms_sample": br_ms,
+        "queries_per_s": nb / (br_ms * 1e-3),
+        "capt_query_speedup": (br_ms / nb) / (q_ms / m),
+        "exact": bool(torch.equal(br, out[:nb])),
+    }
+    del sub, br
+
+    res = {
+        "value": m / (ms_step * 1e-3),
+        "ms_per_step": ms_step,
+        "config": {
+            "workload": "room-1.2M: 1,200,000 points (6 x 6 x 3 m room, floor + 4 walls + 20 boxes + 20 "
+                        "cylinders, 3 mm noise, 10% uniform outliers) -> Morton filter r_filter = 0.005 -> CAPT "
+                        "r_min = 0.01, r_max = 0.1 -> 100,000,000 spheres uniform in the room, r in [0.01, 0.1], "
+                        "one bool per sphere",
+            "points_in": len(w.cloud),
+            "points_after_filter": int(info["n"]),
+            "tree_depth": int(info["D"]),
+            "set_entries": int(info["set_total"]),
+            "forest_bytes": int(info["bytes"]),
+            "spheres": m,
+            "group": 1,
+        },
+        "ns_per_query": ms_step * 1e6 / m,
+        "phase_ms": {"filter": filter_ms, "build": build_ms, "query": q_ms},
+        "end_to_end_queries_per_s": m / ((filter_ms + build_ms + q_ms) * 1e-3),
+        "step_query_ms": step_ms,
+        "collision_rate": float(out.float().mean().item()),
+        "tuning": tuned,
+        "roofline": {
+            "kernel": query_kernel(1),
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles("k_collide_cloud_room_traffic.json", src_hash()),
+            "kernel_ms": q_ms,
+            **work,
+        },
+        "achievable": achievable,
+        "brute": brute,
+    }
+    out_host = out
+    return res, f, blob, w, out_host, pts
+
+
+# ---------------------------------------------------------------------------
+# Extras
+# ---------------------------------------------------------------------------
+def bench_tabletop(capt, torch, args):
+    """The tabletop frame loop: Morton filter of 50,000 points, CAPT build and
+    1,000,000 configurations of 60 spheres per frame; serial frames give the
+    phase times, double-buffered frames (the next frame's filter and build
+    beside this frame's query) the throughput."""
+    import synth
+    from paper_2406_02807_amd import autotune
+    w = synth.workload(2)
+    G = w.group
+    xyz = torch.from_numpy(w.cloud).cuda()
+    sph = torch.from_numpy(w.spheres).cuda()
+    m = len(w.spheres)
+    out = torch.empty(m // G, dtype=torch.uint8, device="cuda")
+    prev_tuning = capt.capt_get_tuning()
+
+    def step(ev=None):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if ev is not None else None
+        if e:
+            e[0].record()
+        fx, _ = capt.capt_filter(xyz, w.r_filter)
+        if e:
+            e[1].record()
+        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+        if e:
+            e[2].record()
+        capt.capt_collides(f, sph, G, out=out)
+        if e:
+            e[3].record()
+            ev.append(e)
+        return f, fx
+
+    f, fx = step()
+    tuned, _ = autotune.autotune(f, sph, G)
+    f.close()
+    for _ in range(3):
+        f, fx = step()
+        f.release()
+    torch.cuda.synchronize()
+    events = []
+    forest = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        f, fx = step(events)
+        if forest is not None:
+            forest.release()
+        forest = f
+    torch.cuda.synchronize()
+    serial_ms = (time.perf_counter() - t_start) / args.steps * 1e3
+    forest.close()
+    filt = np.array([a.elapsed_time(b) for a, b, _, _ in events])
+    build = np.array([b.elapsed_time(c) for _, b, c, _ in events])
+    query = np.array([c.elapsed_time(d) for _, _, c, d in events])
+
+    s_query, s_build = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def piped_step(prev, qev=None):
+        with torch.cuda.stream(s_build):
+            f = capt.capt_build_filtered(xyz, w.r_filter, w.r_min, w.r_max)
+            ready = torch.cuda.Event()
+            ready.record(s_build)
+        s_query.wait_event(ready)
+        with torch.cuda.stream(s_query):
+            if qev is not None:
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record(s_query)
+            capt.capt_collides(f, sph, G, out=out)
+            if qev is not None:
+                e[1].record(s_query)
+                qev.append(e)
+            if prev is not None:
+                prev.release()
+        return f
+
+    def piped_frames(k):
+        f = None
+        for _ in range(k):
+            f = piped_step(f)
+        with torch.cuda.stream(s_query):
+            f.release()
+
+    tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
+    forest = None
+    for _ in range(3):
+        forest = piped_step(forest)
+    torch.cuda.synchronize()
+    qev = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        forest = piped_step(forest, qev)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_step = t_total / args.steps * 1e3
+    q_timed = [a.elapsed_time(b) for a, b in qev]
+    info = forest.info()
+    work, _ = query_work(capt, torch, forest, sph, G)
+    q_alone = float(query.mean())
+    alg = work["algorithmic_bytes_per_launch"]
+    res = {
+        "workload": "tabletop-50k: 50,000 points on 24 boxes + 8 cylinders (2 mm noise) -> Morton filter "
+                    "r_filter = 0.01 -> CAPT r_min = 0.015, r_max = 0.08 -> 1,000,000 configurations x 60 "
+                    "spheres, one bool per configuration; one step = filter + build + query, double-buffered",
+        "points_after_filter": int(fx.shape[0]),
+        "tree_depth": int(info["D"]),
+        "set_entries": int(info["set_total"]),
+        "ms_per_step": ms_step,
+        "configurations_per_s": (m // G) / (ms_step * 1e-3),
+        "sphere_queries_per_s_nominal": m / (ms_step * 1e-3),
+        "query_only_configurations_per_s": (m // G) / (q_alone * 1e-3),
+        "phase_ms": {"filter": float(filt.mean()), "build": float(build.mean()), "query": q_alone},
+        "serial_ms_per_step": serial_ms,
+        "query_ms_in_timed_steps": float(np.mean(q_timed)),
+        "step_query_ms": q_timed,
+        "collision_rate": float(out.float().mean().item()),
+        "tuning": tuned,
+        "tuning_timed_steps": tuned_step,
+        "query_roofline": {
+            "kernel": query_kernel(G),
+            "bound": "mall",
+            "sets_bytes_note": "the forest (about 0.1 GB) sits in the 256 MB MALL",
+            "achieved_alone": alg / (q_alone * 1e-3) / 1e9,
+            "achieved_in_steps": alg / (float(np.mean(q_timed)) * 1e-3) / 1e9,
+            "traffic": traffic_from_profiles(f"{query_kernel(G)}_tabletop_traffic.json", src_hash()),
+            **work,
+        },
+    }
+    forest.close()
+    br_ms = event_ms(torch, lambda: capt.capt_bruteforce_collides(fx.contiguous(), sph, G), 1, warm=0)
+    br = capt.capt_bruteforce_collides(fx.contiguous(), sph, G)
+    res["brute"] = {"ms": br_ms, "capt_query_speedup": br_ms / q_alone, "capt_step_speedup": br_ms / ms_step,
+                    "exact": bool(torch.equal(br, out))}
+    capt.capt_set_tuning(**prev_tuning)
+    return res, fx.contiguous(), w
 
 
 def bench_batched(capt, torch, reps=5):
     import synth
+    from paper_2406_02807_amd import autotune
     w = synth.workload(3)
     cloud_off = np.concatenate([[0], np.cumsum([len(c) for c in w.cloud])])
     query_off = np.concatenate([[0], np.cumsum([len(s) for s in w.spheres])])
@@ -151,52 +535,53 @@ def bench_batched(capt, torch, reps=5):
     torch.cuda.synchronize()
     t_build = (time.perf_counter() - t0) * 1e3
     out = torch.empty(len(sph) // 60, dtype=torch.uint8, device="cuda")
-
-    def timed(fn, n):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(n):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            ts.append(a.elapsed_time(b))
-        return float(np.median(ts))
-
-    from paper_2406_02807_amd import autotune
     # one launch per cloud under the caller's shape (the single-cloud kernel's),
     # then the batched kernel under its own tuned shape; the caller's shape is
     # restored afterwards
     prev = capt.capt_get_tuning()
-    t_per = timed(lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out,
-                                             flags=capt.CAPT_PER_CLOUD), reps)
+    t_per = event_ms(torch, lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out,
+                                                       flags=capt.CAPT_PER_CLOUD), reps)
     tuned, _ = autotune.autotune(f, sph, 60, query_off=query_off)
-    t_batch = timed(lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out), reps)
+    t_batch = event_ms(torch, lambda: capt.capt_collides(f, sph, 60, query_off=query_off, out=out), reps)
     res_batch = out.clone()
     capt.capt_set_tuning(**prev)
-    t_brute = timed(lambda: capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off,
-                                                          query_off=query_off), 1)
+    t_brute = event_ms(torch, lambda: capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off,
+                                                                    query_off=query_off), 1, warm=0)
     br = capt.capt_bruteforce_collides(xyz, sph, 60, cloud_off=cloud_off, query_off=query_off)
     exact = bool(torch.equal(br, res_batch))
     m = len(sph)
+    # the batched query's algorithmic bytes and the gather yardstick on its pattern
+    work, (leaf, ms, mask) = query_work(capt, torch, f, sph, 60, query_off=query_off)
+    sizes = [set_sizes(capt, f, c)[0] for c in range(len(w.cloud))]
+    base = np.concatenate([[0], np.cumsum([len(a) for a in sizes])[:-1]])
+    cloud_of = torch.repeat_interleave(torch.arange(len(w.cloud), device="cuda"),
+                                       torch.from_numpy(np.diff(query_off)).cuda())
+    g_ms, g_lpi, g_bytes = gather_yardstick(capt, torch, sizes, torch.from_numpy(base).cuda()[cloud_of], leaf, ms,
+                                            mask)
+    achieved = work["algorithmic_bytes_per_launch"] / (t_batch * 1e-3) / 1e9
     f.close()
     return {
         "workload": "64 clouds of 1e3-2e5 points (log-uniform), 1e4-2e6 spheres each in 60-sphere "
                     "configurations, r_min = 0.015, r_max = 0.08",
         "spheres": m,
+        "configurations": m // 60,
         "cloud_points": int(cloud_off[-1]),
         "build_ms": t_build,
         "batched_ms": t_batch,
         "per_cloud_ms": t_per,
         "brute_per_cloud_ms": t_brute,
-        "batched_queries_per_s": m / (t_batch * 1e-3),
+        "batched_configurations_per_s": (m // 60) / (t_batch * 1e-3),
+        "batched_sphere_queries_per_s_nominal": m / (t_batch * 1e-3),
         "speedup_vs_brute": t_brute / t_batch,
+        "speedup_vs_brute_target": 50.0,
         "speedup_vs_per_cloud_launch": t_per / t_batch,
         "exact_vs_brute": exact,
         "tuning": tuned,
+        "achieved_gbs": achieved,
+        "gather_gbs": g_bytes / (g_ms * 1e-3) / 1e9,
+        "gather_frac": achieved / (g_bytes / (g_ms * 1e-3) / 1e9),
+        "gather_lanes_per_item": g_lpi,
+        **work,
     }
 
 
@@ -231,59 +616,29 @@ def bench_clearance(capt, torch, pts_dev, reps=5):
     }
 
 
-def bench_indexed(capt, torch, reps=5):
+def bench_indexed(capt, torch, room_pts, room_spheres, r_min, r_max, reps=5):
     """Indexed affordance sets (point indices only) against plain sets on the
-    room scene (1.2M points filtered at 5 mm, r_max = 0.1 m): forest bytes and
-    the time of 10,000,000 single-sphere queries, with equal answers, and of
-    all 100,000,000 queries of the workload on the plain forest.  Then
-    the same forest as 4 shards (the subtrees of the depth-2 nodes) built and
-    queried one after the other: bytes, build and query time per shard, and
-    the OR of the shards' answers against the whole forest's."""
-    import synth
-    w = synth.workload(5)
-    xyz = torch.from_numpy(w.cloud).cuda()
-    sph = torch.from_numpy(w.spheres[:10_000_000]).cuda()
-    fx, _ = capt.capt_filter(xyz, w.r_filter)
+    room forest: bytes and the time of 10,000,000 single-sphere queries, with
+    equal answers; then the same forest as 4 shards (the subtrees of the
+    depth-2 nodes) built and queried one after the other: bytes, build and
+    query time per shard, and the OR of the shards' answers against the whole
+    forest's."""
+    sph = room_spheres[:10_000_000]
 
-    def timed(fn, n):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(n):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            ts.append(a.elapsed_time(b))
-        return float(np.median(ts))
-
-    rows = {}
-    outs = {}
     def build(**kw):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max, **kw)
+        f = capt.capt_build(room_pts, r_min, r_max, **kw)
         torch.cuda.synchronize()
         return f, (time.perf_counter() - t0) * 1e3
 
+    rows, outs = {}, {}
     for name, ix in (("plain", False), ("indexed", True)):
         f, rows[name + "_build_ms"] = build(indexed=ix)
         out = capt.capt_collides(f, sph, 1)
-        torch.cuda.synchronize()
-        rows[name + "_ms"] = timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps)
+        rows[name + "_ms"] = event_ms(torch, lambda: capt.capt_collides(f, sph, 1, out=out), reps)
         rows[name + "_bytes"] = int(f.info()["bytes"])
         outs[name] = out.clone()
-        if not ix:
-            # the whole 100,000,000-sphere query set of the room workload
-            full = torch.from_numpy(w.spheres).cuda()
-            out_full = torch.empty(len(full), dtype=torch.uint8, device="cuda")
-            ms = timed(lambda: capt.capt_collides(f, full, 1, out=out_full), 3)
-            rows["full_queries"] = int(len(full))
-            rows["full_query_ms"] = ms
-            rows["full_queries_per_s"] = len(full) / (ms * 1e-3)
-            rows["full_first_10m_agree"] = bool(torch.equal(out_full[:len(sph)], out))
-            del full, out_full
         f.close()
     rows["same_answers"] = bool(torch.equal(outs["plain"], outs["indexed"]))
     bits = 2
@@ -292,45 +647,42 @@ def bench_indexed(capt, torch, reps=5):
     for k in range(2 ** bits):
         f, ms = build(shard=(bits, k))
         out = capt.capt_collides(f, sph, 1)
-        sh["query_ms"].append(timed(lambda: capt.capt_collides(f, sph, 1, out=out), reps))
+        sh["query_ms"].append(event_ms(torch, lambda: capt.capt_collides(f, sph, 1, out=out), reps))
         sh["build_ms"].append(ms)
         sh["bytes"].append(int(f.info()["bytes"]))
         acc |= out
         f.close()
     sh["same_answers_or"] = bool(torch.equal(acc, outs["plain"]))
     rows["shards_4"] = sh
-    rows["workload"] = ("room scene, 1.2M points -> 5 mm filter, r_max = 0.1, 10,000,000 single-sphere queries "
-                        "(full_*: all 100,000,000)")
+    rows["workload"] = "room forest (5 mm filter, r_max = 0.1), the first 10,000,000 single-sphere queries"
     return rows
+
+
+def pose_on_gpu(torch, tmpl, poses):
+    """Sphere k of configuration c: ((R0 x + R1 y) + R2 z) + t0 (likewise y, z),
+    every product and sum a separate float32 operation, radius unchanged."""
+    P = poses.view(-1, 1, 12)
+    x, y, z = tmpl[None, :, 0], tmpl[None, :, 1], tmpl[None, :, 2]
+    cols = []
+    for a in range(3):
+        r0, r1, r2, t = P[..., 3 * a], P[..., 3 * a + 1], P[..., 3 * a + 2], P[..., 9 + a]
+        cols.append(((r0 * x + r1 * y) + r2 * z) + t)
+    r = tmpl[None, :, 3].expand(P.shape[0], -1)
+    return torch.stack(cols + [r], -1).reshape(-1, 4).contiguous()
 
 
 def bench_posed(capt, torch, forest, reps=5):
     """Motion-edge validation: 100,000 edges of 10 rigid poses of the 60-sphere
     template (translation within 0.4 m, rotation by slerp) on the tabletop
-    forest, posed on the fly (48 B per configuration), against the same
-    spheres materialised (960 B per configuration), answers compared."""
-    import oracle
+    forest, posed inside the query kernel (48 B per configuration), against
+    the same spheres materialised on the GPU (960 B per configuration)."""
     import synth
     tmpl = synth.chain_template(2003).astype(np.float32)
     steps, n_edges = 10, 100_000
     poses = synth.pose_edges(n_edges, steps, synth.WORKSPACE, 8002)
-    sph = torch.from_numpy(oracle.pose_spheres(tmpl, poses)).cuda()
     pd, td = torch.from_numpy(poses).cuda(), torch.from_numpy(tmpl).cuda()
+    sph = pose_on_gpu(torch, td, pd)
     G = steps * len(tmpl)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            ts.append(a.elapsed_time(b))
-        return float(np.median(ts))
-
     # the project autotuner picks this workload's launch shape (posing the
     # spheres in the kernel shifts the balance of the slot kernel); both forms
     # are timed under it and the caller's shape is restored afterwards
@@ -339,10 +691,11 @@ def bench_posed(capt, torch, forest, reps=5):
     out = torch.empty(n_edges, dtype=torch.uint8, device="cuda")
     tuned, _ = autotune.autotune_step(lambda: capt.capt_collides_posed(forest, td, pd, steps, out=out),
                                       lambda: out)
-    t_posed = timed(lambda: capt.capt_collides_posed(forest, td, pd, steps))
-    t_mat = timed(lambda: capt.capt_collides(forest, sph, G))
-    same = bool(torch.equal(capt.capt_collides_posed(forest, td, pd, steps), capt.capt_collides(forest, sph, G)))
-    hit = capt.capt_collides_posed(forest, td, pd, steps).float().mean().item()
+    t_posed = event_ms(torch, lambda: capt.capt_collides_posed(forest, td, pd, steps), reps)
+    t_mat = event_ms(torch, lambda: capt.capt_collides(forest, sph, G), reps)
+    a = capt.capt_collides_posed(forest, td, pd, steps)
+    same = bool(torch.equal(a, capt.capt_collides(forest, sph, G)))
+    hit = a.float().mean().item()
     capt.capt_set_tuning(**prev)
     return {"workload": "tabletop forest; 100,000 motion edges x 10 rigid poses of the 60-sphere template",
             "edges": n_edges, "configurations": n_edges * steps, "edge_collision_rate": hit,
@@ -378,7 +731,6 @@ def bench_frame(capt, torch, reps=10):
             tb.append(b.elapsed_time(c))
             info = f.info()
             f.close()
-        # the same frame through the one-call filter + build
         tfu = []
         for _ in range(reps):
             t0 = time.perf_counter()
@@ -401,16 +753,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=200_000, help="configurations timed on the CPU")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="CPU time per oracle leg")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all", metavar="LIST",
                     help="comma-separated extras to run (" + ", ".join(EXTRAS) + "), or all")
-    ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--brute-sample", type=int, default=1_000_000, help="spheres of the GPU brute-force leg")
     ap.add_argument("--tune-query", default=None, metavar="JSON",
-                    help="launch shape for the serial frames instead of autotuning (e.g. for profiling)")
-    ap.add_argument("--tune-steps", default=None, metavar="JSON",
-                    help="launch shape for the timed steps instead of autotuning")
+                    help="launch shape of the room query instead of autotuning (e.g. for profiling)")
+    ap.add_argument("--query-only", action="store_true",
+                    help="only the room's filter, build and timed steps (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -435,227 +787,82 @@ def main():
     import torch
 
     import paper_2406_02807_amd as capt
-    import synth
 
     capt.load_library()
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    t0 = time.perf_counter()
-    w = synth.workload(2)
-    G = w.group
-    log(f"generated workload in {time.perf_counter() - t0:.1f} s: {len(w.cloud)} points, "
-        f"{len(w.spheres)} spheres")
-    xyz = torch.from_numpy(w.cloud).cuda()
-    sph = torch.from_numpy(w.spheres).cuda()
-    out = torch.empty(len(w.spheres) // G, dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
 
-    def step(ev=None):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if ev is not None else None
-        if e:
-            e[0].record()
-        fx, _ = capt.capt_filter(xyz, w.r_filter)
-        if e:
-            e[1].record()
-        f = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
-        if e:
-            e[2].record()
-        capt.capt_collides(f, sph, G, out=out)
-        if e:
-            e[3].record()
-            ev.append(e)
-        return f, fx
-
-    # launch shape from the project autotuner, on this workload, before timing
-    from paper_2406_02807_amd import autotune
-    f, fx = step()
-    if args.tune_query:
-        tuned = json.loads(args.tune_query)
-        capt.capt_set_tuning(**tuned)
-    else:
-        tuned, _ = autotune.autotune(f, sph, G)
-    f.close()
-    log(f"tuning: {tuned}")
-    for _ in range(args.warmup):
-        f, fx = step()
-        f.release()
-    torch.cuda.synchronize()
-
-    # serial frames: filter -> build -> query, one after the other on one
-    # stream; gives the per-phase times and the latency of one frame
-    events = []
-    forest = None
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        f, fx = step(events)
-        if forest is not None:
-            forest.release()
-        forest = f
-    torch.cuda.synchronize()
-    serial_ms = (time.perf_counter() - t_start) / args.steps * 1e3
-    forest.close()
-    filt = np.array([a.elapsed_time(b) for a, b, _, _ in events])
-    build = np.array([b.elapsed_time(c) for _, b, c, _ in events])
-    query = np.array([c.elapsed_time(d) for _, _, c, d in events])
-
-    # double-buffered frames (the timed steps): frame k+1 is filtered and
-    # built on one stream while frame k's configurations are queried on
-    # another; every frame still runs the whole path
-    s_query, s_build = torch.cuda.Stream(), torch.cuda.Stream()
-
-    def piped_step(prev, qev=None):
-        with torch.cuda.stream(s_build):
-            f = capt.capt_build_filtered(xyz, w.r_filter, w.r_min, w.r_max)
-            ready = torch.cuda.Event()
-            ready.record(s_build)
-        s_query.wait_event(ready)
-        with torch.cuda.stream(s_query):
-            if qev is not None:
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-                e[0].record(s_query)
-            capt.capt_collides(f, sph, G, out=out)
-            if qev is not None:
-                e[1].record(s_query)
-                qev.append(e)
-            if prev is not None:
-                prev.release()
-        return f
-
-    def piped_frames(k):
-        f = None
-        for _ in range(k):
-            f = piped_step(f)
-        with torch.cuda.stream(s_query):
-            f.release()
-
-    # launch shape for these steps: the query shares the chip with the next
-    # frame's build, so the best shape is tuned on the steps themselves
-    if args.tune_steps:
-        tuned_step = json.loads(args.tune_steps)
-        capt.capt_set_tuning(**tuned_step)
-    else:
-        tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
-    log(f"tuning for the double-buffered steps: {tuned_step}")
-    forest = None
-    for _ in range(args.warmup):
-        forest = piped_step(forest)
-    torch.cuda.synchronize()
-    out.zero_()
-    torch.cuda.synchronize()
-    qev = []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        forest = piped_step(forest, qev)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ms_step = t_total / args.steps * 1e3
-    m = len(w.spheres)
-    value = m / (t_total / args.steps)
-    # the query kernel's duration inside the timed steps, from events on the
-    # stream it runs on (it shares the chip with the next frame's build)
-    q_timed = np.array([a.elapsed_time(b) for a, b in qev])
-
-    info = forest.info()
-    alg_bytes, alg = algorithmic_bytes(capt, forest, sph, G)
-    q_ms = float(q_timed.mean())
-    q_alone_ms = float(query.mean())
-    achieved = alg_bytes / (q_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(query_kernel(G), src_hash())
+    if args.query_only:
+        args.no_extras, args.no_cpu = True, True
+    room, f, blob, w, out, room_pts = bench_room(capt, torch, args)
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": room.pop("value"),
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": room.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "tabletop-50k: 50,000 points on 24 boxes + 8 cylinders (2 mm noise) -> Morton "
-                        "filter r_filter = 0.01 -> CAPT r_min = 0.015, r_max = 0.08 -> 1,000,000 "
-                        "configurations x 60 spheres, one bool per configuration",
-            "points_in": len(w.cloud),
-            "points_after_filter": int(fx.shape[0]),
-            "tree_depth": info["D"],
-            "set_entries": info["set_total"],
-            "spheres": m,
-            "configurations": m // G,
-        },
-        "ns_per_query": ms_step * 1e6 / m,
-        "phase_ms": {"filter": float(filt.mean()), "build": float(build.mean()), "query": q_alone_ms},
-        "serial_ms_per_step": serial_ms,
-        "query_ms_in_timed_steps": q_ms,
-        "query_only_queries_per_s": m / (q_alone_ms * 1e-3),
-        "collision_rate": float(out.float().mean().item()),
-        "tuning": tuned,
-        "tuning_timed_steps": tuned_step,
-        "roofline": {
-            "kernel": query_kernel(G),
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "achieved_query_alone": alg_bytes / (q_alone_ms * 1e-3) / 1e9,
-            "frac_query_alone": alg_bytes / (q_alone_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes,
-            **alg,
-        },
     }
-    log(f"step {ms_step:.2f} ms double-buffered, {serial_ms:.2f} ms serial: filter {filt.mean():.2f}, "
-        f"build {build.mean():.2f}, query {q_alone_ms:.2f} alone, {q_ms:.2f} in the timed steps")
+    result.update(room)
 
-    if not args.no_brute:
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        br = capt.capt_bruteforce_collides(fx.contiguous(), sph, G)
-        b.record()
-        torch.cuda.synchronize()
-        tb = a.elapsed_time(b)
-        result["brute"] = {
-            "ms": tb,
-            "queries_per_s": m / (tb * 1e-3),
-            "capt_query_speedup": tb / q_alone_ms,
-            "capt_step_speedup": tb / ms_step,
-            "exact": bool(torch.equal(br, out)),
-        }
-        log(f"brute force {tb:.1f} ms, exact {result['brute']['exact']}")
-    forest.close()
+    if args.query_only:
+        f.close()
+        print(json.dumps(result))
+        return
+    if not args.no_cpu:
+        cb, agree = cpu_baseline_room(blob, w.spheres, out, args.cpu_seconds)
+        result["cpu_baseline"] = cb
+        result["cpu_baseline_agrees"] = agree
+        log(f"cpu baseline {cb['value']:.3g} queries/s on {cb['cores']} threads, "
+            f"{cb['single_thread_ns_per_query']:.1f} ns/query on one")
+    del blob
 
     extras = set(EXTRAS if args.extras == "all" else args.extras.split(","))
     if args.no_extras:
         extras = set()
-    capt.capt_set_tuning(**tuned)   # the extras run under the query's own tuned shape
+    room_tuning = capt.capt_get_tuning()
+    if "indexed_sets" in extras:
+        sph = torch.from_numpy(w.spheres[:10_000_000]).cuda()
+        f.close()
+        result["indexed_sets"] = bench_indexed(capt, torch, room_pts, sph, w.r_min, w.r_max)
+        log(f"indexed sets: {result['indexed_sets']}")
+        del sph
+    else:
+        f.close()
+    del w, out, room_pts
+    torch.cuda.empty_cache()
+    tab_pts = None
+    if "tabletop" in extras:
+        tt, tab_pts, _ = bench_tabletop(capt, torch, args)
+        result["tabletop"] = tt
+        log(f"tabletop: {tt['ms_per_step']:.2f} ms per double-buffered step, "
+            f"{tt['configurations_per_s']:.3g} configurations/s")
+    elif extras & {"clearance", "posed"}:
+        import synth
+        w2 = synth.workload(2, scale=1e-6)
+        tab_pts = capt.capt_filter(torch.from_numpy(w2.cloud).cuda(), w2.r_filter)[0].contiguous()
+    capt.capt_set_tuning(**room_tuning)
     if "batched" in extras:
         result["batched"] = bench_batched(capt, torch)
         log(f"batched: {result['batched']}")
     if "clearance" in extras:
-        result["clearance"] = bench_clearance(capt, torch, fx.contiguous())
+        result["clearance"] = bench_clearance(capt, torch, tab_pts)
         log(f"clearance: {result['clearance']}")
     if "frame" in extras:
         result["frame"] = bench_frame(capt, torch)
         log(f"frame: {result['frame']}")
     if "posed" in extras:
-        f_posed = capt.capt_build(fx.contiguous(), w.r_min, w.r_max)
+        f_posed = capt.capt_build(tab_pts, 0.015, 0.08)   # the tabletop forest
         result["posed"] = bench_posed(capt, torch, f_posed)
         f_posed.close()
         log(f"posed: {result['posed']}")
-    if "indexed_sets" in extras:
-        result["indexed_sets"] = bench_indexed(capt, torch)
-        log(f"indexed sets: {result['indexed_sets']}")
-
-    if not args.no_cpu:
-        cb, ref = cpu_baseline(w, G, min(args.cpu_sample, m // G))
-        result["cpu_baseline"] = cb
-        result["cpu_baseline_agrees"] = bool(np.array_equal(ref, out[: len(ref)].cpu().numpy()))
-        log(f"cpu baseline {cb['value']:.3g} queries/s")
     print(json.dumps(result))
 
 

@@ -434,6 +434,36 @@ typedef struct {
 capt_status capt_set_tuning(const capt_tuning *t);
 capt_status capt_get_tuning(capt_tuning *t);
 
+/*
+ * Achievable-bandwidth yardsticks (measurement only, not the hot path).  The
+ * benchmark divides a query's algorithmic bytes by what these reach, to state
+ * how close the query runs to the memory roofline it can actually attain.
+ *
+ * capt_probe_read: every lane reads the buffer's float4s in a grid-stride
+ * loop, `passes` times over the whole buffer (bytes / 16 float4s; a tail
+ * below 16 bytes is not read).  A buffer far larger than the caches measures
+ * HBM; one that fits the L2 (4 MB per XCD) or the MALL measures that level.
+ *   buf     device, any alignment of 16 bytes
+ *   sink    device [1] float; written only if the loads sum to -1
+ *
+ * capt_probe_gather: the collision query's memory pattern without its
+ * arithmetic.  Item k (16 bytes, int32 leaf, len, unused, unused) reads
+ * leaves[leaf] (32 bytes: float lo[3], hi[3], uint32 start, uint32 count),
+ * then entries start .. start + min(len, count) - 1 of x, y and z, and writes
+ * out[k] (1 iff the sum of the loads is -1).  Items whose leaf is outside
+ * [0, nleaf) read nothing past their descriptor; runs are cut at `entries`.
+ *   items          device [m][4] int32
+ *   leaves         device [nleaf] records as above
+ *   x, y, z        device [entries] float32
+ *   lanes_per_item 16 or 64: the lanes that share one item's run
+ *   out            device [m] bytes
+ * Both are asynchronous on `stream`; CAPT_EINVAL on bad arguments.
+ */
+capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, void *stream);
+capt_status capt_probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf,
+                              const float *x, const float *y, const float *z, int64_t entries,
+                              int32_t lanes_per_item, uint8_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ def _load():
             "orc_morton_cell": (None, [P, P, C.c_double, P]),
             "orc_filter": (i64, [P, i64, f32, C.c_int, P, P]),
             "orc_prunable": (C.c_int, [P, P, f32]),
+            "orc_set_threads": (None, [i32]),
+            "orc_max_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -279,6 +281,15 @@ def query_serial(N: int, D: int, T, aabb, off, setxyz, spheres, group: int, axes
                              _p(setxyz) if len(setxyz) else None, _p(sph), len(sph),
                              group, _p(out), _p(_axes(axes)))
     return out
+
+
+def set_threads(k: int) -> None:
+    """Thread count of the oracle's OpenMP loops."""
+    _load().orc_set_threads(int(k))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def morton_key(q, perm: int) -> int:

@@ -37,11 +37,17 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_API __attribute__((visibility("default")))
+
+/* Thread count of the OpenMP loops (the benchmark times the query on one
+ * thread and on all host cores). */
+ORC_API void orc_set_threads(int32_t k) { omp_set_num_threads(k > 0 ? k : 1); }
+ORC_API int32_t orc_max_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------- */
 /* The float32 sphere-point predicate (Alg. 3, "||x - p|| <= r").            */

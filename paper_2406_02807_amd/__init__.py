@@ -34,7 +34,7 @@ EXPORTS = [
     "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
-    "capt_get_tuning",
+    "capt_get_tuning", "capt_probe_read", "capt_probe_gather",
 ]
 
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         "capt_collides_posed": [P, P, i32, P, P, i32, P, u32, P],
         "capt_set_tuning": [P],
         "capt_get_tuning": [P],
+        "capt_probe_read": [P, C.c_size_t, i32, P, P],
+        "capt_probe_gather": [P, i64, P, i64, P, P, P, i64, i32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -422,6 +424,37 @@ def capt_query_chunk_stats(forest: Forest, spheres, query_off=None, stream=None)
     _check(lib.capt_query_chunk_stats(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p),
                                       _ptr(boxes), _ptr(chunks), _stream(stream)))
     return boxes, chunks
+
+
+def capt_probe_read(buf, passes: int = 1, stream=None):
+    """Stream-read a device tensor `passes` times (bandwidth yardstick)."""
+    import torch
+    lib = load_library()
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("buf must be a contiguous CUDA tensor")
+    sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
+    _check(lib.capt_probe_read(_ptr(buf), buf.numel() * buf.element_size(), passes, _ptr(sink), _stream(stream)))
+    return sink
+
+
+def capt_probe_gather(items, leaves, x, y, z, lanes_per_item: int = 16, out=None, stream=None):
+    """The query's gather pattern without its arithmetic (bandwidth yardstick):
+    items int32 [m, 4] (leaf, len, -, -), leaves int32 [nleaf, 8] records
+    (float lo[3], hi[3] as bits, uint32 start, count), x, y, z float32 [entries]."""
+    import torch
+    lib = load_library()
+    items = _dev(items, torch.int32, 4, "items")
+    leaves = _dev(leaves, torch.int32, 8, "leaves")
+    for name, t in (("x", x), ("y", y), ("z", z)):
+        _dev(t, torch.float32, None, name)
+    if not (x.numel() == y.numel() == z.numel()):
+        raise ValueError("x, y and z must have the same length")
+    m = items.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.uint8, device=items.device)
+    _check(lib.capt_probe_gather(_ptr(items), m, _ptr(leaves), leaves.shape[0], _ptr(x), _ptr(y), _ptr(z),
+                                 x.numel(), lanes_per_item, _ptr(out), _stream(stream)))
+    return out
 
 
 def capt_set_tuning(waves_per_group=0, groups_per_cu=0, tile_cfgs=0, lds_levels=0, scan_unroll=0):

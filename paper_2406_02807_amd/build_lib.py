@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcapt.so")
-SOURCES = ["api.hip", "primitives.hip", "build.hip", "query.hip", "clearance.hip", "filter.hip"]
+SOURCES = ["api.hip", "primitives.hip", "build.hip", "query.hip", "clearance.hip", "filter.hip", "probe.hip"]
 ARCH = os.environ.get("CAPT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -993,4 +993,46 @@ capt_status capt_query_chunk_stats(capt_forest f, const float *spheres, const in
     return chunk_stats(f, spheres, query_off, boxes, chunks, (hipStream_t)stream);
 }
 
+
+capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, void *stream) {
+    ApiGuard g;
+    if (bytes >= 16 && (!buf || !sink)) {
+        set_error("buf and sink must be set");
+        return CAPT_EINVAL;
+    }
+    if (passes < 0) {
+        set_error("passes = %d is negative", passes);
+        return CAPT_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(buf) % 16) {
+        set_error("buf is not 16-byte aligned");
+        return CAPT_EINVAL;
+    }
+    return probe_read(buf, bytes, passes, sink, (hipStream_t)stream);
+}
+
+capt_status capt_probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf, const float *x,
+                              const float *y, const float *z, int64_t entries, int32_t lanes_per_item, uint8_t *out,
+                              void *stream) {
+    ApiGuard g;
+    if (m < 0 || nleaf < 0 || entries < 0) {
+        set_error("negative size");
+        return CAPT_EINVAL;
+    }
+    if (lanes_per_item != 16 && lanes_per_item != 64) {
+        set_error("lanes_per_item = %d, expected 16 or 64", lanes_per_item);
+        return CAPT_EINVAL;
+    }
+    if (m > 0 && (!items || !out || (nleaf > 0 && !leaves) || (entries > 0 && (!x || !y || !z)))) {
+        set_error("a buffer is NULL");
+        return CAPT_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(items) % 16 || reinterpret_cast<uintptr_t>(leaves) % 16) {
+        set_error("items and leaves must be 16-byte aligned");
+        return CAPT_EINVAL;
+    }
+    if (m == 0) return CAPT_OK;
+    return probe_gather(items, m, leaves, nleaf, x, y, z, entries, lanes_per_item, out, (hipStream_t)stream);
+}
+
 }  // extern "C"
