@@ -152,8 +152,11 @@ def read_yardsticks(capt, torch):
     for name, size, passes in (("hbm_stream_read", 4 << 30, 1), ("l2_reread", 16 << 20, 256),
                                ("mall_reread", 128 << 20, 32)):
         buf = torch.ones(size // 4, dtype=torch.float32, device="cuda")
-        t = event_ms(torch, lambda: capt.capt_probe_read(buf, passes), 5)
-        res[name + "_gbs"] = size * passes / (t * 1e-3) / 1e9
+        best = 0.0
+        for bpc in (2, 4, 8, 16):   # the best launch shape of each level
+            t = event_ms(torch, lambda: capt.capt_probe_read(buf, passes, bpc), 5)
+            best = max(best, size * passes / (t * 1e-3) / 1e9)
+        res[name + "_gbs"] = best
         del buf
     return res
 

@@ -76,8 +76,10 @@ typedef int32_t capt_status;
  *              order, bitwise equal to the input coordinates
  *   out_index  [n] capacity or NULL; original index of each kept point
  *   n_out      host; number of kept points
- * Synchronises on `stream` once at the end to read n_out.  Scratch memory is
- * taken from the allocator (capt_set_allocator) and released before return.
+ * n must be below 2^30 (CAPT_EUNSUPPORTED otherwise).  Synchronises on
+ * `stream` once at the end to read n_out.  Scratch memory is taken from the
+ * allocator (capt_set_allocator) and released before return.  A pass costs
+ * time linear in n whatever runs of coincident points the cloud holds.
  */
 capt_status capt_filter(const float *xyz, int64_t n, float r_filter,
                         float *out_xyz, int32_t *out_index, int64_t *n_out,
@@ -439,12 +441,14 @@ capt_status capt_get_tuning(capt_tuning *t);
  * benchmark divides a query's algorithmic bytes by what these reach, to state
  * how close the query runs to the memory roofline it can actually attain.
  *
- * capt_probe_read: every lane reads the buffer's float4s in a grid-stride
- * loop, `passes` times over the whole buffer (bytes / 16 float4s; a tail
- * below 16 bytes is not read).  A buffer far larger than the caches measures
- * HBM; one that fits the L2 (4 MB per XCD) or the MALL measures that level.
- *   buf     device, any alignment of 16 bytes
- *   sink    device [1] float; written only if the loads sum to -1
+ * capt_probe_read: reads the buffer's float4s `passes` times over (bytes / 16
+ * float4s; a tail below 16 bytes is not read), each of the 8 XCDs one eighth
+ * of the buffer with blocks_per_cu x (compute units) blocks of 256 threads
+ * in all.  A buffer far larger than the caches measures HBM; one whose eighth
+ * fits an XCD's L2 (4 MB) or whose whole fits the MALL measures that level.
+ *   buf            device, 16-byte aligned
+ *   blocks_per_cu  1 .. 32
+ *   sink           device [1] float; written only if the loads sum to -1
  *
  * capt_probe_gather: the collision query's memory pattern without its
  * arithmetic.  Item k (16 bytes, int32 leaf, len, unused, unused) reads
@@ -459,7 +463,8 @@ capt_status capt_get_tuning(capt_tuning *t);
  *   out            device [m] bytes
  * Both are asynchronous on `stream`; CAPT_EINVAL on bad arguments.
  */
-capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, void *stream);
+capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, int32_t blocks_per_cu, float *sink,
+                            void *stream);
 capt_status capt_probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf,
                               const float *x, const float *y, const float *z, int64_t entries,
                               int32_t lanes_per_item, uint8_t *out, void *stream);

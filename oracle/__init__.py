@@ -20,6 +20,10 @@ Functions and what they follow:
   build_tree       Construct (Alg. 1, Sec. IV-A/B) with r_min pruning; split
                    axis d mod 3, or a given axis per depth (the alternative
                    to the cyclic rule that Sec. IV-A mentions)
+  build_splits     Construct's splits alone (T and representatives)
+  leaf_cells       every leaf's closed cell from the test sequence (Alg. 1)
+  afford_direct    the affordance set of given cells by its direct definition
+                   (Lemma 1, case 1)
   query            CollisionCheck (Alg. 3, Sec. IV-D) on a tree given as arrays
   morton_key       Z-order key (Sec. II-B, Sec. IV-C)
   filter           Filter (Alg. 2, Sec. IV-C), optionally after crop
@@ -83,6 +87,10 @@ def _load():
             "orc_filter": (i64, [P, i64, f32, C.c_int, P, P]),
             "orc_prunable": (C.c_int, [P, P, f32]),
             "orc_set_threads": (None, [i32]),
+            "orc_build_splits": (None, [P, i64, P, P, P]),
+            "orc_leaf_cells": (None, [i64, i32, P, P, P]),
+            "orc_afford_count": (None, [P, i64, P, i64, f32, P]),
+            "orc_afford_fill": (None, [P, i64, P, i64, f32, P, P]),
             "orc_max_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
@@ -215,6 +223,44 @@ def build_tree(points, r_min: float, r_max: float, prune: bool = True, axes=None
         lib.orc_tree_free(h)
     return Tree(n.value, N_, D.value, float(np.float32(r_min)), float(np.float32(r_max)),
                 T, rep, cell, aabb, pruned, off, idx[:tot.value], None if ax is None else ax[:D.value].copy())
+
+
+def build_splits(points, axes=None):
+    """Construct's splits alone (Sec. IV-A): (T float32 [N-1], rep int32 [N])."""
+    pts = _f32(points, 3)
+    n = len(pts)
+    N = 1
+    while N < n:
+        N <<= 1
+    T = np.zeros(max(N - 1, 1), dtype=np.float32)
+    rep = np.zeros(N, dtype=np.int32)
+    _load().orc_build_splits(_p(pts), n, _p(_axes(axes)), _p(T), _p(rep))
+    return T[:N - 1], rep
+
+
+def leaf_cells(N: int, D: int, T, axes=None) -> np.ndarray:
+    """Closed cell [N, 6] (lo xyz, hi xyz) of every leaf from the test sequence."""
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    cells = np.zeros((N, 6), dtype=np.float32)
+    _load().orc_leaf_cells(N, D, _p(T) if len(T) else None, _p(_axes(axes)), _p(cells))
+    return cells
+
+
+def afford_direct(points, cells, r_max: float):
+    """Lemma 1, case 1: for each cell, every point it affords at r_max
+    (float64 distance to the closed cell <= r_max (1 + 2^-20)).  Returns
+    (off int64 [k+1], idx int32 [off[k]]), members in increasing order."""
+    pts = _f32(points, 3)
+    cells = np.ascontiguousarray(cells, dtype=np.float32).reshape(-1, 6)
+    k = len(cells)
+    cnt = np.zeros(k, dtype=np.int64)
+    lib = _load()
+    lib.orc_afford_count(_p(pts), len(pts), _p(cells), k, np.float32(r_max), _p(cnt))
+    off = np.zeros(k + 1, dtype=np.int64)
+    off[1:] = np.cumsum(cnt)
+    idx = np.zeros(max(int(off[-1]), 1), dtype=np.int32)
+    lib.orc_afford_fill(_p(pts), len(pts), _p(cells), k, np.float32(r_max), _p(off), _p(idx))
+    return off, idx[:off[-1]]
 
 
 def query(N: int, D: int, T, aabb, off, setxyz, spheres, axes=None):

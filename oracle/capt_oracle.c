@@ -198,7 +198,10 @@ typedef struct {
     int32_t **sets;        /* [N] sorted original indices */
     int64_t *off;          /* [N+1] after finalisation */
     int32_t *idx;          /* flattened sets */
+    int no_sets;           /* splits only: no affordance sets, AABBs or pruning */
 } orc_tree;
+
+ORC_API void orc_tree_free(orc_tree *t);
 
 static double R_afford2(float r_max)
 {
@@ -286,6 +289,10 @@ static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
         int32_t x = pc[0];
         memcpy(t->cell + 6 * leaf, c, 6 * sizeof(float));
         t->rep[leaf] = x;
+        if (t->no_sets) {
+            t->sets[leaf] = (int32_t *)malloc(sizeof(int32_t));
+            return;
+        }
         int real = x < t->n;
         int pr = real && t->prune && prunable(c, point(t, x), t->r_min);
         int64_t k = 0;
@@ -323,15 +330,15 @@ static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
     c2[d] = Ti;       /* raise the lower bound of c2 */
     /* z1 = {p in z u B2 : c1 affords p}, z2 = {p in z u B1 : c2 affords p};
      * padding points are never afforded. */
-    int32_t *z1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nz + h + 1));
-    int32_t *z2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nz + h + 1));
+    int32_t *z1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(t->no_sets ? 1 : nz + h + 1));
+    int32_t *z2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(t->no_sets ? 1 : nz + h + 1));
     int64_t n1 = 0, n2 = 0;
     for (int64_t j = 0; j < nz; ++j) {
         const float *p = point(t, z[j]);
         if (affords(c1, p, R2)) z1[n1++] = z[j];
         if (affords(c2, p, R2)) z2[n2++] = z[j];
     }
-    for (int64_t j = 0; j < h; ++j) {
+    for (int64_t j = 0; j < h && !t->no_sets; ++j) {
         if (B2[j] < t->n && affords(c1, point(t, B2[j]), R2)) z1[n1++] = B2[j];
         if (B1[j] < t->n && affords(c2, point(t, B1[j]), R2)) z2[n2++] = B1[j];
     }
@@ -346,10 +353,11 @@ static void construct(orc_tree *t, int32_t *pc, int64_t m, float c[6],
  * cyclic rule d mod 3 of Sec. IV-A (the paper names a random choice of axis
  * as an alternative; here a sequence of axes per depth keeps the tree
  * implicit). */
-ORC_API orc_tree *orc_build(const float *pts, int64_t n, float r_min, float r_max, int prune,
-                            const uint8_t *axes)
+static orc_tree *build(const float *pts, int64_t n, float r_min, float r_max, int prune,
+                       const uint8_t *axes, int no_sets)
 {
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
+    t->no_sets = no_sets;
     int64_t N = 1;
     int D = 0;
     while (N < n) { N <<= 1; ++D; }
@@ -387,6 +395,73 @@ ORC_API orc_tree *orc_build(const float *pts, int64_t n, float r_min, float r_ma
     free(t->sets);
     t->sets = NULL;
     return t;
+}
+
+ORC_API orc_tree *orc_build(const float *pts, int64_t n, float r_min, float r_max, int prune,
+                            const uint8_t *axes)
+{
+    return build(pts, n, r_min, r_max, prune, axes, 0);
+}
+
+/* Construct's splits alone (Sec. IV-A): T and the representative of every
+ * leaf, without affordance sets; the same recursion as orc_build. */
+ORC_API void orc_build_splits(const float *pts, int64_t n, const uint8_t *axes, float *T, int32_t *rep)
+{
+    orc_tree *t = build(pts, n, 0.0f, 1.0f, 0, axes, 1);
+    if (T && t->N > 1) memcpy(T, t->T, sizeof(float) * (size_t)(t->N - 1));
+    if (rep) memcpy(rep, t->rep, sizeof(int32_t) * (size_t)t->N);
+    orc_tree_free(t);
+}
+
+/* The closed cell of every leaf from the test sequence alone (Alg. 1: a
+ * left descent at node i caps the cell at T_i on the node's axis, a right
+ * descent raises its lower bound to T_i; bounds never met stay infinite).
+ * Leaf l is reached by the bits of l, most significant first, 1 = right. */
+ORC_API void orc_leaf_cells(int64_t N, int32_t D, const float *T, const uint8_t *axes, float *cells)
+{
+    for (int64_t l = 0; l < N; ++l) {
+        float c[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+        int64_t i = 0;
+        for (int d = 0; d < D; ++d) {
+            const int a = axes ? axes[d] : d % 3;
+            if ((l >> (D - 1 - d)) & 1) {
+                c[a] = T[i];
+                i = 2 * i + 2;
+            } else {
+                c[3 + a] = T[i];
+                i = 2 * i + 1;
+            }
+        }
+        memcpy(cells + 6 * l, c, sizeof c);
+    }
+}
+
+/* Lemma 1, case 1, written out: the affordance set of a closed cell is every
+ * real point it affords at r_max, the set Construct's incremental z reaches.
+ * orc_afford_count gives the size for each of k cells, orc_afford_fill the
+ * members in increasing index order at the caller's offsets. */
+ORC_API void orc_afford_count(const float *pts, int64_t n, const float *cells, int64_t k, float r_max,
+                              int64_t *cnt)
+{
+    const double R2 = R_afford2(r_max);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t l = 0; l < k; ++l) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) c += affords(cells + 6 * l, pts + 3 * j, R2);
+        cnt[l] = c;
+    }
+}
+
+ORC_API void orc_afford_fill(const float *pts, int64_t n, const float *cells, int64_t k, float r_max,
+                             const int64_t *off, int32_t *idx)
+{
+    const double R2 = R_afford2(r_max);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t l = 0; l < k; ++l) {
+        int64_t c = off[l];
+        for (int64_t j = 0; j < n; ++j)
+            if (affords(cells + 6 * l, pts + 3 * j, R2)) idx[c++] = (int32_t)j;
+    }
 }
 
 ORC_API void orc_tree_dims(const orc_tree *t, int64_t *n, int64_t *N, int32_t *D, int64_t *total)

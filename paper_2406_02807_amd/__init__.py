@@ -84,7 +84,7 @@ def load_library(path: str = LIB_PATH):
         "capt_collides_posed": [P, P, i32, P, P, i32, P, u32, P],
         "capt_set_tuning": [P],
         "capt_get_tuning": [P],
-        "capt_probe_read": [P, C.c_size_t, i32, P, P],
+        "capt_probe_read": [P, C.c_size_t, i32, i32, P, P],
         "capt_probe_gather": [P, i64, P, i64, P, P, P, i64, i32, P, P],
     }
     for name, args in sig.items():
@@ -426,14 +426,15 @@ def capt_query_chunk_stats(forest: Forest, spheres, query_off=None, stream=None)
     return boxes, chunks
 
 
-def capt_probe_read(buf, passes: int = 1, stream=None):
+def capt_probe_read(buf, passes: int = 1, blocks_per_cu: int = 2, stream=None):
     """Stream-read a device tensor `passes` times (bandwidth yardstick)."""
     import torch
     lib = load_library()
     if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
         raise TypeError("buf must be a contiguous CUDA tensor")
     sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
-    _check(lib.capt_probe_read(_ptr(buf), buf.numel() * buf.element_size(), passes, _ptr(sink), _stream(stream)))
+    _check(lib.capt_probe_read(_ptr(buf), buf.numel() * buf.element_size(), passes, blocks_per_cu, _ptr(sink),
+                               _stream(stream)))
     return sink
 
 

@@ -368,8 +368,8 @@ capt_status capt_filter(const float *xyz, int64_t n, float r_filter, float *out_
         set_error("r_filter = %g must be finite and >= 0", (double)r_filter);
         return CAPT_EINVAL;
     }
-    if (n >= ((int64_t)1 << 31)) {
-        set_error("cloud of %lld points exceeds 2^31", (long long)n);
+    if (n >= ((int64_t)1 << 30)) {
+        set_error("cloud of %lld points reaches 2^30", (long long)n);
         return CAPT_EUNSUPPORTED;
     }
     return filter(xyz, n, r_filter, nullptr, out_xyz, out_index, n_out, (hipStream_t)stream);
@@ -520,7 +520,7 @@ capt_status capt_build_filtered(const float *xyz, int64_t n, float r_filter, con
         capt_status cs = check_crop(crop);
         if (cs) return cs;
     }
-    if (n >= ((int64_t)1 << (crop ? 30 : 31))) {
+    if (n >= ((int64_t)1 << 30)) {
         set_error("cloud of %lld points exceeds the filter's limit", (long long)n);
         return CAPT_EUNSUPPORTED;
     }
@@ -994,8 +994,13 @@ capt_status capt_query_chunk_stats(capt_forest f, const float *spheres, const in
 }
 
 
-capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, void *stream) {
+capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, int32_t blocks_per_cu, float *sink,
+                            void *stream) {
     ApiGuard g;
+    if (blocks_per_cu < 1 || blocks_per_cu > 32) {
+        set_error("blocks_per_cu = %d outside 1 .. 32", blocks_per_cu);
+        return CAPT_EINVAL;
+    }
     if (bytes >= 16 && (!buf || !sink)) {
         set_error("buf and sink must be set");
         return CAPT_EINVAL;
@@ -1008,7 +1013,7 @@ capt_status capt_probe_read(const void *buf, size_t bytes, int32_t passes, float
         set_error("buf is not 16-byte aligned");
         return CAPT_EINVAL;
     }
-    return probe_read(buf, bytes, passes, sink, (hipStream_t)stream);
+    return probe_read(buf, bytes, passes, blocks_per_cu, sink, (hipStream_t)stream);
 }
 
 capt_status capt_probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf, const float *x,

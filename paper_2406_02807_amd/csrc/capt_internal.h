@@ -263,7 +263,8 @@ void free_plan(BatchPlan *p);
 capt_tuning &tuning();
 
 // probe.hip
-capt_status probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, hipStream_t s);
+capt_status probe_read(const void *buf, size_t bytes, int32_t passes, int32_t blocks_per_cu, float *sink,
+                       hipStream_t s);
 capt_status probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf, const float *x,
                          const float *y, const float *z, int64_t entries, int32_t lanes_per_item, uint8_t *out,
                          hipStream_t s);

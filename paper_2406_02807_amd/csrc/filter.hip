@@ -183,9 +183,19 @@ __global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState
 // (256, or 1024 for large clouds, where fewer chunks shorten the look-back).
 constexpr int CI = 1;                // positions per thread
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
-// dynamic LDS of the chain kernel: J [CR][CC] u16, Nx [CC] u32, Ex [CC] u32, mark [CC] i8
-constexpr size_t chain_lds(int CC) { return sizeof(uint16_t) * ilog2c(CC) * CC + 2 * sizeof(uint32_t) * CC + CC; }
+// dynamic LDS of the chain kernel: J [CR][CC] u16, Nx [CC] u32, Ex [CC] u32, Cu [CC] u16, mark [CC] i8
+constexpr size_t chain_lds(int CC) {
+    return sizeof(uint16_t) * ilog2c(CC) * CC + 2 * sizeof(uint32_t) * CC + sizeof(uint16_t) * CC + CC;
+}
 constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"
+// A next pointer is searched for at most SCAN_BOUND positions ahead; beyond
+// that it is left unresolved (UNRES) and found only if the chain reaches its
+// position, by one wavefront scanning on from there.  Every position's own
+// search is then bounded, and the scans for chain nodes cover disjoint ranges
+// of the curve, so a pass stays linear in n whatever runs of coincident or
+// near-coincident points the cloud holds.
+constexpr int SCAN_BOUND = 1024;
+constexpr uint32_t UNRES = 0xFFFFFFFFu;
 constexpr uint32_t PUB = 0x80000000u;
 constexpr uint32_t MX_AGG = 0x40000000u;   // farthest reach: this chunk's own (positions < 2^30)
 constexpr uint32_t MX_PRE = 0x80000000u;   // farthest reach of chunks 0 .. c
@@ -197,6 +207,30 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
 }
 __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The next pointer of position j by a wavefront scan from position `from`:
+// the first live position k >= from farther than r_filter from j when j is
+// live, the first live k >= from when j is dead; n when there is none.  All 64
+// lanes of the wavefront call it together.
+__device__ uint32_t scan_next(const float *__restrict__ xyz, const uint32_t *__restrict__ ord, int64_t n,
+                              const uint8_t *__restrict__ live_in, float rf2, int64_t j, int64_t from) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint32_t a = ord[j];
+    const bool lj = live_in[a] != 0;
+    const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
+    for (int64_t base = from; base < n; base += WAVE) {
+        const int64_t k = base + lane;
+        bool ok = false;
+        if (k < n) {
+            const uint32_t b = ord[k];
+            if (live_in[b])
+                ok = !lj || sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2;
+        }
+        const uint64_t bal = __ballot(ok);
+        if (bal) return (uint32_t)(base + __builtin_ctzll(bal));
+    }
+    return (uint32_t)n;
 }
 
 template <int CT>
@@ -241,7 +275,8 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     auto J = reinterpret_cast<uint16_t(*)[CC]>(chain_mem);
     uint32_t *Nx = chain_mem + CR * CC / 2;
     uint32_t *Ex = Nx + CC;
-    int8_t *mark = reinterpret_cast<int8_t *>(Ex + CC);
+    uint16_t *Cu = reinterpret_cast<uint16_t *>(Ex + CC);
+    int8_t *mark = reinterpret_cast<int8_t *>(Cu + CC);
     __shared__ uint32_t s_chunk, s_entry, s_prefix, s_max;
     __shared__ uint32_t lw[CT / WAVE];
     if (threadIdx.x == 0) {
@@ -254,26 +289,29 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     if (cs >= n) return;                      // uniform
     const int64_t ce = min(cs + (int64_t)CC, n);
     const int len = (int)(ce - cs);
-    // 1. next pointers and the first jump table
+    // 1. next pointers (searched at most SCAN_BOUND positions ahead) and the
+    //    first jump table
     for (int i = threadIdx.x; i < CC; i += CT) {
         if (i < len) {
             const int64_t j = cs + i;
             const uint32_t a = ord[j];
+            const int64_t kend = min(n, j + 1 + (int64_t)SCAN_BOUND);
             int64_t k = j + 1;
             if (live_in[a]) {
                 const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
-                for (; k < n; ++k) {
+                for (; k < kend; ++k) {
                     const uint32_t b = ord[k];
                     if (live_in[b] &&
                         sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2)
                         break;
                 }
             } else {
-                while (k < n && !live_in[ord[k]]) ++k;
+                while (k < kend && !live_in[ord[k]]) ++k;
             }
-            Nx[i] = (uint32_t)k;
+            const bool unres = k == kend && kend < n;
+            Nx[i] = unres ? UNRES : (uint32_t)k;
             J[0][i] = k < ce ? (uint16_t)(k - cs) : OUTL;
-            atomicMax(&s_max, (uint32_t)k);
+            atomicMax(&s_max, unres ? (uint32_t)n : (uint32_t)k);   // an unresolved pointer reaches at most n
         } else {
             J[0][i] = OUTL;
         }
@@ -292,11 +330,13 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
         }
         __syncthreads();
     }
-    // 3. where the chain leaves the chunk from every entry position
+    // 3. where the chain leaves the chunk from every entry position: its last
+    //    node inside the chunk and that node's next pointer (maybe UNRES)
     for (int i = threadIdx.x; i < len; i += CT) {
         int cur = i;
         for (int t = CR - 1; t >= 0; --t)
             if (J[t][cur] != OUTL) cur = J[t][cur];
+        Cu[i] = (uint16_t)cur;
         Ex[i] = Nx[cur];
     }
     // The chain enters this chunk at a position no later than M, the farthest
@@ -336,14 +376,17 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     }
     __syncthreads();
     const int64_t M = c > 0 ? (int64_t)s_max : cs;
-    bool same = M < ce;
+    bool same = M < ce && Ex[0] != UNRES;
     if (same)
         for (int i = threadIdx.x; i <= (int)(M - cs); i += CT) same = same && Ex[i] == Ex[0];
     const bool merged = __syncthreads_and(same) != 0;
-    if (threadIdx.x == 0) {
-        if (merged) st_agent(&exit_pub[c], PUB | Ex[0]);
+    if (threadIdx.x < WAVE) {
+        // the first wavefront waits for the entry and publishes the exit,
+        // scanning on from the chunk's last chain node if its pointer is unresolved
+        const int lane = threadIdx.x;
+        if (merged && lane == 0) st_agent(&exit_pub[c], PUB | Ex[0]);
         uint32_t X = 0;
-        if (c > 0) {
+        if (c > 0 && lane == 0) {
             uint32_t v = 0, spins = 0;
             while (((v = ld_agent(&exit_pub[c - 1])) & PUB) == 0) {
                 if (++spins > SPIN_LIMIT) {
@@ -353,8 +396,13 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
             }
             X = v & ~PUB;
         }
-        if (!merged) st_agent(&exit_pub[c], PUB | ((int64_t)X < ce ? Ex[X - cs] : X));
-        s_entry = X;
+        X = (uint32_t)__shfl((int)X, 0, WAVE);
+        if (!merged) {
+            uint32_t E = (int64_t)X < ce ? Ex[X - cs] : X;
+            if (E == UNRES) E = scan_next(xyz, ord, n, live_in, rf2, cs + Cu[X - cs], cs + Cu[X - cs] + 1);
+            if (lane == 0) st_agent(&exit_pub[c], PUB | E);
+        }
+        if (lane == 0) s_entry = X;
     }
     for (int i = threadIdx.x; i < CC; i += CT) mark[i] = -1;
     __syncthreads();

@@ -2,11 +2,11 @@
 // on the hot path; the benchmark divides the query's algorithmic bytes by
 // what these kernels reach on the same chip).
 //
-//  k_probe_read    every lane streams float4s through a buffer, `passes`
-//                  times: HBM bandwidth when the buffer is far larger than the
-//                  caches, L2 or MALL bandwidth when it fits in them (each
-//                  lane re-reads its own addresses, so a block keeps hitting
-//                  the L2 of its own XCD).
+//  k_probe_read    every lane streams float4s through one XCD's part of a
+//                  buffer, `passes` times: HBM bandwidth when the buffer is
+//                  far larger than the caches, L2 or MALL bandwidth when it
+//                  fits in them (a part is only read by blocks on its XCD, so
+//                  re-reads hit that XCD's L2).
 //  k_probe_gather  the collision query's memory pattern without its
 //                  arithmetic: per item a 16-byte descriptor (the size of a
 //                  sphere), the 32-byte leaf record it names, then `len`
@@ -22,21 +22,35 @@ namespace capt {
 
 namespace {
 
+// The buffer is split into one part per XCD (blocks go to the XCDs round
+// robin, so block b works on part b % 8); a thread walks (pass, float4) pairs
+// of its part with a fixed stride, eight loads in flight.
 __global__ void __launch_bounds__(256) k_probe_read(const float4 *__restrict__ p, int64_t n4, int passes,
                                                     float *__restrict__ sink) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NX = 8, U = 8;
+    const int nx = (int)min<int64_t>(NX, (int64_t)gridDim.x);
+    const int part = (int)(blockIdx.x % (unsigned)nx);
+    const int64_t pb = blockIdx.x / nx;
+    const int64_t nb = ((int64_t)gridDim.x - part + nx - 1) / nx;   // blocks on this part
+    const int64_t p0 = n4 * part / nx, p1 = n4 * (part + 1) / nx;
+    const int64_t len = p1 - p0;
+    if (len <= 0) return;
+    const int64_t stride = nb * blockDim.x;
+    const int64_t total = len * passes;
+    int64_t done = pb * blockDim.x + threadIdx.x;
+    int64_t q = done % len;
+    const int64_t step = stride % len;
     float acc = 0.0f;
-    for (int r = 0; r < passes; ++r) {
-        int64_t i = i0;
-        for (; i + 3 * stride < n4; i += 4 * stride) {
-            const float4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-            acc += ((a.x + a.w) + (b.x + b.w)) + ((c.x + c.w) + (d.x + d.w));
+    for (; done < total; done += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = done + u * stride < total ? p[p0 + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            q += step;
+            q = q >= len ? q - len : q;
         }
-        for (; i < n4; i += stride) {
-            const float4 a = p[i];
-            acc += a.x + a.w;
-        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u].x + v[u].w;
     }
     // the buffer's contents decide whether anything is stored, so no load is dead
     if (acc == -1.0f) sink[0] = acc;
@@ -76,10 +90,11 @@ __global__ void __launch_bounds__(256) k_probe_gather(const int4 *__restrict__ i
 
 }  // namespace
 
-capt_status probe_read(const void *buf, size_t bytes, int32_t passes, float *sink, hipStream_t s) {
+capt_status probe_read(const void *buf, size_t bytes, int32_t passes, int32_t blocks_per_cu, float *sink,
+                       hipStream_t s) {
     const int64_t n4 = (int64_t)(bytes / 16);
     if (n4 == 0 || passes <= 0) return CAPT_OK;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, (int64_t)device_info().cus * 8));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, (int64_t)device_info().cus * blocks_per_cu));
     hipLaunchKernelGGL(k_probe_read, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float4 *>(buf), n4,
                        passes, sink);
     CAPT_LAUNCH_CHECK();

@@ -77,6 +77,7 @@ def test_no_gpu_needed_for_validation(lib):
     assert lib.capt_filter(P(1), 10, -1.0, P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
     assert lib.capt_filter(P(1), 10, float("nan"), P(1), None, C.byref(n_out), None) == capt.CAPT_EINVAL
     assert lib.capt_filter(P(1), 10, 0.01, P(1), None, None, None) == capt.CAPT_EINVAL
+    assert lib.capt_filter(P(1), 1 << 30, 0.01, P(1), None, C.byref(n_out), None) == capt.CAPT_EUNSUPPORTED
     # filter + build: NULL out, bad filter radius, bad build radii, unknown flags, bad crop
     m = C.c_int64()
     crop = (C.c_float * 4)(0.0, 0.0, 0.0, 1.0)
