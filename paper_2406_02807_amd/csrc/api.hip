@@ -890,7 +890,8 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     const size_t oPts = al(oLeaf + sizeof(Leaf) * (size_t)h.N);
     const size_t oRep = al(oPts + sizeof(float) * 3 * (size_t)std::max<int64_t>(h.n, 1));
     const size_t oPr = al(oRep + sizeof(int32_t) * (size_t)h.N);
-    c.fixed_bytes = al(oPr + (size_t)h.N);
+    const size_t oTb = al(oPr + (size_t)h.N);
+    c.fixed_bytes = al(oTb + sizeof(float4) * 4 * (size_t)tree_blocks_count(h.D));
     c.fixed = dev_alloc(c.fixed_bytes, s);
     const bool indexed = (h.flags & CAPT_INDEXED_SETS) != 0;
     c.sets_bytes = sets_bytes(E, indexed);
@@ -906,6 +907,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     c.dev.pts = reinterpret_cast<float *>(F + oPts);
     c.rep = reinterpret_cast<int32_t *>(F + oRep);
     c.pruned_flag = reinterpret_cast<uint8_t *>(F + oPr);
+    c.dev.tb = tree_blocks_count(h.D) > 0 ? reinterpret_cast<float4 *>(F + oTb) : nullptr;
     {
         float *qx, *qy, *qz;
         int32_t *qi;
@@ -932,6 +934,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     if (!st) st = cp(const_cast<float *>(c.dev.pts), pts, sizeof(float) * 3 * (size_t)h.n);
     if (!st) st = cp(c.rep, rep, sizeof(int32_t) * (size_t)h.N);
     if (!st) st = cp(c.pruned_flag, pr, (size_t)h.N);
+    if (!st) st = tree_blocks(c.dev.T, (int)h.D, const_cast<float4 *>(c.dev.tb), s);
     if (!indexed) {
         if (!st) st = cp(const_cast<float *>(c.dev.px), px.data(), sizeof(float) * E);
         if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);

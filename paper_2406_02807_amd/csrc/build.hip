@@ -774,6 +774,27 @@ __global__ void k_publish(const unsigned long long *__restrict__ totals, const u
 
 inline unsigned nblk(int64_t n, int tb = TB) { return (unsigned)((n + tb - 1) / tb); }
 
+// One thread per block of the blocked tree copy (see tree_block_base).
+__global__ void __launch_bounds__(TB) k_tree_blocks(const float *__restrict__ T, int D, int64_t nblocks,
+                                                    float4 *__restrict__ tb) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    int r = D & 3;
+    while (r + 4 <= D - 4 && (uint64_t)b >= tree_block_base(r + 4, D)) r += 4;
+    const int64_t i = ((int64_t)1 << r) - 1 + (b - (int64_t)tree_block_base(r, D));
+    float v[16];
+    v[0] = T[i];
+    v[1] = T[2 * i + 1];
+    v[2] = T[2 * i + 2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[3 + k] = T[4 * i + 3 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[7 + k] = T[8 * i + 7 + k];
+    v[15] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tb[4 * b + k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Per-cloud scratch kept from the count phase to the fill phase.
@@ -810,7 +831,8 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     const size_t oPts = align256(oLeaf + sizeof(Leaf) * (size_t)N);
     const size_t oRep = align256(oPts + sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
     const size_t oPr = align256(oRep + sizeof(int32_t) * (size_t)N);
-    const size_t fixed_bytes = align256(oPr + (size_t)N);
+    const size_t oTb = align256(oPr + (size_t)N);
+    const size_t fixed_bytes = align256(oTb + sizeof(float4) * 4 * (size_t)tree_blocks_count(D));
     C.fixed = dev_alloc(fixed_bytes, s);
     if (!C.fixed) {
         set_error("device allocation of %zu bytes failed", fixed_bytes);
@@ -825,6 +847,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     C.dev.pts = pts;
     C.rep = reinterpret_cast<int32_t *>(F + oRep);
     C.pruned_flag = reinterpret_cast<uint8_t *>(F + oPr);
+    C.dev.tb = tree_blocks_count(D) > 0 ? reinterpret_cast<float4 *>(F + oTb) : nullptr;
     C.dev.n = n;
     C.dev.D = D;
     C.dev.flags = flags;
@@ -988,6 +1011,10 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     hipLaunchKernelGGL(k_local_levels, dim3(1u << d), dim3(LTB), 0, s, L[0][cur[0]], L[1][cur[1]], L[2][cur[2]],
                        inv, xyz, n, N, D, d, ax, T, C.rep);
     CAPT_LAUNCH_CHECK();
+    {
+        capt_status tbs = tree_blocks(T, D, const_cast<float4 *>(C.dev.tb), s);
+        if (tbs) return tbs;
+    }
 
     // 3. leaf cells and pruning
     const int prune = (!(flags & CAPT_NO_PRUNE) && r_min > 0.0f) ? 1 : 0;
@@ -1207,6 +1234,14 @@ capt_status chunk_boxes(const float *px, const float *py, const float *pz, const
     const int64_t nchunk = entries / CHUNK;
     if (nchunk <= 0) return CAPT_OK;
     hipLaunchKernelGGL(k_chunk_boxes, dim3(nblk(nchunk * CHUNK)), dim3(TB), 0, s, px, py, pz, pidx, pts, nchunk, cbox);
+    CAPT_LAUNCH_CHECK();
+    return CAPT_OK;
+}
+
+capt_status tree_blocks(const float *T, int D, float4 *tb, hipStream_t s) {
+    const int64_t nb = tree_blocks_count(D);
+    if (nb <= 0 || !tb) return CAPT_OK;
+    hipLaunchKernelGGL(k_tree_blocks, dim3(nblk(nb)), dim3(TB), 0, s, T, D, nb, tb);
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
 }

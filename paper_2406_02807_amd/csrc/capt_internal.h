@@ -29,6 +29,7 @@ static_assert(sizeof(Leaf) == 32, "leaf record is 32 bytes");
 // kernel and passed by value to the single-cloud kernels.
 struct CloudDev {
     const float *T;        // [N-1] split values, Eytzinger order
+    const float4 *tb;      // 4-level blocks of the lower levels (tree_blocks), or NULL
     const Leaf *leaf;      // [N]
     const float *px;       // set entries, structure of arrays
     const float *py;
@@ -51,6 +52,20 @@ inline uint64_t axes_code(const uint8_t *axes, int D) {
     return c;
 }
 __host__ __device__ __forceinline__ int axis_at(uint64_t code, int d) { return (int)((code >> (2 * d)) & 3u); }
+
+// Blocked copy of a tree's lower levels: for every node i at a root level
+// r = D - 4k (k >= 1), the 15 split values of its 4-level subtree in
+// breadth-first order (i; 2i+1, 2i+2; 4i+3 .. 4i+6; 8i+7 .. 8i+14) and one
+// pad, 64 bytes, so a descent reads four levels from one cache line.  Blocks
+// go by root level, shallowest first, then by node; those of root level r
+// start at block tree_block_base(r, D).  Built for 4 <= D <= 29 (the query
+// addresses them with 32-bit byte offsets).
+__host__ __device__ __forceinline__ uint32_t tree_block_base(int r, int D) {
+    return (uint32_t)((((uint64_t)1 << r) - ((uint64_t)1 << (D & 3))) / 15u);
+}
+inline int64_t tree_blocks_count(int D) {
+    return (D >= 4 && D <= 29) ? (int64_t)tree_block_base(D, D) : 0;
+}
 
 // Stored-set alignment: every set starts at a multiple of this many entries
 // and is padded with +inf entries up to one.  A chunk of SET_ALIGN entries is
@@ -268,6 +283,9 @@ capt_status probe_read(const void *buf, size_t bytes, int32_t passes, int32_t bl
 capt_status probe_gather(const int32_t *items, int64_t m, const void *leaves, int64_t nleaf, const float *x,
                          const float *y, const float *z, int64_t entries, int32_t lanes_per_item, uint8_t *out,
                          hipStream_t s);
+
+// build.hip: the blocked copy of T's lower levels (tree_blocks_count(D) blocks)
+capt_status tree_blocks(const float *T, int D, float4 *tb, hipStream_t s);
 
 // clearance.hip
 capt_status clearance_fwd(capt_forest_s *f, const float *spheres, const int64_t *query_off,

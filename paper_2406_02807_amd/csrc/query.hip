@@ -93,12 +93,12 @@ __device__ __forceinline__ Leaf descend_leaf_any(const float4 &q, const float *T
 // The same descent, shaped for latency: the LDS levels are taken three per
 // round trip (the node, both children and all four grandchildren are read
 // together, then three comparisons pick the path), and so are the global
-// levels, the last one or two of them together when D - L is not a multiple
-// of three; so a tree with g global levels reaches its leaf record after
-// ceil(g / 3) + 1 memory round trips.  Returns the leaf record; *lf gets its
-// index.
+// levels down to the first root level of the tree's blocked copy (TB, when the
+// forest has one); from there every four levels are one 64-byte block, one
+// cache line per round trip.  Returns the leaf record; *lf gets its index.
 __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, int L, const float *__restrict__ Tg,
-                                             const Leaf *__restrict__ leaves, int D, uint32_t *lf) {
+                                             const float4 *__restrict__ TB, const Leaf *__restrict__ leaves, int D,
+                                             uint32_t *lf) {
     const float xs[3] = {q.x, q.y, q.z};
     uint32_t i = 0;
     int lv = 0;
@@ -117,12 +117,11 @@ __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, i
         i = 2 * i + 1 + (xs[a] > Tl[i] ? 1u : 0u);
         a = (a == 2) ? 0 : a + 1;
     }
-    // global levels three per round trip: the node, both children and all
-    // four grandchildren are read together, then three comparisons pick the
-    // path (after three levels the cyclic axis is back to `a`)
+    // Eytzinger levels lv .. gend - 1 (all the rest without a blocked copy)
+    const int gend = TB ? D - 4 * ((D - lv) / 4) : D;
     const int a1 = (a == 2) ? 0 : a + 1;
     const int a2 = (a1 == 2) ? 0 : a1 + 1;
-    for (; lv + 3 <= D; lv += 3) {
+    for (; lv + 3 <= gend; lv += 3) {   // after three levels the cyclic axis is back to `a`
         const float t0 = ld32(Tg, 4u * i);
         const float t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
         const float t2a = ld32(Tg, 16u * i + 12u), t2b = ld32(Tg, 16u * i + 16u);
@@ -133,13 +132,36 @@ __device__ __forceinline__ Leaf descend_leaf(const float4 &q, const float *Tl, i
         const uint32_t b2 = xs[a2] > t2 ? 1u : 0u;
         i = 8 * i + 7 + 4 * b0 + 2 * b1 + b2;
     }
-    if (D - lv == 2) {
+    if (gend - lv == 2) {
         const float t0 = ld32(Tg, 4u * i), t1a = ld32(Tg, 8u * i + 4u), t1b = ld32(Tg, 8u * i + 8u);
         const uint32_t b0 = xs[a] > t0 ? 1u : 0u;
         const uint32_t b1 = xs[a1] > (b0 ? t1b : t1a) ? 1u : 0u;
         i = 4 * i + 3 + 2 * b0 + b1;
-    } else if (D - lv == 1) {
+    } else if (gend - lv == 1) {
         i = 2 * i + 1 + (xs[a] > ld32(Tg, 4u * i) ? 1u : 0u);
+    }
+    if (TB) {
+        // 4-level blocks from root level gend: levels r .. r+3 split on axes
+        // c0, c1, c2, c0 (cyclic), and the next block's root on c1
+        int c0 = gend % 3;
+        for (int r = gend; r < D; r += 4) {
+            const int c1 = (c0 == 2) ? 0 : c0 + 1;
+            const int c2 = (c1 == 2) ? 0 : c1 + 1;
+            const uint32_t off = 64u * (tree_block_base(r, D) + (i - ((1u << r) - 1u)));
+            const float4 v0 = ld32(TB, off), v1 = ld32(TB, off + 16u), v2 = ld32(TB, off + 32u),
+                         v3 = ld32(TB, off + 48u);
+            // v0 = (n0, n1, n2, n3), v1 = (n4, n5, n6, n7), v2 = (n8 .. n11), v3 = (n12, n13, n14, pad)
+            const uint32_t b0 = xs[c0] > v0.x ? 1u : 0u;
+            const uint32_t b1 = xs[c1] > (b0 ? v0.z : v0.y) ? 1u : 0u;
+            const float t2 = b0 ? (b1 ? v1.z : v1.y) : (b1 ? v1.x : v0.w);
+            const uint32_t b2 = xs[c2] > t2 ? 1u : 0u;
+            const float p0 = b2 ? v2.x : v1.w, p1 = b2 ? v2.z : v2.y;
+            const float p2 = b2 ? v3.x : v2.w, p3 = b2 ? v3.z : v3.y;
+            const float t3 = b0 ? (b1 ? p3 : p2) : (b1 ? p1 : p0);
+            const uint32_t b3 = xs[c0] > t3 ? 1u : 0u;
+            i = 16 * i + 15 + 8 * b0 + 4 * b1 + 2 * b2 + b3;
+            c0 = c1;
+        }
     }
     *lf = i - ((1u << D) - 1u);
     return leaves[*lf];
@@ -197,7 +219,7 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     if (AXES && !C.cyclic)   // uniform; the batched kernel takes cyclic forests only
         leaf = descend_leaf_any(q, Tl, L, C.T, C.leaf, C.D, C.axes, &lf);
     else
-        leaf = descend_leaf(q, Tl, L, C.T, C.leaf, C.D, &lf);
+        leaf = descend_leaf(q, Tl, L, C.T, C.tb, C.leaf, C.D, &lf);
     if (!valid) leaf.count = 0;
     bool alive = leaf.count > 0;
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
