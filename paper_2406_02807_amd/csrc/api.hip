@@ -854,15 +854,16 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
         }
     }
     const size_t E = (size_t)std::max<int64_t>(padded, (int64_t)CHUNK);
-    std::vector<float> px(E, INFINITY), py(E, INFINITY), pz(E, INFINITY);
+    std::vector<float> pe(3 * E, INFINITY);   // per chunk: 16 x, 16 y, 16 z (set_off)
     std::vector<int32_t> pidx(E, -1);
     for (int64_t l = 0; l < h.N; ++l)
         for (int64_t k = off[l]; k < off[l + 1]; ++k) {
             const size_t e = leaves[(size_t)l].start + (size_t)(k - off[l]);
             const int64_t id = idx[k];
-            px[e] = pts[3 * id];
-            py[e] = pts[3 * id + 1];
-            pz[e] = pts[3 * id + 2];
+            const int64_t o = set_off((int64_t)e);
+            pe[o] = pts[3 * id];
+            pe[o + CHUNK] = pts[3 * id + 1];
+            pe[o + 2 * CHUNK] = pts[3 * id + 2];
             pidx[e] = (int32_t)id;
         }
 
@@ -935,11 +936,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     if (!st) st = cp(c.rep, rep, sizeof(int32_t) * (size_t)h.N);
     if (!st) st = cp(c.pruned_flag, pr, (size_t)h.N);
     if (!st) st = tree_blocks(c.dev.T, (int)h.D, const_cast<float4 *>(c.dev.tb), s);
-    if (!indexed) {
-        if (!st) st = cp(const_cast<float *>(c.dev.px), px.data(), sizeof(float) * E);
-        if (!st) st = cp(const_cast<float *>(c.dev.py), py.data(), sizeof(float) * E);
-        if (!st) st = cp(const_cast<float *>(c.dev.pz), pz.data(), sizeof(float) * E);
-    }
+    if (!indexed && !st) st = cp(const_cast<float *>(c.dev.px), pe.data(), sizeof(float) * 3 * E);
     if (!st) st = cp(const_cast<int32_t *>(c.dev.pidx), pidx.data(), sizeof(int32_t) * E);
     if (!st)
         st = chunk_boxes(c.dev.px, c.dev.py, c.dev.pz, c.dev.pidx, c.dev.pts, padded, const_cast<float4 *>(c.dev.cbox),

@@ -561,9 +561,10 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         if (FILL && ok) {
             const uint32_t pos = out0 + cnt + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             if (px) {   // not for indexed sets
-                px[pos] = x;
-                py[pos] = y;
-                pz[pos] = z;
+                const int64_t o = set_off(pos);
+                px[o] = x;
+                py[o] = y;
+                pz[o] = z;
             }
             pidx[pos] = id;
             lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
@@ -679,9 +680,10 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
     const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
     for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
         if (px) {
-            px[out0 + k] = INFINITY;
-            py[out0 + k] = INFINITY;
-            pz[out0 + k] = INFINITY;
+            const int64_t o = set_off(out0 + k);
+            px[o] = INFINITY;
+            py[o] = INFINITY;
+            pz[o] = INFINITY;
         }
         pidx[out0 + k] = -1;
     }
@@ -1184,11 +1186,11 @@ __global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restr
     const int64_t k = e / CHUNK;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (px) {
-        const float x = k < nchunk ? px[e] : INFINITY;
+        const float x = k < nchunk ? px[set_off(e)] : INFINITY;
         if (x < INFINITY) {
             lo[0] = hi[0] = x;
-            lo[1] = hi[1] = py[e];
-            lo[2] = hi[2] = pz[e];
+            lo[1] = hi[1] = py[set_off(e)];
+            lo[2] = hi[2] = pz[set_off(e)];
         }
     } else {   // indexed sets
         const int32_t id = k < nchunk ? pidx[e] : -1;
@@ -1214,19 +1216,22 @@ __global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restr
 }  // namespace
 
 size_t sets_bytes(size_t E, bool indexed) {
-    return align256(sizeof(float) * E) * (indexed ? 0 : 3) + align256(sizeof(int32_t) * E) +
+    return (indexed ? 0 : align256(sizeof(float) * 3 * E)) + align256(sizeof(int32_t) * E) +
            align256(sizeof(float4) * 2 * (E / CHUNK + 1));
 }
 
+// E (a multiple of CHUNK) entries: the interleaved coordinate blocks (not for
+// indexed sets), the indices, the chunk boxes.
 void sets_layout(void *base, size_t E, bool indexed, float **px, float **py, float **pz, int32_t **pidx,
                  float4 **cbox) {
     char *P = static_cast<char *>(base);
-    const size_t a = indexed ? 0 : align256(sizeof(float) * E);
-    *px = indexed ? nullptr : reinterpret_cast<float *>(P);
-    *py = indexed ? nullptr : reinterpret_cast<float *>(P + a);
-    *pz = indexed ? nullptr : reinterpret_cast<float *>(P + 2 * a);
-    *pidx = reinterpret_cast<int32_t *>(P + 3 * a);
-    *cbox = reinterpret_cast<float4 *>(P + 3 * a + align256(sizeof(int32_t) * E));
+    const size_t a = indexed ? 0 : align256(sizeof(float) * 3 * E);
+    float *b = indexed ? nullptr : reinterpret_cast<float *>(P);
+    *px = b;
+    *py = b ? b + CHUNK : nullptr;
+    *pz = b ? b + 2 * CHUNK : nullptr;
+    *pidx = reinterpret_cast<int32_t *>(P + a);
+    *cbox = reinterpret_cast<float4 *>(P + a + align256(sizeof(int32_t) * E));
 }
 
 capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, const float *pts,

@@ -31,9 +31,9 @@ struct CloudDev {
     const float *T;        // [N-1] split values, Eytzinger order
     const float4 *tb;      // 4-level blocks of the lower levels (tree_blocks), or NULL
     const Leaf *leaf;      // [N]
-    const float *px;       // set entries, structure of arrays
-    const float *py;
-    const float *pz;
+    const float *px;       // set entries: x, y, z blocks of every 16-entry chunk (set_off)
+    const float *py;       // px + 16
+    const float *pz;       // px + 32
     const int32_t *pidx;   // original index of each set entry (-1 = padding)
     const float4 *cbox;    // per 16-entry chunk of the sets: [2k] = lo, [2k+1] = hi
     const float *pts;      // [n][3] the cloud as built
@@ -72,6 +72,13 @@ inline int64_t tree_blocks_count(int D) {
 // also the unit of the second-level bounding boxes the query scan tests.
 constexpr uint32_t SET_ALIGN = 16;
 constexpr uint32_t CHUNK = SET_ALIGN;
+// Set entries are stored per chunk of CHUNK entries as structure of arrays:
+// chunk k holds its 16 x values, then its 16 y, then its 16 z (192 bytes), so
+// the coordinates of one chunk sit in two 128-byte cache lines.  With px the x
+// block of chunk 0, py = px + 16 and pz = px + 32, the coordinate of entry e
+// is at float offset set_off(e) from each.
+__host__ __device__ __forceinline__ int64_t set_off(int64_t e) { return 48 * (e >> 4) + (e & 15); }
+
 // Stored set entries per cloud (with padding) stay below this, so the query
 // kernels address the set arrays with 32-bit byte offsets.
 constexpr unsigned long long MAX_SET_ENTRIES = 1ull << 30;
@@ -340,9 +347,10 @@ __device__ __forceinline__ void set_point(const CloudDev &C, int64_t e, float &x
             z = C.pts[3 * (int64_t)id + 2];
         }
     } else {
-        x = C.px[e];
-        y = C.py[e];
-        z = C.pz[e];
+        const int64_t o = set_off(e);
+        x = C.px[o];
+        y = C.py[o];
+        z = C.pz[o];
     }
 }
 

@@ -244,8 +244,6 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     uint32_t head = 0, tail = (uint32_t)__popcll(dm);     // ring [head, tail), wave-uniform
     const float4 *__restrict__ CB = C.cbox;
     const float *__restrict__ PX = C.px;
-    const float *__restrict__ PY = C.py;
-    const float *__restrict__ PZ = C.pz;
     const int32_t *__restrict__ PI = C.pidx;
     const float *__restrict__ PT = C.pts;
     constexpr bool indexed = IDX;   // sets of point indices (CAPT_INDEXED_SETS)
@@ -282,9 +280,11 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
                 py[u] = in[u] ? PT[p3 + 1] : 0.f;
                 pz[u] = in[u] ? PT[p3 + 2] : 0.f;
             } else {
-                px[u] = in[u] ? ld32(PX, 4u * e) : 0.f;
-                py[u] = in[u] ? ld32(PY, 4u * e) : 0.f;
-                pz[u] = in[u] ? ld32(PZ, 4u * e) : 0.f;
+                // the chunk's x, y and z blocks from one 64-bit address
+                const float *cp = PX + 48 * (size_t)ch + ((uint32_t)lane & (CHUNK - 1));
+                px[u] = in[u] ? cp[0] : 0.f;
+                py[u] = in[u] ? cp[CHUNK] : 0.f;
+                pz[u] = in[u] ? cp[2 * CHUNK] : 0.f;
             }
         }
         bool hit[U];
