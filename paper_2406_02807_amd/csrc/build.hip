@@ -549,7 +549,7 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                                                      const uint32_t *__restrict__ pstart,
                                                      float *__restrict__ px, float *__restrict__ py,
                                                      float *__restrict__ pz, int32_t *__restrict__ pidx,
-                                                     Leaf *__restrict__ leaf) {
+                                                     Leaf *__restrict__ leaf, float4 *__restrict__ cbox) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (l >= A.N) return;
@@ -696,6 +696,53 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         L.start = out0;
         L.count = cnt;
         leaf[l] = L;
+    }
+    // the box of every 16-entry chunk of the set, from the entries this wave
+    // has just written (still in L2): 16 lanes per chunk, padding skipped
+    // (x = +inf in plain sets, index -1 in indexed sets).  The wave's stores
+    // become visible to its own lanes' loads with a workgroup-scope fence (the
+    // CU's vector L1 is shared by the workgroup; an agent-scope fence would
+    // write back the XCD's whole L2).
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const uint32_t nch = padded / CHUNK;
+    for (uint32_t k0 = 0; k0 < nch; k0 += WAVE / CHUNK) {
+        const uint32_t k = k0 + (uint32_t)lane / CHUNK;
+        const int64_t e = (int64_t)out0 + (int64_t)k * CHUNK + (lane & (CHUNK - 1));
+        float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (k < nch) {
+            float x = INFINITY, y = 0.f, z = 0.f;
+            if (px) {
+                const int64_t o = set_off(e);
+                x = px[o];
+                y = py[o];
+                z = pz[o];
+            } else {
+                const int32_t id = pidx[e];
+                if (id >= 0) {
+                    x = A.xyz[3 * (int64_t)id];
+                    y = A.xyz[3 * (int64_t)id + 1];
+                    z = A.xyz[3 * (int64_t)id + 2];
+                }
+            }
+            if (x < INFINITY) {
+                blo[0] = bhi[0] = x;
+                blo[1] = bhi[1] = y;
+                blo[2] = bhi[2] = z;
+            }
+        }
+#pragma unroll
+        for (int off = CHUNK / 2; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                blo[a] = fminf(blo[a], __shfl_xor(blo[a], off, WAVE));
+                bhi[a] = fmaxf(bhi[a], __shfl_xor(bhi[a], off, WAVE));
+            }
+        }
+        if (k < nch && (lane & (CHUNK - 1)) == 0) {
+            const int64_t c = (int64_t)out0 / CHUNK + k;
+            cbox[2 * c] = make_float4(blo[0], blo[1], blo[2], 0.0f);
+            cbox[2 * c + 1] = make_float4(bhi[0], bhi[1], bhi[2], 0.0f);
+        }
     }
 }
 
@@ -1051,7 +1098,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     A.R = R;
     A.R2 = R * R;
     hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, nullptr);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, pad_part);
     CAPT_LAUNCH_CHECK();
@@ -1087,9 +1134,9 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     C.dev.pidx = pidx;
     C.dev.cbox = cbox;
     hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
-                       py, pz, pidx, const_cast<Leaf *>(C.dev.leaf));
+                       py, pz, pidx, const_cast<Leaf *>(C.dev.leaf), cbox);
     CAPT_LAUNCH_CHECK();
-    return chunk_boxes(px, py, pz, pidx, C.dev.pts, (int64_t)tot[1], cbox, s);
+    return CAPT_OK;
 }
 
 }  // namespace
