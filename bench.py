@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 LEAF_BYTES = 32      # AABB (24 B) + set start and length (8 B)
 SPHERE_BYTES = 16
 ENTRY_BYTES = 12     # x, y, z of one set entry
-BOX_BYTES = 32       # one chunk box (two float4)
+BOX_BYTES = 16       # one chunk box (six half-precision offsets + pad)
 CHUNK = 16           # set entries per chunk
 EXTRAS = ("tabletop", "batched", "clearance", "frame", "posed", "indexed_sets")
 

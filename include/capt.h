@@ -401,10 +401,15 @@ capt_status capt_query_stats(capt_forest f, const float *spheres, const int64_t 
 
 /*
  * Work of the collision kernel's two-level set scan (not on the hot path).
- * capt_collides stores every set as chunks of 16 entries, each with a float32
+ * capt_collides stores every set as chunks of 16 entries, each with a
  * bounding box, tests the boxes and scans only the entries of chunks whose
  * box lies within the sphere's radius; a box is never farther than any of its
- * points, so the answers are those of the full scan of Alg. 3.  Per sphere
+ * points, so the answers are those of the full scan of Alg. 3.  A chunk's box
+ * is kept as half-precision offsets from the lower corner b of its set's box
+ * (the leaf AABB): per axis, the lower bound's offset is the nearest half to
+ * lo - b (float32), then moved down one half at a time while b + offset > lo
+ * in float32, the upper bound's likewise moved up while b + offset < hi; the
+ * test uses the box b + offset.  Per sphere
  * whose leaf AABB does not reject it, for a scan in stored order up to and
  * including the chunk that holds its first hit (all chunks if none):
  *   boxes  [M] int32  chunk boxes tested

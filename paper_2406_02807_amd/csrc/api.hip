@@ -866,6 +866,22 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
             pe[o + 2 * CHUNK] = pts[3 * id + 2];
             pidx[e] = (int32_t)id;
         }
+    // the box of every 16-entry chunk, relative to its set's box (hbox_encode)
+    std::vector<uint4> cbox(E / CHUNK, make_uint4(0u, 0u, 0u, 0u));
+    for (int64_t l = 0; l < h.N; ++l) {
+        const Leaf &lf = leaves[(size_t)l];
+        for (uint32_t c0 = 0; c0 < lf.count; c0 += CHUNK) {
+            float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (uint32_t k = c0; k < std::min(lf.count, c0 + CHUNK); ++k) {
+                const int64_t id = idx[off[l] + k];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], pts[3 * id + a]);
+                    hi[a] = std::max(hi[a], pts[3 * id + a]);
+                }
+            }
+            cbox[(lf.start + c0) / CHUNK] = hbox_encode(lf.lo, lo, hi);
+        }
+    }
 
     capt_forest_s *f = new (std::nothrow) capt_forest_s();
     if (!f) {
@@ -912,7 +928,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     {
         float *qx, *qy, *qz;
         int32_t *qi;
-        float4 *qb;
+        uint4 *qb;
         sets_layout(c.sets, E, indexed, &qx, &qy, &qz, &qi, &qb);
         c.dev.px = qx;
         c.dev.py = qy;
@@ -938,9 +954,7 @@ capt_status capt_import(const void *host_blob, size_t bytes, void *stream, capt_
     if (!st) st = tree_blocks(c.dev.T, (int)h.D, const_cast<float4 *>(c.dev.tb), s);
     if (!indexed && !st) st = cp(const_cast<float *>(c.dev.px), pe.data(), sizeof(float) * 3 * E);
     if (!st) st = cp(const_cast<int32_t *>(c.dev.pidx), pidx.data(), sizeof(int32_t) * E);
-    if (!st)
-        st = chunk_boxes(c.dev.px, c.dev.py, c.dev.pz, c.dev.pidx, c.dev.pts, padded, const_cast<float4 *>(c.dev.cbox),
-                         s);
+    if (!st) st = cp(const_cast<uint4 *>(c.dev.cbox), cbox.data(), sizeof(uint4) * cbox.size());
     if (!st) st = upload_views(f, s);
     if (st) {
         destroy_forest(f);

@@ -21,8 +21,8 @@
 //     (Lemma 1, case 1); the float64 distance test is monotone under cell
 //     shrinking, so they agree exactly.  A count pass sizes the sets, a scan
 //     places them (each set starts at a multiple of SET_ALIGN entries), a fill
-//     pass writes them SoA with each leaf's AABB, and a last pass writes the
-//     box of every 16-entry chunk.
+//     pass writes them with each leaf's AABB and the box of every 16-entry
+//     chunk.
 #include <cmath>
 
 #include "capt_internal.h"
@@ -549,7 +549,7 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                                                      const uint32_t *__restrict__ pstart,
                                                      float *__restrict__ px, float *__restrict__ py,
                                                      float *__restrict__ pz, int32_t *__restrict__ pidx,
-                                                     Leaf *__restrict__ leaf, float4 *__restrict__ cbox) {
+                                                     Leaf *__restrict__ leaf, uint4 *__restrict__ cbox) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (l >= A.N) return;
@@ -738,11 +738,7 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                 bhi[a] = fmaxf(bhi[a], __shfl_xor(bhi[a], off, WAVE));
             }
         }
-        if (k < nch && (lane & (CHUNK - 1)) == 0) {
-            const int64_t c = (int64_t)out0 / CHUNK + k;
-            cbox[2 * c] = make_float4(blo[0], blo[1], blo[2], 0.0f);
-            cbox[2 * c + 1] = make_float4(bhi[0], bhi[1], bhi[2], 0.0f);
-        }
+        if (k < nch && (lane & (CHUNK - 1)) == 0) cbox[(int64_t)out0 / CHUNK + k] = hbox_encode(lo, blo, bhi);
     }
 }
 
@@ -1126,7 +1122,7 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     C.sets_bytes = bytes;
     float *px, *py, *pz;
     int32_t *pidx;
-    float4 *cbox;
+    uint4 *cbox;
     sets_layout(C.sets, E, indexed, &px, &py, &pz, &pidx, &cbox);
     C.dev.px = px;
     C.dev.py = py;
@@ -1221,56 +1217,16 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     return CAPT_OK;   // scratch is released stream-ordered; the forest is ready in stream order
 }
 
-namespace {
-__global__ void k_chunk_boxes(const float *__restrict__ px, const float *__restrict__ py, const float *__restrict__ pz,
-                              const int32_t *__restrict__ pidx, const float *__restrict__ pts, int64_t nchunk,
-                              float4 *__restrict__ cbox) {
-    // CHUNK consecutive lanes share one chunk: one entry each, then a
-    // butterfly min / max over the group (padding entries do not count).
-    // Stored points are finite and padding holds x = +inf, so plain sets
-    // need no index read; indexed sets mark padding with index -1.
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t k = e / CHUNK;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (px) {
-        const float x = k < nchunk ? px[set_off(e)] : INFINITY;
-        if (x < INFINITY) {
-            lo[0] = hi[0] = x;
-            lo[1] = hi[1] = py[set_off(e)];
-            lo[2] = hi[2] = pz[set_off(e)];
-        }
-    } else {   // indexed sets
-        const int32_t id = k < nchunk ? pidx[e] : -1;
-        if (id >= 0) {
-            lo[0] = hi[0] = pts[3 * (int64_t)id];
-            lo[1] = hi[1] = pts[3 * (int64_t)id + 1];
-            lo[2] = hi[2] = pts[3 * (int64_t)id + 2];
-        }
-    }
-#pragma unroll
-    for (int off = CHUNK / 2; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
-            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
-        }
-    }
-    if (k < nchunk && (e & (CHUNK - 1)) == 0) {
-        cbox[2 * k] = make_float4(lo[0], lo[1], lo[2], 0.0f);
-        cbox[2 * k + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
-    }
-}
-}  // namespace
 
 size_t sets_bytes(size_t E, bool indexed) {
     return (indexed ? 0 : align256(sizeof(float) * 3 * E)) + align256(sizeof(int32_t) * E) +
-           align256(sizeof(float4) * 2 * (E / CHUNK + 1));
+           align256(sizeof(uint4) * (E / CHUNK + 1));
 }
 
 // E (a multiple of CHUNK) entries: the interleaved coordinate blocks (not for
 // indexed sets), the indices, the chunk boxes.
 void sets_layout(void *base, size_t E, bool indexed, float **px, float **py, float **pz, int32_t **pidx,
-                 float4 **cbox) {
+                 uint4 **cbox) {
     char *P = static_cast<char *>(base);
     const size_t a = indexed ? 0 : align256(sizeof(float) * 3 * E);
     float *b = indexed ? nullptr : reinterpret_cast<float *>(P);
@@ -1278,17 +1234,9 @@ void sets_layout(void *base, size_t E, bool indexed, float **px, float **py, flo
     *py = b ? b + CHUNK : nullptr;
     *pz = b ? b + 2 * CHUNK : nullptr;
     *pidx = reinterpret_cast<int32_t *>(P + a);
-    *cbox = reinterpret_cast<float4 *>(P + a + align256(sizeof(int32_t) * E));
+    *cbox = reinterpret_cast<uint4 *>(P + a + align256(sizeof(int32_t) * E));
 }
 
-capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, const float *pts,
-                        int64_t entries, float4 *cbox, hipStream_t s) {
-    const int64_t nchunk = entries / CHUNK;
-    if (nchunk <= 0) return CAPT_OK;
-    hipLaunchKernelGGL(k_chunk_boxes, dim3(nblk(nchunk * CHUNK)), dim3(TB), 0, s, px, py, pz, pidx, pts, nchunk, cbox);
-    CAPT_LAUNCH_CHECK();
-    return CAPT_OK;
-}
 
 capt_status tree_blocks(const float *T, int D, float4 *tb, hipStream_t s) {
     const int64_t nb = tree_blocks_count(D);

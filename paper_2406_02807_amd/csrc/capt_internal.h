@@ -35,7 +35,7 @@ struct CloudDev {
     const float *py;       // px + 16
     const float *pz;       // px + 32
     const int32_t *pidx;   // original index of each set entry (-1 = padding)
-    const float4 *cbox;    // per 16-entry chunk of the sets: [2k] = lo, [2k+1] = hi
+    const uint4 *cbox;     // per 16-entry chunk of the sets: its box, half-precision (hbox_encode)
     const float *pts;      // [n][3] the cloud as built
     int64_t n;
     int32_t D;
@@ -78,6 +78,47 @@ constexpr uint32_t CHUNK = SET_ALIGN;
 // block of chunk 0, py = px + 16 and pz = px + 32, the coordinate of entry e
 // is at float offset set_off(e) from each.
 __host__ __device__ __forceinline__ int64_t set_off(int64_t e) { return 48 * (e >> 4) + (e & 15); }
+
+// The box of every 16-entry chunk is stored in 16 bytes: per axis, the lower
+// and upper bound as half-precision offsets from the lower corner of the
+// set's own box (the leaf AABB), rounded outward so that the box decoded in
+// float32, base + (float)offset, contains every point of the chunk.  A decoded
+// box may only be larger than the exact one, so the scan's test on it never
+// skips a chunk that holds a hit.  Layout: offsets lo x, y, z, hi x, y, z, two
+// unused halves.
+__host__ __device__ __forceinline__ float h2f(uint32_t h) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+// Offset of v >= base: the nearest half, then moved down (up) one half at a
+// time until base + offset <= v (>= v) holds in float32.
+__host__ __device__ inline uint32_t hbox_offset(float base, float v, bool up) {
+    const float d = v - base;
+    uint32_t h = __builtin_bit_cast(uint16_t, (_Float16)d);   // d >= 0: 0 .. 0x7C00 (+inf)
+    if (up) {
+        for (int it = 0; it < 8 && base + h2f(h) < v; ++it) h = h < 0x7C00u ? h + 1u : h;
+        if (base + h2f(h) < v) h = 0x7C00u;
+    } else {
+        for (int it = 0; it < 8 && base + h2f(h) > v; ++it) h = h > 0u ? h - 1u : 0u;
+        if (base + h2f(h) > v) h = 0u;
+    }
+    return h;
+}
+__host__ __device__ inline uint4 hbox_encode(const float base[3], const float lo[3], const float hi[3]) {
+    uint32_t o[6];
+    for (int a = 0; a < 3; ++a) {
+        o[a] = hbox_offset(base[a], lo[a], false);
+        o[3 + a] = hbox_offset(base[a], hi[a], true);
+    }
+    return make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), 0u);
+}
+__device__ __forceinline__ void hbox_decode(uint4 b, float bx, float by, float bz, float lo[3], float hi[3]) {
+    lo[0] = bx + h2f(b.x & 0xFFFFu);
+    lo[1] = by + h2f(b.x >> 16);
+    lo[2] = bz + h2f(b.y & 0xFFFFu);
+    hi[0] = bx + h2f(b.y >> 16);
+    hi[1] = by + h2f(b.z & 0xFFFFu);
+    hi[2] = bz + h2f(b.z >> 16);
+}
 
 // Stored set entries per cloud (with padding) stay below this, so the query
 // kernels address the set arrays with 32-bit byte offsets.
@@ -253,15 +294,11 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
 void free_cloud(CloudHost &c, hipStream_t s);
 capt_status upload_views(capt_forest_s *f, hipStream_t s);
 capt_status ensure_views(capt_forest_s *f, hipStream_t s);   // per-cloud views on the device (batched kernel)
-// Bounding box of every CHUNK-entry chunk of the stored sets (padding skipped).
-// With px == NULL (indexed sets) the coordinates come from pts[pidx].
-capt_status chunk_boxes(const float *px, const float *py, const float *pz, const int32_t *pidx, const float *pts,
-                        int64_t entries, float4 *cbox, hipStream_t s);
 // Bytes of the sets block for `entries` padded entries and its sub-arrays.
 // indexed: no coordinate arrays (px, py, pz come back NULL).
 size_t sets_bytes(size_t entries, bool indexed);
 void sets_layout(void *base, size_t entries, bool indexed, float **px, float **py, float **pz, int32_t **pidx,
-                 float4 **cbox);
+                 uint4 **cbox);
 
 // query.hip
 capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *query_off,

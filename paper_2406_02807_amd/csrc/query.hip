@@ -47,6 +47,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int) {
     return v;
 }
 
+// Inclusive maximum over the 64 lanes with the same DPP pattern (lanes that
+// receive nothing take -1, below every lane index).
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return v;
+}
+
 // Load at a 32-bit byte offset from a wave-uniform base: the address stays a
 // scalar base plus one 32-bit lane offset (no 64-bit per-lane address math).
 // Used for arrays under 4 GiB: T (fewer than 2^30 nodes), the set arrays and
@@ -177,6 +189,10 @@ struct WaveLds {
     float4 sph[WAVE];        // the tile's spheres, w = fl(r*r)
     uint32_t chunk[RING];    // surviving chunk (global chunk index)
     uint8_t owner[RING];     // lane of the sphere it belongs to
+    float4 base[WAVE];       // lower corner of each sphere's set box (chunk boxes are relative to it)
+    int8_t start[WAVE];      // box step: the lane whose pairs start at this slot, or -1
+    uint8_t hitf[WAVE];      // entry round: 1 for a sphere hit in this round
+    uint8_t pad[32];
 };
 static_assert(sizeof(WaveLds) % 16 == 0, "per-wave LDS blocks stay 16-byte aligned");
 
@@ -225,6 +241,9 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
     if (alive) alive = box_sqdist(q.x, q.y, q.z, leaf.lo, leaf.hi) <= r2;
     wave_lds_sync();   // the previous tile's readers of W are done
     W.sph[lane] = make_float4(q.x, q.y, q.z, r2);
+    W.base[lane] = make_float4(leaf.lo[0], leaf.lo[1], leaf.lo[2], 0.0f);
+    W.start[lane] = -1;
+    W.hitf[lane] = 0;
     const int cfg = lane / gg;
     const uint64_t gmask = gg >= WAVE ? ~0ull : ((1ull << gg) - 1);
     bool done = false;
@@ -242,7 +261,7 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
         rem = 0u;
     }
     uint32_t head = 0, tail = (uint32_t)__popcll(dm);     // ring [head, tail), wave-uniform
-    const float4 *__restrict__ CB = C.cbox;
+    const uint4 *__restrict__ CB = C.cbox;
     const float *__restrict__ PX = C.px;
     const int32_t *__restrict__ PI = C.pidx;
     const float *__restrict__ PT = C.pts;
@@ -312,13 +331,15 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
             }
             if (valid) done = done || ((gm >> cfg) & 1u) != 0;
         } else {
-            uint64_t om = 0;   // owners hit by this lane's entries
+            // the spheres hit in this round, flagged in LDS by the lanes that
+            // found the hits, then read back one flag per lane
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (hit[u]) om |= 1ull << own[u];
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1) om |= __shfl_xor(om, d, WAVE);
-            if (valid) done = done || (((om >> (cfg * gg)) & gmask) != 0);
+                if (hit[u]) W.hitf[own[u]] = 1;
+            wave_lds_sync();
+            const uint64_t hm = __ballot(W.hitf[lane] != 0);
+            W.hitf[lane] = 0;
+            if (valid) done = done || (((hm >> (cfg * gg)) & gmask) != 0);
         }
         dead = __ballot(done);
         return true;
@@ -337,22 +358,26 @@ __device__ __forceinline__ bool wave_tile(const CloudDev &C, const float *Tl, in
         const uint32_t base_l = cpos - excl;   // chunk of pair slot t of this lane = base_l + t
         bool rescan = false;
         uint32_t end = 0;
+        int carry = -1;   // the lane whose pairs cover slot k0 (from the previous step)
         for (uint32_t k0 = 0; k0 < total && !rescan; k0 += WAVE) {
             const uint32_t slot = k0 + (uint32_t)lane;
-            int o = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const uint32_t e = __shfl(excl, o + step, WAVE);
-                if (e <= slot) o += step;
-            }
+            // owner of this lane's slot: the last lane whose pairs start at or
+            // before it (lanes mark their first slot in LDS, then a prefix maximum)
+            if (rem > 0u && excl >= k0 && excl - k0 < (uint32_t)WAVE) W.start[excl - k0] = (int8_t)lane;
+            wave_lds_sync();
+            int sv = W.start[lane];
+            W.start[lane] = -1;
+            if (lane == 0) sv = max(sv, carry);
+            const int o = wave_incl_max(sv);
+            carry = __builtin_amdgcn_readlane(o, WAVE - 1);
             const uint32_t ch = __shfl(base_l, o, WAVE) + slot;
             const bool in = slot < total && !((dead >> o) & 1ull);
             const float4 so = W.sph[o];
             bool surv = false;
             if (in) {
-                const float4 a = ld32(CB, 32u * ch);
-                const float4 b = ld32(CB, 32u * ch + 16u);
-                const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+                const float4 bo = W.base[o];
+                float lo[3], hi[3];
+                hbox_decode(ld32(CB, 16u * ch), bo.x, bo.y, bo.z, lo, hi);
                 surv = box_sqdist(so.x, so.y, so.z, lo, hi) <= so.w;
             }
             const uint64_t m = __ballot(surv);
@@ -772,8 +797,8 @@ __global__ void k_chunk_stats(CloudDev C, const float4 *__restrict__ sph, int64_
         const uint32_t c0 = L.start / CHUNK, c1 = c0 + (L.count + CHUNK - 1) / CHUNK;
         for (uint32_t c = c0; c < c1 && !hit; ++c) {
             ++nb;
-            const float4 a = C.cbox[2 * (size_t)c], b = C.cbox[2 * (size_t)c + 1];
-            const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+            float lo[3], hi[3];
+            hbox_decode(C.cbox[c], L.lo[0], L.lo[1], L.lo[2], lo, hi);
             if (box_sqdist(q.x, q.y, q.z, lo, hi) > r2) continue;
             ++nc;
             for (uint32_t e = c * CHUNK; e < (c + 1) * CHUNK && !hit; ++e) {

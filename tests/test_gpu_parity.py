@@ -448,10 +448,34 @@ def _f32_box_sqdist(q, lo, hi):
     return (s[0] + s[1]) + s[2]
 
 
+def _hbox_offset(base, v, up):
+    """The chunk-box offset rule of capt.h: the nearest half of v - base
+    (float32), moved one half at a time until base + offset <= v (>= v)."""
+    base, v = np.float32(base), np.float32(v)
+    h = int(np.float16(np.float32(v - base)).view(np.uint16))
+    val = lambda h: np.float32(base + np.float32(np.uint16(h).view(np.float16)))
+    for _ in range(8):
+        if up and val(h) < v:
+            h = min(h + 1, 0x7C00)
+        elif not up and val(h) > v:
+            h = max(h - 1, 0)
+    if up and val(h) < v:
+        h = 0x7C00
+    if not up and val(h) > v:
+        h = 0
+    return val(h)
+
+
+def _decoded_box(base, lo, hi):
+    return (np.array([_hbox_offset(base[a], lo[a], False) for a in range(3)], np.float32),
+            np.array([_hbox_offset(base[a], hi[a], True) for a in range(3)], np.float32))
+
+
 def test_chunk_stats_match_stored_order_replay(capt):
     """The two-level scan's accounting, replayed on the host from the exported
-    sets in stored order: 16-entry chunks, float32 chunk boxes, early exit at
-    the chunk holding the first hit."""
+    sets in stored order: 16-entry chunks, each chunk's box rounded outward to
+    half-precision offsets from its set's box, early exit at the chunk holding
+    the first hit."""
     pts = synth.tabletop_cloud(8000, 41)
     _say("case: chunk stats")
     f = capt.capt_build(dev(pts), 0.015, 0.08)
@@ -468,7 +492,9 @@ def test_chunk_stats_match_stored_order_replay(capt):
             for c0 in range(0, len(ids), 16):
                 cp = P[ids[c0:c0 + 16]]
                 want_b += 1
-                if _f32_box_sqdist(q, cp.min(0), cp.max(0)) > r2:
+                blo, bhi = _decoded_box(b.aabb[leaf[i], :3], cp.min(0), cp.max(0))
+                assert (blo <= cp.min(0)).all() and (bhi >= cp.max(0)).all()
+                if _f32_box_sqdist(q, blo, bhi) > r2:
                     assert not (_f32_sqdist(q, cp) <= r2).any(), "a skipped chunk holds a hit"
                     continue
                 want_c += 1
