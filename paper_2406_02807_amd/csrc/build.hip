@@ -540,7 +540,30 @@ struct AffArgs {
     int64_t l0, l1;            // leaves that get sets (a shard's subtree); the others stay empty
     double R2;                 // (r_max (1 + 2^-20))^2
     double R;
+    // float32 pre-test: a float32 squared distance at most R2lo is afforded and
+    // one above R2hi is not (its relative error is below 6 * 2^-24, the band
+    // is R2 (1 -+ 2^-21)); only candidates in between take the float64 test.
+    float R2lo, R2hi;
+    int pre32;                 // R2 within [1e-30, 1e30], where that bound holds
 };
+
+// LDS sync of one wave (lanes write what other lanes of the wave read).
+__device__ __forceinline__ void wave_lds_sync_b() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive maximum over the 64 lanes (lanes that receive nothing take -1).
+__device__ __forceinline__ int wave_incl_max_b(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));
+    return v;
+}
 
 // One wavefront per leaf.  COUNT: write the set size.  FILL: write the set
 // (rows in order, points in bin order), its padding, AABB and leaf record.
@@ -550,9 +573,11 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                                                      float *__restrict__ px, float *__restrict__ py,
                                                      float *__restrict__ pz, int32_t *__restrict__ pidx,
                                                      Leaf *__restrict__ leaf, uint4 *__restrict__ cbox) {
+    __shared__ int8_t s_start[256 / WAVE][WAVE];   // per wave: the row whose candidates start at a slot
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (l >= A.N) return;
+    int8_t *S = s_start[threadIdx.x / WAVE];
     const uint32_t out0 = FILL ? pstart[l] : 0u;
     uint32_t cnt = 0;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -580,6 +605,7 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         const Grid g = *A.grid;
         const float *c = A.cells + 6 * l;
         double cl[3], ch[3];
+        const float clf[3] = {c[0], c[1], c[2]}, chf[3] = {c[3], c[4], c[5]};
         int32_t b0[3], b1[3];
         bool empty = false;
         for (int a = 0; a < 3; ++a) {
@@ -621,20 +647,26 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                 const uint32_t excl = incl - rem;
                 const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
                 const uint32_t base_l = s - excl;   // sorted index of list slot t of this row = base_l + t
+                S[lane] = -1;
+                int carry = -1;   // the row whose candidates cover the window's first slot
                 for (uint32_t k0 = 0; k0 < total; k0 += AU * WAVE) {
                     float x[AU], y[AU], z[AU];
                     int32_t id[AU];
                     bool in[AU];
 #pragma unroll
                     for (int u = 0; u < AU; ++u) {
-                        const uint32_t slot = k0 + (uint32_t)(u * WAVE + lane);
+                        const uint32_t w0 = k0 + (uint32_t)(u * WAVE);
+                        const uint32_t slot = w0 + (uint32_t)lane;
                         in[u] = slot < total;
-                        int o = 0;
-#pragma unroll
-                        for (int step = 32; step >= 1; step >>= 1) {
-                            const uint32_t ev = __shfl(excl, o + step, WAVE);
-                            if (ev <= slot) o += step;
-                        }
+                        // the row of this slot: the last row starting at or before it
+                        // (rows mark their first slot in LDS, then a prefix maximum)
+                        if (rem > 0u && excl >= w0 && excl - w0 < (uint32_t)WAVE) S[excl - w0] = (int8_t)lane;
+                        wave_lds_sync_b();
+                        int sv = S[lane];
+                        S[lane] = -1;
+                        if (lane == 0) sv = max(sv, carry);
+                        const int o = wave_incl_max_b(sv);
+                        carry = __builtin_amdgcn_readlane(o, WAVE - 1);
                         const uint32_t k = __shfl(base_l, o, WAVE) + slot;
                         x[u] = y[u] = z[u] = 0.f;
                         id[u] = -1;
@@ -648,7 +680,24 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
 #pragma unroll
                     for (int u = 0; u < AU; ++u) {
                         bool ok = false;
-                        if (in[u]) {
+                        bool open = in[u];
+                        if (open && A.pre32) {
+                            const float pf[3] = {x[u], y[u], z[u]};
+                            float gs[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const float gg = fmaxf(fmaxf(__fsub_rn(clf[a], pf[a]), __fsub_rn(pf[a], chf[a])), 0.0f);
+                                gs[a] = __fmul_rn(gg, gg);
+                            }
+                            const float d2f = __fadd_rn(__fadd_rn(gs[0], gs[1]), gs[2]);
+                            if (d2f <= A.R2lo) {
+                                ok = true;
+                                open = false;
+                            } else if (d2f > A.R2hi) {
+                                open = false;
+                            }
+                        }
+                        if (open) {
                             const double pp[3] = {(double)x[u], (double)y[u], (double)z[u]};
                             double d2 = 0.0;
 #pragma unroll
@@ -1093,6 +1142,16 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     A.l1 = l1;
     A.R = R;
     A.R2 = R * R;
+    {
+        // the float32 pre-test's band, rounded outward to float
+        const double lo = A.R2 * (1.0 - 0x1p-21), hi = A.R2 * (1.0 + 0x1p-21);
+        float flo = (float)lo, fhi = (float)hi;
+        if ((double)flo > lo) flo = std::nextafter(flo, 0.0f);
+        if ((double)fhi < hi) fhi = std::nextafter(fhi, INFINITY);
+        A.R2lo = flo;
+        A.R2hi = fhi;
+        A.pre32 = (A.R2 >= 1e-30 && A.R2 <= 1e30) ? 1 : 0;
+    }
     hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
                        nullptr, nullptr, nullptr, nullptr, nullptr);
     CAPT_LAUNCH_CHECK();
