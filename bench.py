@@ -427,7 +427,11 @@ def bench_tabletop(capt, torch, args):
         return f, fx
 
     f, fx = step()
-    tuned, _ = autotune.autotune(f, sph, G)
+    if args.tune_query:
+        tuned = json.loads(args.tune_query)
+        capt.capt_set_tuning(**tuned)
+    else:
+        tuned, _ = autotune.autotune(f, sph, G)
     f.close()
     for _ in range(3):
         f, fx = step()
@@ -475,7 +479,10 @@ def bench_tabletop(capt, torch, args):
         with torch.cuda.stream(s_query):
             f.release()
 
-    tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
+    if args.tune_query:
+        tuned_step = tuned
+    else:
+        tuned_step, _ = autotune.autotune_step(lambda: piped_frames(6), lambda: out)
     forest = None
     for _ in range(3):
         forest = piped_step(forest)
@@ -772,6 +779,8 @@ def main():
                     help="launch shape of the room query instead of autotuning (e.g. for profiling)")
     ap.add_argument("--query-only", action="store_true",
                     help="only the room's filter, build and timed steps (for profiling)")
+    ap.add_argument("--only-extra", default=None, metavar="NAME", choices=EXTRAS,
+                    help="run one extra alone, without the room headline, and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -802,6 +811,26 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
 
+    if args.only_extra:
+        name = args.only_extra
+        if name in ("tabletop", "clearance", "posed"):
+            tt, tab_pts, _ = bench_tabletop(capt, torch, args)
+            res = tt
+            if name == "clearance":
+                res = bench_clearance(capt, torch, tab_pts)
+            elif name == "posed":
+                f_posed = capt.capt_build(tab_pts, 0.015, 0.08)
+                res = bench_posed(capt, torch, f_posed)
+                f_posed.close()
+        elif name == "batched":
+            res = bench_batched(capt, torch)
+        elif name == "frame":
+            res = bench_frame(capt, torch)
+        else:
+            print("indexed_sets runs only after the room headline", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({name: res}))
+        return
     if args.query_only:
         args.no_extras, args.no_cpu = True, True
     room, f, blob, w, out, room_pts = bench_room(capt, torch, args)

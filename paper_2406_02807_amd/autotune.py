@@ -129,12 +129,14 @@ STEP_SPACE = {
 }
 
 
-def autotune_step(step, answers, space=None, reps=3, rounds=2, verbose=False):
+def autotune_step(step, answers, space=None, reps=5, rounds=2, verbose=False):
     """Coordinate descent over the launch shape for `step()` (any host code
     that runs the workload and returns when it is queued); `answers()` returns
     the tensor of results, which must not change with the shape.  Each
-    candidate's cost is the median wall time of `reps` synchronised runs.
-    Returns (best tuning dict, list of (tuning, ms))."""
+    candidate's cost is the median wall time of `reps` synchronised runs; at
+    the end the winner and the starting shape are timed again with twice the
+    repetitions and the faster one is kept, so one noisy median cannot move
+    the choice.  Returns (best tuning dict, list of (tuning, ms))."""
     import torch
     space = dict(STEP_SPACE if space is None else space)
 
@@ -174,5 +176,13 @@ def autotune_step(step, answers, space=None, reps=3, rounds=2, verbose=False):
                     best, best_ms, improved = cand, ms, True
         if not improved:
             break
+    start = history[0][0]
+    if best != start:
+        reps *= 2
+        t_best, t_start = run(best), run(start)
+        history.append((dict(best), t_best))
+        history.append((dict(start), t_start))
+        if t_start <= t_best:
+            best = start
     capt_set_tuning(**best)
     return best, history

@@ -76,6 +76,8 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
     return p;
 }
 
+bool default_allocator() { return g_alloc.alloc == nullptr; }
+
 void dev_free(void *p, hipStream_t s) {
     if (!p) return;
     if (g_alloc.release) {

@@ -24,6 +24,8 @@
 //     pass writes them with each leaf's AABB and the box of every 16-entry
 //     chunk.
 #include <cmath>
+#include <string>
+#include <thread>
 
 #include "capt_internal.h"
 
@@ -37,6 +39,7 @@ constexpr int LMAX_LOG2 = 10;
 constexpr int LTB = 512;     // threads of the LDS levels kernel (8 waves, so a block fits beside a running query)
 constexpr int AU = 2;        // 64-candidate steps in flight in the affordance kernels
 constexpr int GTILE = 2048;  // tile of the global partition passes
+constexpr int BUILD_STREAMS = 4;   // streams a build of several clouds spreads them over
 
 __device__ __forceinline__ uint32_t ord_key(float v) {
     if (v == 0.0f) v = 0.0f;  // -0 and +0 compare equal
@@ -1224,10 +1227,58 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     f->r_max = r_max;
     f->flags = flags;
     std::vector<CloudWork> work(ncloud);
-    for (int c = 0; c < ncloud; ++c) {
-        const int64_t n = cloud_off[c + 1] - cloud_off[c];
-        capt_status st = build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, shard_bits, shard, s,
-                                      f->clouds[c], work[c]);
+    // Several clouds are built on BUILD_STREAMS streams forked from the
+    // caller's (cloud c on stream c % BUILD_STREAMS), so the many small kernels
+    // of small clouds run side by side instead of one after the other.
+    const int nst = std::max(1, std::min<int>(ncloud, BUILD_STREAMS));
+    std::vector<ForkJoin> fj(nst);
+    std::vector<hipStream_t> ws(nst, s);
+    for (int i = 1; i < nst; ++i) {
+        capt_status st = fj[i].fork(s);
+        if (st) return st;
+        ws[i] = fj[i].side;
+    }
+    // Each stream's clouds are also issued by a host thread of their own (the
+    // launch chains of many small clouds are host-bound), unless the caller's
+    // allocator hooks are installed: those need not be thread-safe.
+    const int nth = default_allocator() ? nst : 1;
+    std::vector<capt_status> th_st(nth, CAPT_OK);
+    std::vector<std::string> th_msg(nth);
+    int dev = 0;
+    CAPT_HIP(hipGetDevice(&dev));
+    auto issue = [&](int t, auto &&per_cloud) {
+        if (t > 0 && hipSetDevice(dev) != hipSuccess) {
+            th_st[t] = CAPT_EHIP;
+            th_msg[t] = "hipSetDevice failed in a build thread";
+            return;
+        }
+        for (int c = t; c < ncloud; c += nth) {
+            const capt_status st = per_cloud(c);
+            if (st) {
+                th_st[t] = st;
+                th_msg[t] = capt_last_error();
+                return;
+            }
+        }
+    };
+    auto in_threads = [&](auto &&per_cloud) -> capt_status {
+        std::vector<std::thread> th;
+        for (int t = 1; t < nth; ++t) th.emplace_back([&, t] { issue(t, per_cloud); });
+        issue(0, per_cloud);
+        for (auto &x : th) x.join();
+        for (int t = 0; t < nth; ++t)
+            if (th_st[t]) {
+                set_error("%s", th_msg[t].c_str());
+                return th_st[t];
+            }
+        return CAPT_OK;
+    };
+    {
+        capt_status st = in_threads([&](int c) {
+            const int64_t n = cloud_off[c + 1] - cloud_off[c];
+            return build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, shard_bits, shard, ws[c % nst],
+                                f->clouds[c], work[c]);
+        });
         if (st) return st;
     }
     // every cloud's totals and error word straight into pinned host memory,
@@ -1239,14 +1290,16 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
     }
     unsigned long long *hw = res.as<unsigned long long>();
     for (int c = 0; c < ncloud; ++c) {
-        hipLaunchKernelGGL(k_publish, dim3(1), dim3(WAVE), 0, s, work[c].totals, work[c].rad, work[c].rad_g,
-                           hw + 5 * c);
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(WAVE), 0, ws[c % nst], work[c].totals, work[c].rad,
+                           work[c].rad_g, hw + 5 * c);
         CAPT_LAUNCH_CHECK();
     }
-    const hipError_t se = hipStreamSynchronize(s);
-    if (se != hipSuccess) {
-        res.p = nullptr;   // the kernels' state is unknown: never hand the block out again
-        return hip_fail(se, "hipStreamSynchronize", __FILE__, __LINE__);
+    for (int i = 0; i < nst; ++i) {
+        const hipError_t se = hipStreamSynchronize(ws[i]);
+        if (se != hipSuccess) {
+            res.p = nullptr;   // the kernels' state is unknown: never hand the block out again
+            return hip_fail(se, "hipStreamSynchronize", __FILE__, __LINE__);
+        }
     }
     std::vector<unsigned long long> tot(4 * (size_t)ncloud);
     std::vector<unsigned long long> sort_err((size_t)ncloud);
@@ -1266,13 +1319,17 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
             return CAPT_EINVAL;
         }
     }
-    int64_t pruned = 0;
-    for (int c = 0; c < ncloud; ++c) {
-        capt_status st = build_phase2(s, f->clouds[c], work[c], &tot[4 * c]);
+    {
+        capt_status st = in_threads([&](int c) { return build_phase2(ws[c % nst], f->clouds[c], work[c], &tot[4 * c]); });
         if (st) return st;
-        pruned += f->clouds[c].pruned;
     }
+    int64_t pruned = 0;
+    for (int c = 0; c < ncloud; ++c) pruned += f->clouds[c].pruned;
     f->pruned_total = pruned;
+    for (int i = 1; i < nst; ++i) {
+        capt_status st = fj[i].join(s);
+        if (st) return st;
+    }
     return CAPT_OK;   // scratch is released stream-ordered; the forest is ready in stream order
 }
 

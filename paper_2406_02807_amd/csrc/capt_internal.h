@@ -132,6 +132,7 @@ constexpr int32_t MAX_GROUP = 1 << 20;
 void set_error(const char *fmt, ...);
 capt_status hip_fail(hipError_t e, const char *what, const char *file, int line);
 void *dev_alloc(size_t bytes, hipStream_t s);
+bool default_allocator();   // no caller hooks installed (the pool is safe to use from several threads)
 void dev_free(void *p, hipStream_t s);
 
 #define CAPT_HIP(call)                                                          \
