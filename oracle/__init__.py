@@ -45,7 +45,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "capt_oracle.c")
-_LIB = os.path.join(_HERE, "libcapt_oracle.so")
+# CAPT_ORACLE_LIB names a prebuilt copy to load instead (the sanitizer test
+# builds one with AddressSanitizer and UBSan); it is never recompiled here.
+_LIB = os.environ.get("CAPT_ORACLE_LIB") or os.path.join(_HERE, "libcapt_oracle.so")
+_PREBUILT = bool(os.environ.get("CAPT_ORACLE_LIB"))
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
           "-fPIC", "-shared", "-Wall", "-Wextra"]
 
@@ -54,6 +57,8 @@ _lib = None
 
 def compile_library(force: bool = True) -> str:
     """Compile the oracle with gcc (contraction off, no fast-math)."""
+    if _PREBUILT:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
@@ -64,7 +69,7 @@ def compile_library(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _PREBUILT and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             compile_library(force=True)
         lib = C.CDLL(_LIB)
         P = C.c_void_p

@@ -17,7 +17,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcapt.so")
+# CAPT_LIBRARY names another build of the library to load (a sanitizer build of
+# the host code, say); by default the in-tree libcapt.so.
+LIB_PATH = os.environ.get("CAPT_LIBRARY") or os.path.join(_HERE, "libcapt.so")
 
 CAPT_OK, CAPT_EINVAL, CAPT_ENOMEM, CAPT_EHIP, CAPT_ERADIUS, CAPT_EPRUNED, CAPT_EUNSUPPORTED = range(7)
 CAPT_NO_PRUNE = 0x1
