@@ -233,6 +233,22 @@ capt_status capt_collides_noalloc(capt_forest f, const float *spheres, const int
                                   int32_t group, uint8_t *out, uint32_t flags, void *stream);
 
 /*
+ * Diagnostic form of capt_collides that checks the batched kernel's work
+ * queue: the same answers, always from one launch of the batched kernel over
+ * all clouds (tiles of configurations popped from one queue; no graph, no
+ * cached plan), which also adds 1 to visits[k] each time it decides
+ * configuration k.  With visits zeroed beforehand every entry reads 1 after
+ * the call: each configuration lies in exactly one tile and each tile is
+ * taken exactly once.
+ *   visits  [M / group] int32 (device), added to with atomics
+ * Other arguments as capt_collides (flags are implied 0).  Synchronises the
+ * stream before it returns.  Forests built with per-depth split axes
+ * (capt_build_axes) give CAPT_EUNSUPPORTED.
+ */
+capt_status capt_collides_visits(capt_forest f, const float *spheres, const int64_t *query_off,
+                                 int32_t group, uint8_t *out, int32_t *visits, void *stream);
+
+/*
  * capt_collides with query padding (Sec. V-B, after the filter lemma): every
  * radius r becomes fl(r + pad) before the test, so that a forest built from a
  * filtered cloud answers conservatively (pad = r_filter per filter pass that

@@ -32,7 +32,7 @@ CAPT_NOALLOC_MAX_CLOUDS = 256
 
 EXPORTS = [
     "capt_filter", "capt_filter_crop", "capt_build", "capt_build_axes", "capt_build_shard", "capt_build_filtered", "capt_collides",
-    "capt_collides_noalloc",
+    "capt_collides_noalloc", "capt_collides_visits",
     "capt_collides_padded", "capt_clearance", "capt_clearance_backward",
     "capt_destroy", "capt_destroy_async", "capt_last_error", "capt_forest_info", "capt_export", "capt_import",
     "capt_set_allocator", "capt_bruteforce_collides", "capt_query_stats", "capt_query_chunk_stats", "capt_set_tuning", "capt_collides_posed",
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "capt_collides_padded": [P, P, P, i32, f32, P, u32, P],
         "capt_collides": [P, P, P, i32, P, u32, P],
         "capt_collides_noalloc": [P, P, P, i32, P, u32, P],
+        "capt_collides_visits": [P, P, P, i32, P, P, P],
         "capt_clearance": [P, P, P, P, P, P],
         "capt_clearance_backward": [P, P, P, P, P, P, P, P],
         "capt_forest_info": [P, i32, P, P, P, P, P],
@@ -305,6 +306,26 @@ def capt_collides_noalloc(forest: Forest, spheres, group: int, out, query_off=No
     _check(lib.capt_collides_noalloc(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
                                      _ptr(out), 0, _stream(stream)))
     return out
+
+
+def capt_collides_visits(forest: Forest, spheres, group: int = 1, query_off=None, stream=None):
+    """The batched kernel's answers and, per configuration, how many times it
+    decided it (int32; 1 everywhere when every tile was taken exactly once).
+    Returns (out uint8 [M / group], visits int32 [M / group])."""
+    import torch
+    lib = load_library()
+    spheres = _dev(spheres, torch.float32, 4, "spheres")
+    M = spheres.shape[0]
+    if query_off is None:
+        if forest.ncloud != 1:
+            raise ValueError("query_off is required for a forest of several clouds")
+        query_off = [0, M]
+    off = _offsets(query_off, forest.ncloud)
+    out = torch.empty((M // group,), dtype=torch.uint8, device=spheres.device)
+    visits = torch.zeros((M // group,), dtype=torch.int32, device=spheres.device)
+    _check(lib.capt_collides_visits(forest.handle, _ptr(spheres), off.ctypes.data_as(C.c_void_p), group,
+                                    _ptr(out), _ptr(visits), _stream(stream)))
+    return out, visits
 
 
 def capt_collides_padded(forest: Forest, spheres, group: int, pad: float, query_off=None, flags: int = 0,

@@ -597,6 +597,20 @@ capt_status capt_collides_noalloc(capt_forest f, const float *spheres, const int
     return collides_noalloc(f, spheres, query_off, group, out, (hipStream_t)stream);
 }
 
+capt_status capt_collides_visits(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
+                                 uint8_t *out, int32_t *visits, void *stream) {
+    ApiGuard g;
+    capt_status st = check_queries(f, spheres, query_off, group);
+    if (st) return st;
+    const int64_t M = query_off[f->clouds.size()];
+    if (M > 0 && (!out || !visits)) {
+        set_error("out or visits is NULL");
+        return CAPT_EINVAL;
+    }
+    if (M == 0) return CAPT_OK;
+    return collides_visits(f, spheres, query_off, group, out, visits, (hipStream_t)stream);
+}
+
 capt_status capt_collides_padded(capt_forest f, const float *spheres, const int64_t *query_off, int32_t group,
                                  float pad, uint8_t *out, uint32_t flags, void *stream) {
     ApiGuard g;

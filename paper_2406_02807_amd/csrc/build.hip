@@ -568,8 +568,75 @@ __device__ __forceinline__ int wave_incl_max_b(int v) {
     return v;
 }
 
-// One wavefront per leaf.  COUNT: write the set size.  FILL: write the set
-// (rows in order, points in bin order), its padding, AABB and leaf record.
+// Minimum / maximum over each row of 16 lanes, in every lane of the row: DPP
+// swaps within quads (quad_perm [1,0,3,2], then [2,3,0,1]), then the
+// half-row mirror (lane i <-> 7 - i of each 8) and the row mirror
+// (i <-> 15 - i), each step fused into the min / max.
+__device__ __forceinline__ float dpp_f(float v, int ctrl) {
+    switch (ctrl) {   // the control must be a constant of the builtin
+        case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));
+        case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false));
+        case 0x141: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false));
+        default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false));
+    }
+}
+__device__ __forceinline__ float row16_min(float v) {
+    v = fminf(v, dpp_f(v, 0xB1));
+    v = fminf(v, dpp_f(v, 0x4E));
+    v = fminf(v, dpp_f(v, 0x141));
+    return fminf(v, dpp_f(v, 0x140));
+}
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_f(v, 0xB1));
+    v = fmaxf(v, dpp_f(v, 0x4E));
+    v = fmaxf(v, dpp_f(v, 0x141));
+    return fmaxf(v, dpp_f(v, 0x140));
+}
+// The same over float keys: ok(f) maps floats (no NaN) to int32 in the same
+// order (-0 below +0), so the row reductions are integer min / max, which
+// fold into one DPP instruction each.
+__device__ __forceinline__ int32_t ok_of(float f) {
+    const int32_t b = __float_as_int(f);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float ok_float(int32_t k) { return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF)); }
+__device__ __forceinline__ int32_t row16_min_i(int32_t v) {
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0xB1, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x4E, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x141, 0xf, 0xf, false));
+    return min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x140, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int32_t row16_max_i(int32_t v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0xB1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x4E, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x141, 0xf, 0xf, false));
+    return max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x140, 0xf, 0xf, false));
+}
+// ... and over the whole wave, uniform: the four row results by readlane.
+__device__ __forceinline__ float wave_min_f(float v) {
+    v = row16_min(v);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fminf(fminf(a, b), fminf(c, d));
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    v = row16_max(v);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+}
+
+// One wavefront per leaf.  COUNT: write the set size and the leaf record's
+// bounding box of the set.  FILL: write the set (rows in order, points in bin
+// order), its padding, the leaf record's start and length, and the box of
+// every 16-entry chunk.  The fill stages the accepted points in a per-wave
+// LDS ring and encodes the chunk boxes from there, four chunks at a time, as
+// they complete (their base, the set's box, is known from the count pass).
+constexpr uint32_t RING = 256;   // staged set entries per wave (> (AU + 1) * WAVE)
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__restrict__ count,
                                                      const uint32_t *__restrict__ pstart,
@@ -577,26 +644,79 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                                                      float *__restrict__ pz, int32_t *__restrict__ pidx,
                                                      Leaf *__restrict__ leaf, uint4 *__restrict__ cbox) {
     __shared__ int8_t s_start[256 / WAVE][WAVE];   // per wave: the row whose candidates start at a slot
+    __shared__ float s_ring[FILL ? 256 / WAVE : 1][3][FILL ? RING : 1];
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (l >= A.N) return;
     int8_t *S = s_start[threadIdx.x / WAVE];
+    float *rx = s_ring[FILL ? threadIdx.x / WAVE : 0][0];
+    float *ry = s_ring[FILL ? threadIdx.x / WAVE : 0][1];
+    float *rz = s_ring[FILL ? threadIdx.x / WAVE : 0][2];
     const uint32_t out0 = FILL ? pstart[l] : 0u;
+    // FILL: the set's box corner, the chunk boxes' base (scalars: a lane picks
+    // one by a lane-dependent choice, which must not become an indexed array)
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    if (FILL) {
+        const Leaf L0 = leaf[l];
+        bx = L0.lo[0];
+        by = L0.lo[1];
+        bz = L0.lo[2];
+    }
     uint32_t cnt = 0;
+    uint32_t done = 0;   // FILL: entries whose chunk boxes are written
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    // chunk boxes of set positions [first, first + 64) from the ring, up to
+    // `end` (later positions, padding, stay out of the boxes)
+    auto boxes = [&](uint32_t first, uint32_t end) {
+        static_assert(CHUNK == 16, "chunk boxes reduce over DPP rows of 16 lanes");
+        wave_lds_sync_b();
+        const uint32_t p = first + (uint32_t)lane;
+        const bool real = p < cnt;
+        const uint32_t q = p & (RING - 1);
+        const float x = real ? rx[q] : 0.f, y = real ? ry[q] : 0.f, z = real ? rz[q] : 0.f;
+        const int32_t kinf = ok_of(INFINITY), kninf = ok_of(-INFINITY);
+        const int32_t lx = row16_min_i(real ? ok_of(x) : kinf), ly = row16_min_i(real ? ok_of(y) : kinf),
+                      lz = row16_min_i(real ? ok_of(z) : kinf);
+        const int32_t hx = row16_max_i(real ? ok_of(x) : kninf), hy = row16_max_i(real ? ok_of(y) : kninf),
+                      hz = row16_max_i(real ? ok_of(z) : kninf);
+        // lanes 0..5 of a chunk's row encode lo x, y, z, hi x, y, z (the
+        // halves of hbox_encode, in its order), lanes 6 and 7 the zero pad
+        const int j = lane & (CHUNK - 1);
+        // (masks, not selects: the compiler turns a chain of lane-dependent
+        // selects into a table in scratch memory)
+        const int32_t m0 = -(int32_t)(j == 0), m1 = -(int32_t)(j == 1), m2 = -(int32_t)(j == 2);
+        const int32_t m3 = -(int32_t)(j == 3), m4 = -(int32_t)(j == 4), m5 = -(int32_t)(j == 5);
+        const int32_t kv = (lx & m0) | (ly & m1) | (lz & m2) | (hx & m3) | (hy & m4) | (hz & m5);
+        const float b = __int_as_float((__float_as_int(bx) & (m0 | m3)) | (__float_as_int(by) & (m1 | m4)) |
+                                       (__float_as_int(bz) & (m2 | m5)));
+        const float v = ok_float(kv);
+        const uint32_t h = j < 6 ? hbox_offset(b, v, j >= 3) : 0u;
+        const uint32_t k = p / CHUNK;   // chunk of the set
+        if (p - (uint32_t)j < end && j < 8)
+            reinterpret_cast<uint16_t *>(cbox + (int64_t)out0 / CHUNK + k)[j] = (uint16_t)h;
+        wave_lds_sync_b();   // the ring slots are free again
+    };
     auto emit = [&](bool ok, float x, float y, float z, int32_t id) {
         const uint64_t m = __ballot(ok);
-        if (FILL && ok) {
-            const uint32_t pos = out0 + cnt + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (px) {   // not for indexed sets
-                const int64_t o = set_off(pos);
-                px[o] = x;
-                py[o] = y;
-                pz[o] = z;
+        if (ok) {
+            if (FILL) {
+                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                const uint32_t pos = out0 + cnt + rank;
+                if (px) {   // not for indexed sets
+                    const int64_t o = set_off(pos);
+                    px[o] = x;
+                    py[o] = y;
+                    pz[o] = z;
+                }
+                pidx[pos] = id;
+                const uint32_t q = (cnt + rank) & (RING - 1);
+                rx[q] = x;
+                ry[q] = y;
+                rz[q] = z;
+            } else {
+                lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+                hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
             }
-            pidx[pos] = id;
-            lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
-            hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
         }
         cnt += (uint32_t)__popcll(m);
     };
@@ -715,20 +835,36 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                         }
                         emit(ok, x[u], y[u], z[u], id[u]);
                     }
+                    if (FILL) {
+                        static_assert(RING > (AU + 1) * WAVE, "the ring holds the pending and the new entries");
+                        while (cnt - done >= (uint32_t)WAVE) {   // four whole chunks are staged
+                            boxes(done, done + WAVE);
+                            done += WAVE;
+                        }
+                    }
                 }
             }
         }
     }
     if (!FILL) {
-        if (lane == 0) count[l] = cnt;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = wave_min_f(lo[a]);
+            hi[a] = wave_max_f(hi[a]);
+        }
+        if (lane == 0) {
+            count[l] = cnt;
+            Leaf L;
+            for (int a = 0; a < 3; ++a) {
+                L.lo[a] = lo[a];
+                L.hi[a] = hi[a];
+            }
+            L.start = 0;
+            L.count = cnt;
+            leaf[l] = L;
+        }
         return;
     }
-    // wave reductions of the AABB, padding, leaf record
-    for (int a = 0; a < 3; ++a)
-        for (int off = WAVE / 2; off >= 1; off >>= 1) {
-            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, WAVE));
-            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, WAVE));
-        }
+    // padding, the chunk boxes still to write, the leaf record's placement
     const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
     for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
         if (px) {
@@ -739,58 +875,10 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
         }
         pidx[out0 + k] = -1;
     }
+    for (uint32_t first = done; first < padded; first += WAVE) boxes(first, padded);
     if (lane == 0) {
-        Leaf L;
-        for (int a = 0; a < 3; ++a) {
-            L.lo[a] = lo[a];
-            L.hi[a] = hi[a];
-        }
-        L.start = out0;
-        L.count = cnt;
-        leaf[l] = L;
-    }
-    // the box of every 16-entry chunk of the set, from the entries this wave
-    // has just written (still in L2): 16 lanes per chunk, padding skipped
-    // (x = +inf in plain sets, index -1 in indexed sets).  The wave's stores
-    // become visible to its own lanes' loads with a workgroup-scope fence (the
-    // CU's vector L1 is shared by the workgroup; an agent-scope fence would
-    // write back the XCD's whole L2).
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const uint32_t nch = padded / CHUNK;
-    for (uint32_t k0 = 0; k0 < nch; k0 += WAVE / CHUNK) {
-        const uint32_t k = k0 + (uint32_t)lane / CHUNK;
-        const int64_t e = (int64_t)out0 + (int64_t)k * CHUNK + (lane & (CHUNK - 1));
-        float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        if (k < nch) {
-            float x = INFINITY, y = 0.f, z = 0.f;
-            if (px) {
-                const int64_t o = set_off(e);
-                x = px[o];
-                y = py[o];
-                z = pz[o];
-            } else {
-                const int32_t id = pidx[e];
-                if (id >= 0) {
-                    x = A.xyz[3 * (int64_t)id];
-                    y = A.xyz[3 * (int64_t)id + 1];
-                    z = A.xyz[3 * (int64_t)id + 2];
-                }
-            }
-            if (x < INFINITY) {
-                blo[0] = bhi[0] = x;
-                blo[1] = bhi[1] = y;
-                blo[2] = bhi[2] = z;
-            }
-        }
-#pragma unroll
-        for (int off = CHUNK / 2; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                blo[a] = fminf(blo[a], __shfl_xor(blo[a], off, WAVE));
-                bhi[a] = fmaxf(bhi[a], __shfl_xor(bhi[a], off, WAVE));
-            }
-        }
-        if (k < nch && (lane & (CHUNK - 1)) == 0) cbox[(int64_t)out0 / CHUNK + k] = hbox_encode(lo, blo, bhi);
+        leaf[l].start = out0;
+        leaf[l].count = cnt;
     }
 }
 
@@ -1156,7 +1244,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         A.pre32 = (A.R2 >= 1e-30 && A.R2 <= 1e30) ? 1 : 0;
     }
     hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, const_cast<Leaf *>(C.dev.leaf), nullptr);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, pad_part);
     CAPT_LAUNCH_CHECK();

@@ -307,6 +307,9 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *quer
 // the same answers with the queue counters in the library's static device array
 capt_status collides_noalloc(capt_forest_s *f, const float *spheres, const int64_t *query_off, int32_t group,
                              uint8_t *out, hipStream_t s);
+// the batched launch with per-configuration decision counts (diagnostic)
+capt_status collides_visits(capt_forest_s *f, const float *spheres, const int64_t *query_off, int32_t group,
+                            uint8_t *out, int32_t *visits, hipStream_t s);
 capt_status collides_posed(capt_forest_s *f, const float *tmpl, int32_t g, const float *poses, const int64_t *pose_off,
                            int32_t edge, uint8_t *out, uint32_t flags, hipStream_t s);
 capt_status query_stats(capt_forest_s *f, const float *spheres, const int64_t *query_off,

@@ -609,7 +609,8 @@ __global__ void k_reset_counter(unsigned int *ctr) {
 // [c0, c1) of one cloud (no LDS tree levels); returns when all are answered.
 template <int U, bool IDX>
 __device__ void slots_over_range(const CloudDev &C, const float *Tl, int L, const float4 *__restrict__ sph, int g,
-                                 int64_t c0, int64_t c1, uint8_t *__restrict__ out, WaveLds &W) {
+                                 int64_t c0, int64_t c1, uint8_t *__restrict__ out, int32_t *__restrict__ visits,
+                                 WaveLds &W) {
     const int lane = lane_id();
     const int j = lane & (SLOT - 1);
     const int lead = lane & ~(SLOT - 1);
@@ -636,7 +637,10 @@ __device__ void slots_over_range(const CloudDev &C, const float *Tl, int L, cons
         hit = __shfl(hit, lead, WAVE);
         if (active) {
             if (hit || s0 + SLOT >= g) {
-                if (j == 0) out[cfg] = (uint8_t)hit;
+                if (j == 0) {
+                    out[cfg] = (uint8_t)hit;
+                    if (visits) atomicAdd(&visits[cfg], 1);
+                }
                 cfg = -1;
             } else {
                 s0 += SLOT;
@@ -652,7 +656,8 @@ constexpr int BATCH_TOP = 9;
 template <int U, bool IDX>
 __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Tile *__restrict__ tiles,
                                   int64_t ntiles, unsigned int *__restrict__ ctr,
-                                  const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out) {
+                                  const float4 *__restrict__ sph, int g, uint8_t *__restrict__ out,
+                                  int32_t *__restrict__ visits) {
     extern __shared__ float4 lds4[];
     WaveLds &W = reinterpret_cast<WaveLds *>(lds4)[threadIdx.x / WAVE];
     // the top BATCH_TOP levels of the current tile's tree, one copy per wave,
@@ -676,7 +681,7 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
             wave_lds_sync();
         }
         if (g > SLOT) {
-            slots_over_range<U, IDX>(C, Tl, L, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, W);
+            slots_over_range<U, IDX>(C, Tl, L, sph, g, tile.cfg0, tile.cfg0 + tile.ncfg, out, visits, W);
         } else {
             const int cpt = WAVE / g;
             for (int c = 0; c < tile.ncfg; c += cpt) {
@@ -684,7 +689,10 @@ __global__ void k_collide_batched(const CloudDev *__restrict__ clouds, const Til
                 const int nc = min(cpt, tile.ncfg - c);
                 const float4 q = lane < nc * g ? sph[c0 * g + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
                 const bool hit = wave_tile<U, IDX, false, false>(C, Tl, L, q, lane < nc * g, g, 2 * g > nc * g, W);
-                if (lane < nc * g && lane % g == 0) out[c0 + lane / g] = (uint8_t)hit;
+                if (lane < nc * g && lane % g == 0) {
+                    out[c0 + lane / g] = (uint8_t)hit;
+                    if (visits) atomicAdd(&visits[c0 + lane / g], 1);
+                }
             }
         }
     }
@@ -843,6 +851,7 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    int32_t *visits = nullptr;   // diagnostic decision counts, or null
 };
 
 void free_plan(BatchPlan *p) {
@@ -1043,15 +1052,15 @@ capt_status enqueue_batched_t(capt_forest_s *f, BatchPlan *p, hipStream_t s) {
         switch (t.scan_unroll) {
             case 4:
                 hipLaunchKernelGGL((k_collide_batched<4, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
-                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out, p->visits);
                 break;
             case 2:
                 hipLaunchKernelGGL((k_collide_batched<2, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
-                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out, p->visits);
                 break;
             default:
                 hipLaunchKernelGGL((k_collide_batched<1, IDX>), dim3((unsigned)blocks), dim3(threads), lds, s, f->d_clouds,
-                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out);
+                                   p->d_tiles, p->ntiles, p->d_ctr, sp, p->group, p->out, p->visits);
                 break;
         }
         CAPT_LAUNCH_CHECK();
@@ -1151,6 +1160,29 @@ capt_status collides(capt_forest_s *f, const float *spheres, const int64_t *qoff
     }
     CAPT_HIP(hipGraphLaunch(p->exec, s));
     return CAPT_OK;
+}
+
+// The batched launch of capt_collides on a plan of its own (no graph, not
+// cached) whose kernel also counts, per configuration, how often it decides it.
+capt_status collides_visits(capt_forest_s *f, const float *spheres, const int64_t *qoff, int32_t g, uint8_t *out,
+                            int32_t *visits, hipStream_t s) {
+    for (const CloudHost &H : f->clouds) {
+        if (!H.dev.cyclic) {
+            set_error("the batched query takes forests with the cyclic split axes only");
+            return CAPT_EUNSUPPORTED;
+        }
+    }
+    capt_status st = ensure_views(f, s);
+    if (st) return st;
+    BatchPlan *p = new BatchPlan();
+    st = make_plan(f, spheres, qoff, g, out, p);
+    if (!st) {
+        p->visits = visits;
+        st = enqueue_batched(f, p, s);
+    }
+    if (!st) CAPT_HIP(hipStreamSynchronize(s));
+    free_plan(p);
+    return st;
 }
 
 // Queue counters of capt_collides_noalloc: one set of NXCD counters (a

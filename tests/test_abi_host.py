@@ -66,6 +66,7 @@ def test_no_gpu_needed_for_validation(lib):
     q = np.array([0, 60], np.int64)
     assert lib.capt_collides(None, P(1), q.ctypes.data_as(P), 60, P(1), 0, None) == capt.CAPT_EINVAL
     assert lib.capt_collides_noalloc(None, P(1), q.ctypes.data_as(P), 60, P(1), 0, None) == capt.CAPT_EINVAL
+    assert lib.capt_collides_visits(None, P(1), q.ctypes.data_as(P), 60, P(1), P(1), None) == capt.CAPT_EINVAL
     assert lib.capt_clearance(None, P(1), q.ctypes.data_as(P), P(1), P(1), None) == capt.CAPT_EINVAL
     # posed queries: bad template size, NULL template, bad edge
     assert lib.capt_collides_posed(None, P(1), 0, P(1), q.ctypes.data_as(P), 1, P(1), 0, None) == capt.CAPT_EINVAL

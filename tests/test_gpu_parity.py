@@ -609,6 +609,39 @@ def test_batched_tiny_and_empty_clouds(capt, orc, group):
     assert want.any() and not want.all()
 
 
+@pytest.mark.parametrize("group", [60, 7, 1])
+def test_batched_queue_decides_every_configuration_once(capt, orc, group):
+    """The batched kernel's tile queue: with per-configuration decision counts,
+    every configuration of every cloud is decided exactly once (no tile
+    skipped, none taken twice, tiles do not overlap), for several tile sizes
+    and launch shapes, on a forest with empty, tiny and deep clouds."""
+    sizes = [0, 1, 5, 3000, 20000, 300, 0, 9000]
+    clouds = [synth.tabletop_cloud(n, 470 + k) if n else np.zeros((0, 3), np.float32)
+              for k, n in enumerate(sizes)]
+    ncfg = [0, 13, 40, 700, 2500, 1, 33, 1200]
+    qs = [synth.uniform_spheres(group * m, synth.WORKSPACE, 0.015, 0.08, 480 + k) for k, m in enumerate(ncfg)]
+    off = np.cumsum([0] + [len(c) for c in clouds]).tolist()
+    qoff = np.cumsum([0] + [len(q) for q in qs]).tolist()
+    f = capt.capt_build(dev(np.concatenate(clouds)), 0.015, 0.08, cloud_off=off)
+    want = np.concatenate([orc.brute_f32(c, q, group) if len(c) else np.zeros(len(q) // group, np.uint8)
+                           for c, q in zip(clouds, qs)])
+    sq = dev(np.concatenate(qs))
+    before = capt.capt_get_tuning()
+    try:
+        for shape in [dict(tile_cfgs=1, waves_per_group=4, groups_per_cu=1), dict(tile_cfgs=16),
+                      dict(tile_cfgs=64, waves_per_group=16, groups_per_cu=4), dict(tile_cfgs=1000)]:
+            capt.capt_set_tuning(**{**before, **shape})
+            _say(f"case: batched queue, group {group}, {shape}")
+            out, visits = capt.capt_collides_visits(f, sq, group, query_off=qoff)
+            v = visits.cpu().numpy()
+            assert v.shape == (sum(ncfg),)
+            assert (v == 1).all(), (shape, np.flatnonzero(v != 1)[:10], v[v != 1][:10])
+            assert np.array_equal(out.cpu().numpy(), want), shape
+    finally:
+        capt.capt_set_tuning(**before)
+    assert want.any() and not want.all()
+
+
 # ---------------------------------------------------------------------------
 # Clearance and its gradient
 # ---------------------------------------------------------------------------
