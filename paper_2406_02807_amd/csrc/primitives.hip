@@ -270,7 +270,10 @@ __global__ void __launch_bounds__(TB) k_os_hist_sum(const uint32_t *__restrict__
 // One digit pass.  Wave w of a tile owns the tile's items [w * 512, (w + 1) *
 // 512) and walks them in eight rounds of 64; a lane's rank among the round's
 // items with its digit comes from ballots, and each wave keeps its own running
-// offset per digit in LDS, so the ranking needs no block barrier.
+// offset per digit in LDS, so the ranking needs no block barrier.  The ranked
+// items are first placed in LDS in the tile's digit order, then written out
+// by consecutive threads, so each digit's run of the tile leaves as one
+// contiguous store sequence instead of scattered single items.
 template <class K>
 __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                    K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t len,
@@ -280,8 +283,11 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     constexpr int R = 256;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t start[R];     // where the tile's run of each digit begins in the segment
+    __shared__ uint32_t tstart[R];    // ... and in the tile's digit order
     __shared__ uint32_t wrun[NW][R];  // per-wave digit counts, then per-wave running offsets
     __shared__ uint32_t lw[NW];
+    __shared__ K skey[TILE];          // the tile in digit order
+    __shared__ uint32_t sval[TILE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
@@ -354,6 +360,8 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     uint32_t tot;
     const uint32_t gex = block_excl_scan(ghist[(size_t)g * R + d], lw, &tot);
     start[d] = gex + excl;
+    uint32_t tcount;
+    tstart[d] = block_excl_scan(c, lw, &tcount);
     // per-wave counts -> offsets of each wave's run inside the tile's run
     uint32_t run = 0;
 #pragma unroll
@@ -368,10 +376,24 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
         if (same[r] == 0ull) continue;   // lane holds no item in this round
         const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
         const uint32_t rank = (uint32_t)__popcll(same[r] & lt_mask);
-        const uint32_t pos = start[dg] + wrun[w][dg] + rank;
-        kout[seg0 + pos] = key[r];
-        vout[seg0 + pos] = val[r];
+        const uint32_t lp = tstart[dg] + wrun[w][dg] + rank;   // place in the tile's digit order
+        skey[lp] = key[r];
+        sval[lp] = val[r];
         if (rank == 0) wrun[w][dg] += (uint32_t)__popcll(same[r]);
+    }
+    __syncthreads();
+    // item i of the tile's digit order goes to its digit's segment start plus
+    // its place in the digit's run of the tile
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t i = (uint32_t)(r * TB) + threadIdx.x;
+        if (i < tcount) {
+            const K k = skey[i];
+            const uint32_t dg = (uint32_t)(k >> shift) & 255u;
+            const uint32_t pos = start[dg] + (i - tstart[dg]);
+            kout[seg0 + pos] = k;
+            vout[seg0 + pos] = sval[i];
+        }
     }
 }
 
