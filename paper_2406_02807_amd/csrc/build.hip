@@ -51,10 +51,6 @@ __device__ __forceinline__ float coord_of(const float *xyz, int64_t n, uint32_t 
     return (int64_t)id < n ? xyz[3 * (int64_t)id + a] : INFINITY;
 }
 
-__global__ void k_fill_u32_b(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
-}
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -65,9 +61,13 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 
 
 // Zero the phase's counters and bins in one launch.
+// Zero regions of a build's scratch: the totals, the two sorts' error words
+// and the rest of their scratch (r1, r2 words after the error words), the bin
+// counts, the scan and level status words.
 __global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__restrict__ errw,
                         uint32_t *__restrict__ errw2, uint32_t *__restrict__ cstart, int64_t ncs,
-                        uint32_t *__restrict__ scan_st, int64_t nss) {
+                        uint32_t *__restrict__ scan_st, int64_t nss, int64_t r1, int64_t r2,
+                        uint32_t *__restrict__ lvl, int64_t nlvl) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 4) totals[t] = 0ull;
@@ -75,6 +75,9 @@ __global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__res
     if (t < 64) errw2[t] = 0u;
     for (int64_t i = t; i < ncs; i += stride) cstart[i] = 0u;
     for (int64_t i = t; i < nss; i += stride) scan_st[i] = 0u;
+    for (int64_t i = t; i < r1; i += stride) errw[64 + i] = 0u;
+    for (int64_t i = t; i < r2; i += stride) errw2[64 + i] = 0u;
+    for (int64_t i = t; i < nlvl; i += stride) lvl[i] = 0u;
 }
 
 // One read of the cloud: sort keys of all three axes (segment a of keys /
@@ -996,7 +999,7 @@ struct CloudWork {
 
 capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, uint32_t flags,
                          const uint8_t *axes, int shard_bits, int shard, hipStream_t s, CloudHost &C,
-                         CloudWork &W) {
+                         CloudWork &W, bool fork_grid) {
     int64_t N = 1;
     int D = 0;
     while (N < n) {
@@ -1103,8 +1106,12 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     float *bbp = reinterpret_cast<float *>(pad_part + 2 * nbN);                          // [nbN][6]
     uint32_t *badp = reinterpret_cast<uint32_t *>(bbp + 6 * nbN);                         // [nbN]
     uint32_t *prp = badp + nbN;                                                           // [nbN]
+    // one clearing launch for the build's scratch: both sorts skip their own
+    const int64_t clr_pre = radix_clear_words(3, N, 32), clr_grid = radix_clear_words(1, n, cell_bits);
+    const int64_t clr_lvl = (N >> 0) > LMAX ? (int64_t)(lvl_words * (size_t)nglob) : 0;
     hipLaunchKernelGGL(k_binit, dim3((unsigned)std::min<int64_t>((cell_cap + TB) / TB + 1, 1024)), dim3(TB), 0, s,
-                       W.totals, rad, rad_g, cstart, cell_cap + 1, W.scan_tmp, (int64_t)(nscan_cs + nscan_ps));
+                       W.totals, rad, rad_g, cstart, cell_cap + 1, W.scan_tmp, (int64_t)(nscan_cs + nscan_ps),
+                       clr_pre, clr_grid, sums, clr_lvl);
     CAPT_LAUNCH_CHECK();
 
     // 1. presort: list a sorted by (coordinate a, id), the three lists in
@@ -1120,14 +1127,19 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     // partials: it runs on a side stream while the splits run on s, and s
     // waits for it before the affordance sets.
     const double R = (double)r_max * (1.0 + 0x1p-20);
+    // (A build of several clouds already runs clouds side by side on several
+    // streams: there the branch stays on s, which saves its fork and join.)
     ForkJoin fj;
-    capt_status fs = fj.fork(s);
-    if (fs) return fs;
-    const hipStream_t sg = fj.side;
+    if (fork_grid) {
+        capt_status fs0 = fj.fork(s);
+        if (fs0) return fs0;
+    }
+    const hipStream_t sg = fork_grid ? fj.side : s;
+    capt_status fs = CAPT_OK;
 
     {
         int where = 0;
-        capt_status st = radix_sort_u32_seg(keys, L[0][0], keys + 3 * wN, L[0][1], 3, N, 32, rad, s, &where);
+        capt_status st = radix_sort_u32_seg(keys, L[0][0], keys + 3 * wN, L[0][1], 3, N, 32, rad, s, &where, true);
         if (st) return st;
         cur[0] = cur[1] = cur[2] = where;
     }
@@ -1144,7 +1156,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
     if (fs) return fs;
     int gwhere = 0;
     if (n > 1) {
-        fs = radix_sort_u32(gkeys, gval, gkeys + wn, gval + wn, n, cell_bits, rad_g, sg, &gwhere);
+        fs = radix_sort_u32(gkeys, gval, gkeys + wn, gval + wn, n, cell_bits, rad_g, sg, &gwhere, true);
         if (fs) return fs;
     }
     const uint32_t *sid = gwhere ? gval + wn : gval;
@@ -1157,11 +1169,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
 
     // 2. splits: global levels while segments exceed LMAX, then LDS levels
     int d = 0;
-    if ((N >> d) > LMAX) {
-        const size_t words = lvl_words * (size_t)nglob;
-        hipLaunchKernelGGL(k_fill_u32_b, dim3((unsigned)std::min<size_t>((words + TB - 1) / TB, 1024)), dim3(TB), 0,
-                           s, sums, (int64_t)words, 0u);
-        CAPT_LAUNCH_CHECK();
+    if ((N >> d) > LMAX) {   // (the level status words were cleared with the rest of the scratch)
         const int a0 = axis_at(ax, 0);
         hipLaunchKernelGGL(k_glevel_split, dim3(nblk(N)), dim3(TB), 0, s, L[a0][cur[a0]], xyz, n, N, 0, a0, T, left);
         CAPT_LAUNCH_CHECK();
@@ -1365,7 +1373,7 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
         capt_status st = in_threads([&](int c) {
             const int64_t n = cloud_off[c + 1] - cloud_off[c];
             return build_phase1(xyz + 3 * cloud_off[c], n, r_min, r_max, flags, axes, shard_bits, shard, ws[c % nst],
-                                f->clouds[c], work[c]);
+                                f->clouds[c], work[c], ncloud == 1);
         });
         if (st) return st;
     }

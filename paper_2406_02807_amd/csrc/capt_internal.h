@@ -246,10 +246,14 @@ capt_status radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v
 size_t radix_tmp_words_seg(int nseg, int64_t len);
 capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int nseg, int64_t len,
                                int bits, uint32_t *tmp, hipStream_t s, int *where);
+// cleared: words tmp[64 .. 64 + radix_clear_words(nseg, len, bits)) are zero
+// already (the caller cleared them in a kernel of its own), so the sort skips
+// its clearing launch.
 capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int nseg, int64_t len,
-                               int bits, uint32_t *tmp, hipStream_t s, int *where);
+                               int bits, uint32_t *tmp, hipStream_t s, int *where, bool cleared = false);
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                           int bits, uint32_t *tmp, hipStream_t s, int *where);
+                           int bits, uint32_t *tmp, hipStream_t s, int *where, bool cleared = false);
+int64_t radix_clear_words(int nseg, int64_t len, int bits);
 
 // ---------------------------------------------------------------------------
 // Forest (api.hip / build.hip)

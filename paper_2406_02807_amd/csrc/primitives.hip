@@ -407,7 +407,7 @@ constexpr int ATOMIC_HIST_BLOCKS = 64;    // blocks of the histogram pass (atomi
 // read it at their next sync.
 template <class K>
 capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64_t len, int bits, uint32_t *tmp,
-                       hipStream_t s, int *where) {
+                       hipStream_t s, int *where, bool cleared = false) {
     *where = 0;
     if (len <= 1 || bits <= 0 || nseg <= 0) return CAPT_OK;
     if (nseg > MAX_SEG || len >= ((int64_t)1 << 30)) {   // 30-bit counts per segment
@@ -422,9 +422,11 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
     uint32_t *ctr = ghist + (size_t)npass * nseg * 256;
     uint32_t *status = ctr + 64;
     const int64_t words = 64 + (int64_t)npass * nseg * 256 + 64 + (int64_t)npass * ntiles * 256;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 1024)), dim3(256), 0, s,
-                       tmp + 64, words - 64, 0u);
-    CAPT_LAUNCH_CHECK();
+    if (!cleared) {
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 1024)), dim3(256), 0, s,
+                           tmp + 64, words - 64, 0u);
+        CAPT_LAUNCH_CHECK();
+    }
     const size_t hl = sizeof(uint32_t) * (size_t)nseg * npass * 256;
     if (ntiles <= 4 * ATOMIC_HIST_BLOCKS) {
         // small inputs: one kernel, block histograms added with atomics
@@ -512,13 +514,20 @@ capt_status radix_sort_u64_seg(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_
 }
 
 capt_status radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                           int bits, uint32_t *tmp, hipStream_t s, int *where) {
-    return radix_sort<uint32_t>(k0, v0, k1, v1, 1, n, bits, tmp, s, where);
+                           int bits, uint32_t *tmp, hipStream_t s, int *where, bool cleared) {
+    return radix_sort<uint32_t>(k0, v0, k1, v1, 1, n, bits, tmp, s, where, cleared);
 }
 
 capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int nseg, int64_t len,
-                               int bits, uint32_t *tmp, hipStream_t s, int *where) {
-    return radix_sort<uint32_t>(k0, v0, k1, v1, nseg, len, bits, tmp, s, where);
+                               int bits, uint32_t *tmp, hipStream_t s, int *where, bool cleared) {
+    return radix_sort<uint32_t>(k0, v0, k1, v1, nseg, len, bits, tmp, s, where, cleared);
+}
+
+int64_t radix_clear_words(int nseg, int64_t len, int bits) {
+    if (len <= 1 || bits <= 0 || nseg <= 0) return 0;
+    const int64_t npass = (bits + 7) / 8;
+    const int64_t ntiles = ((len + TILE - 1) / TILE) * nseg;
+    return npass * nseg * 256 + 64 + npass * ntiles * 256;
 }
 
 }  // namespace capt

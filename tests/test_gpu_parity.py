@@ -642,6 +642,17 @@ def test_batched_queue_decides_every_configuration_once(capt, orc, group):
     assert want.any() and not want.all()
 
 
+def test_batched_queue_visits_rejects_per_depth_axes(capt):
+    """The batched kernel takes cyclic split axes only; the diagnostic entry
+    point says so instead of answering."""
+    pts = synth.tabletop_cloud(2000, 481)
+    f = capt.capt_build(dev(pts), 0.015, 0.08, axes=[0] * 12)
+    sph = dev(synth.uniform_spheres(600, synth.WORKSPACE, 0.015, 0.08, 482))
+    with pytest.raises(capt.CaptError) as e:
+        capt.capt_collides_visits(f, sph, 60)
+    assert e.value.status == capt.CAPT_EUNSUPPORTED
+
+
 # ---------------------------------------------------------------------------
 # Clearance and its gradient
 # ---------------------------------------------------------------------------
