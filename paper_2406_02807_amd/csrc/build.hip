@@ -60,8 +60,7 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 }
 
 
-// Zero the phase's counters and bins in one launch.
-// Zero regions of a build's scratch: the totals, the two sorts' error words
+// Zero regions of a build's scratch in one launch: the totals, the two sorts' error words
 // and the rest of their scratch (r1, r2 words after the error words), the bin
 // counts, the scan and level status words.
 __global__ void k_binit(unsigned long long *__restrict__ totals, uint32_t *__restrict__ errw,
