@@ -183,9 +183,15 @@ __global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState
 // (256, or 1024 for large clouds, where fewer chunks shorten the look-back).
 constexpr int CI = 1;                // positions per thread
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
-// dynamic LDS of the chain kernel: J [CR][CC] u16, Nx [CC] u32, Ex [CC] u32, Cu [CC] u16, mark [CC] i8
+// Positions past the chunk whose point is staged in LDS with the chunk's own:
+// next-pointer searches rarely run further (beyond, they read global memory).
+constexpr int STAGE_EXT = 64;
+// dynamic LDS of the chain kernel: the staged positions' x, y, z (f32) and
+// point id (u32) [CC + STAGE_EXT] each, J [CR][CC] u16, Nx [CC] u32, Ex [CC]
+// u32, Cu [CC] u16, mark [CC] i8, the staged liveness flags [CC + STAGE_EXT] u8
 constexpr size_t chain_lds(int CC) {
-    return sizeof(uint16_t) * ilog2c(CC) * CC + 2 * sizeof(uint32_t) * CC + sizeof(uint16_t) * CC + CC;
+    return 4 * sizeof(uint32_t) * (CC + STAGE_EXT) + sizeof(uint16_t) * ilog2c(CC) * CC + 2 * sizeof(uint32_t) * CC +
+           sizeof(uint16_t) * CC + CC + (CC + STAGE_EXT);
 }
 constexpr uint16_t OUTL = 0xFFFF;    // "leaves the chunk"
 // A next pointer is searched for at most SCAN_BOUND positions ahead; beyond
@@ -271,12 +277,18 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
                                                     uint32_t *__restrict__ err) {
     constexpr int CC = CT * CI;          // chunk length
     constexpr int CR = ilog2c(CC);       // jump tables J_0 .. J_{CR-1}
+    constexpr int SG = CC + STAGE_EXT;   // staged positions
     extern __shared__ uint32_t chain_mem[];
-    auto J = reinterpret_cast<uint16_t(*)[CC]>(chain_mem);
-    uint32_t *Nx = chain_mem + CR * CC / 2;
+    float *Sx = reinterpret_cast<float *>(chain_mem);
+    float *Sy = Sx + SG;
+    float *Sz = Sy + SG;
+    uint32_t *So = reinterpret_cast<uint32_t *>(Sz + SG);
+    auto J = reinterpret_cast<uint16_t(*)[CC]>(So + SG);
+    uint32_t *Nx = So + SG + CR * CC / 2;
     uint32_t *Ex = Nx + CC;
     uint16_t *Cu = reinterpret_cast<uint16_t *>(Ex + CC);
     int8_t *mark = reinterpret_cast<int8_t *>(Cu + CC);
+    uint8_t *Sl = reinterpret_cast<uint8_t *>(mark + CC);
     __shared__ uint32_t s_chunk, s_entry, s_prefix, s_max;
     __shared__ uint32_t lw[CT / WAVE];
     if (threadIdx.x == 0) {
@@ -289,24 +301,41 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     if (cs >= n) return;                      // uniform
     const int64_t ce = min(cs + (int64_t)CC, n);
     const int len = (int)(ce - cs);
+    // 0. stage the point, id and liveness of positions [cs, cs + SG): one
+    //    round of gathers instead of one per search step
+    const int slen = (int)(min(cs + (int64_t)SG, n) - cs);
+    for (int i = threadIdx.x; i < slen; i += CT) {
+        const uint32_t b = ord[cs + i];
+        So[i] = b;
+        Sl[i] = live_in[b];
+        Sx[i] = xyz[3 * (int64_t)b];
+        Sy[i] = xyz[3 * (int64_t)b + 1];
+        Sz[i] = xyz[3 * (int64_t)b + 2];
+    }
+    __syncthreads();
     // 1. next pointers (searched at most SCAN_BOUND positions ahead) and the
     //    first jump table
     for (int i = threadIdx.x; i < CC; i += CT) {
         if (i < len) {
             const int64_t j = cs + i;
-            const uint32_t a = ord[j];
             const int64_t kend = min(n, j + 1 + (int64_t)SCAN_BOUND);
             int64_t k = j + 1;
-            if (live_in[a]) {
-                const float ax = xyz[3 * (int64_t)a], ay = xyz[3 * (int64_t)a + 1], az = xyz[3 * (int64_t)a + 2];
+            if (Sl[i]) {
+                const float ax = Sx[i], ay = Sy[i], az = Sz[i];
                 for (; k < kend; ++k) {
-                    const uint32_t b = ord[k];
-                    if (live_in[b] &&
-                        sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) > rf2)
-                        break;
+                    const int64_t q = k - cs;
+                    if (q < slen) {
+                        if (Sl[q] && sqdist(ax, ay, az, Sx[q], Sy[q], Sz[q]) > rf2) break;
+                    } else {
+                        const uint32_t b = ord[k];
+                        if (live_in[b] &&
+                            sqdist(ax, ay, az, xyz[3 * (int64_t)b], xyz[3 * (int64_t)b + 1], xyz[3 * (int64_t)b + 2]) >
+                                rf2)
+                            break;
+                    }
                 }
             } else {
-                while (k < kend && !live_in[ord[k]]) ++k;
+                while (k < kend && !(k - cs < slen ? Sl[k - cs] : live_in[ord[k]])) ++k;
             }
             const bool unres = k == kend && kend < n;
             Nx[i] = unres ? UNRES : (uint32_t)k;
@@ -428,9 +457,8 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
         const int i = threadIdx.x * CI + u;
         f[u] = 0u;
         if (i < len) {
-            const uint32_t a = ord[cs + i];
-            f[u] = (mark[i] >= 0 && live_in[a]) ? 1u : 0u;
-            live_out[a] = (uint8_t)f[u];
+            f[u] = (mark[i] >= 0 && Sl[i]) ? 1u : 0u;
+            live_out[So[i]] = (uint8_t)f[u];
         }
         cnt += f[u];
     }
@@ -470,7 +498,7 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
 #pragma unroll
     for (int u = 0; u < CI; ++u) {
         const int i = threadIdx.x * CI + u;
-        if (f[u]) out[off++] = ord[cs + i];
+        if (f[u]) out[off++] = So[i];
     }
 }
 

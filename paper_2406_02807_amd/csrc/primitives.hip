@@ -267,8 +267,12 @@ __global__ void __launch_bounds__(TB) k_os_hist_sum(const uint32_t *__restrict__
     ghist[((size_t)p * nseg + g) * 256 + d] = t;
 }
 
-// One digit pass.  Wave w of a tile owns the tile's items [w * 512, (w + 1) *
-// 512) and walks them in eight rounds of 64; a lane's rank among the round's
+// Items per thread of a sort tile (the scatter holds a tile in registers and LDS).
+constexpr int OS_IPT = 16;
+constexpr int OS_TILE = TB * OS_IPT;
+
+// One digit pass.  Wave w of a tile owns the tile's items [w * OS_IPT * 64,
+// (w + 1) * OS_IPT * 64) and walks them in OS_IPT rounds of 64; a lane's rank among the round's
 // items with its digit comes from ballots, and each wave keeps its own running
 // offset per digit in LDS, so the ranking needs no block barrier.  The ranked
 // items are first placed in LDS in the tile's digit order, then written out
@@ -286,8 +290,8 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     __shared__ uint32_t tstart[R];    // ... and in the tile's digit order
     __shared__ uint32_t wrun[NW][R];  // per-wave digit counts, then per-wave running offsets
     __shared__ uint32_t lw[NW];
-    __shared__ K skey[TILE];          // the tile in digit order
-    __shared__ uint32_t sval[TILE];
+    __shared__ K skey[OS_TILE];          // the tile in digit order
+    __shared__ uint32_t sval[OS_TILE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
@@ -299,20 +303,20 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     const int64_t g = (int64_t)t / tps;      // its segment
     const int64_t ts = (int64_t)t - g * tps; // tile within the segment
     const int64_t seg0 = g * len;
-    const int64_t wbase = ts * TILE + (int64_t)w * (IPT * WAVE);   // this wave's first item in the segment
+    const int64_t wbase = ts * OS_TILE + (int64_t)w * (OS_IPT * WAVE);   // this wave's first item in the segment
     // the wave's items stay in registers for the whole pass (one load round)
-    K key[IPT];
-    uint32_t val[IPT];
+    K key[OS_IPT];
+    uint32_t val[OS_IPT];
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+    for (int r = 0; r < OS_IPT; ++r) {
         const int64_t j = wbase + (int64_t)r * WAVE + lane;
         key[r] = j < len ? kin[seg0 + j] : K(0);
         val[r] = j < len ? vin[seg0 + j] : 0u;
     }
     // lanes with the same digit in each round (eight ballots match the digit)
-    uint64_t same[IPT];
+    uint64_t same[OS_IPT];
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+    for (int r = 0; r < OS_IPT; ++r) {
         const bool valid = wbase + (int64_t)r * WAVE + lane < len;
         const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t m = __ballot(valid);
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+    for (int r = 0; r < OS_IPT; ++r) {
         if (same[r] == 0ull) continue;   // lane holds no item in this round
         const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
         const uint32_t rank = (uint32_t)__popcll(same[r] & lt_mask);
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, co
     // item i of the tile's digit order goes to its digit's segment start plus
     // its place in the digit's run of the tile
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+    for (int r = 0; r < OS_IPT; ++r) {
         const uint32_t i = (uint32_t)(r * TB) + threadIdx.x;
         if (i < tcount) {
             const K k = skey[i];
@@ -415,7 +419,7 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
         return CAPT_EUNSUPPORTED;
     }
     const int npass = (bits + 7) / 8;
-    const int64_t tps = (len + TILE - 1) / TILE;
+    const int64_t tps = (len + OS_TILE - 1) / OS_TILE;
     const int64_t ntiles = tps * nseg;
     uint32_t *err = tmp;
     uint32_t *ghist = tmp + 64;
@@ -498,7 +502,7 @@ capt_status scan_exclusive_u32_lb(const uint32_t *in, uint32_t *out, int64_t n, 
 size_t radix_tmp_words(int64_t n) { return radix_tmp_words_seg(1, n); }
 
 size_t radix_tmp_words_seg(int nseg, int64_t len) {
-    const int64_t tps = (len + TILE - 1) / TILE;
+    const int64_t tps = (len + OS_TILE - 1) / OS_TILE;
     return (size_t)(64 + 8 * 256 * (int64_t)nseg + 64 + 8 * tps * nseg * 256 +
                     (int64_t)HIST_BLOCKS * nseg * 8 * 256 + 64);
 }
@@ -526,7 +530,7 @@ capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_
 int64_t radix_clear_words(int nseg, int64_t len, int bits) {
     if (len <= 1 || bits <= 0 || nseg <= 0) return 0;
     const int64_t npass = (bits + 7) / 8;
-    const int64_t ntiles = ((len + TILE - 1) / TILE) * nseg;
+    const int64_t ntiles = ((len + OS_TILE - 1) / OS_TILE) * nseg;
     return npass * nseg * 256 + 64 + npass * ntiles * 256;
 }
 
