@@ -180,7 +180,8 @@ __global__ void k_morton6(const float *__restrict__ xyz, int64_t n, const FState
 }
 
 // The chain kernel takes one position per thread; a chunk is CT positions
-// (256, or 1024 for large clouds, where fewer chunks shorten the look-back).
+// (256, or 512 for large clouds, where fewer chunks shorten the look-back; at
+// 1024 a block's LDS and waves let fewer chunks run at once).
 constexpr int CI = 1;                // positions per thread
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 // Positions past the chunk whose point is staged in LDS with the chunk's own:
@@ -580,8 +581,8 @@ capt_status filter_core(const float *xyz, int64_t n, float r_filter, const uint3
     }
     constexpr int NP = 6;
     const size_t wn = (size_t)n;
-    // chunk length: 256 positions, or 1024 once that would make more than 256 chunks
-    const int CT = (n + 255) / 256 > 256 ? 1024 : 256;
+    // chunk length: 256 positions, or 512 once that would make more than 256 chunks
+    const int CT = (n + 255) / 256 > 256 ? 512 : 256;
     const int64_t nchunk = (n + CT - 1) / CT;
     const int64_t npub = NP * (3 * nchunk + 64);   // per pass: exits, survivor counts, farthest reaches, counter
     size_t off = 0;
@@ -640,8 +641,8 @@ capt_status filter_core(const float *xyz, int64_t n, float r_filter, const uint3
     const uint32_t *ord = where ? v1 : v0;
     for (int p = 0; p < NP; ++p) {
         uint32_t *pp = pub + (size_t)p * (3 * nchunk + 64);
-        if (CT == 1024)
-            hipLaunchKernelGGL(k_filter_chain<1024>, dim3((unsigned)nchunk), dim3(1024), chain_lds(1024), s, xyz,
+        if (CT == 512)
+            hipLaunchKernelGGL(k_filter_chain<512>, dim3((unsigned)nchunk), dim3(512), chain_lds(512), s, xyz,
                                ord + (size_t)p * wn, n, live + (size_t)p * wn, live + (size_t)(p + 1) * wn, st, rf2,
                                (int)(p == NP - 1), pp, pp + nchunk, pp + 2 * nchunk, pp + 3 * nchunk, cur, rad);
         else

@@ -550,10 +550,13 @@ def _coincident_clouds():
     ball = base.copy()                                                    # 80% within 1 mm of a point
     pick = rng.choice(len(ball), 40_000, replace=False)
     ball[pick] = (base[555].astype(np.float64) + rng.uniform(-5e-4, 5e-4, (40_000, 3))).astype(np.float32)
-    return {"one-point-80pct": one, "eight-clusters": many, "ball-1mm-80pct": ball}
+    big = synth.tabletop_cloud(120_000, 810)                               # large enough for 512-position chunks
+    for k in range(8):                                                    # 8 clusters of 12,000 copies
+        big[rng.choice(len(big), 12_000, replace=False)] = big[9000 * k + 11]
+    return {"one-point-80pct": one, "eight-clusters": many, "ball-1mm-80pct": ball, "clusters-120k": big}
 
 
-@pytest.mark.parametrize("name", ["one-point-80pct", "eight-clusters", "ball-1mm-80pct"])
+@pytest.mark.parametrize("name", ["one-point-80pct", "eight-clusters", "ball-1mm-80pct", "clusters-120k"])
 @pytest.mark.parametrize("rf", [0.01, 0.0])
 def test_filter_coincident_runs(capt, orc, name, rf):
     """Long runs of coincident or near-coincident points along the curve (far
