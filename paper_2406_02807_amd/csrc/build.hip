@@ -407,6 +407,7 @@ __global__ void __launch_bounds__(TB) k_cells_prune(const float *__restrict__ T,
 struct Grid {
     double origin[3];
     double g;
+    double inv;             // 1 / g
     double lo[3], hi[3];    // bounding box of the points
     int32_t dims[3];
     int32_t pad;
@@ -484,16 +485,30 @@ __global__ void __launch_bounds__(TB) k_grid_setup(const float *__restrict__ bbp
         step *= 1.25;
     }
     g.g = step;
+    g.inv = 1.0 / step;
     g.pad = 0;
     g.ncells = total;
     *G = g;
 }
 
-__device__ __forceinline__ int32_t bin_of(double v, double origin, double g, int32_t dim) {
-    double t = floor((v - origin) / g);
+__device__ __forceinline__ int32_t bin_clamp(double t, int32_t dim) {
     if (!(t >= 0.0)) t = 0.0;   // also catches NaN (non-finite input is rejected after the build's sync)
     if (t > (double)(dim - 1)) t = (double)(dim - 1);
     return (int32_t)t;
+}
+
+__device__ __forceinline__ int32_t bin_of(double v, double origin, double g, int32_t dim) {
+    return bin_clamp(floor((v - origin) / g), dim);
+}
+
+// Bounds on bin_of from a product with 1 / g: bin_lo(v) <= bin_of(v) <=
+// bin_hi(v).  The product and the quotient differ by a few units in the last
+// place, far inside the 2^-40 margins, and the clamp keeps the order.
+__device__ __forceinline__ int32_t bin_lo(double v, double origin, double inv, int32_t dim) {
+    return bin_clamp(floor((v - origin) * inv * (1.0 - 0x1p-40)), dim);
+}
+__device__ __forceinline__ int32_t bin_hi(double v, double origin, double inv, int32_t dim) {
+    return bin_clamp(floor((v - origin) * inv * (1.0 + 0x1p-40)), dim);
 }
 
 __global__ void k_grid_keys(const float *__restrict__ xyz, int64_t n, const Grid *__restrict__ G,
@@ -632,13 +647,16 @@ __device__ __forceinline__ float wave_max_f(float v) {
     return fmaxf(fmaxf(a, b), fmaxf(c, d));
 }
 
-// One wavefront per leaf.  COUNT: write the set size and the leaf record's
-// bounding box of the set.  FILL: write the set (rows in order, points in bin
-// order), its padding, the leaf record's start and length, and the box of
-// every 16-entry chunk.  The fill stages the accepted points in a per-wave
-// LDS ring and encodes the chunk boxes from there, four chunks at a time, as
-// they complete (their base, the set's box, is known from the count pass).
+// LPW consecutive leaves per wavefront, one after the other; the wave's lanes
+// first set up those leaves side by side (the cell, the bins of its reach).
+// COUNT: write the set size and the leaf record's bounding box of the set.
+// FILL: write the set (rows in order, points in bin order), its padding, the
+// leaf record's start and length, and the box of every 16-entry chunk.  The
+// fill stages the accepted points in a per-wave LDS ring and encodes the chunk
+// boxes from there, four chunks at a time, as they complete (their base, the
+// set's box, is known from the count pass).
 constexpr uint32_t RING = 256;   // staged set entries per wave (> (AU + 1) * WAVE)
+constexpr int LPW = 4;           // leaves per wave (more leave a longer tail of slow waves)
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__restrict__ count,
                                                      const uint32_t *__restrict__ pstart,
@@ -647,120 +665,156 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                                                      Leaf *__restrict__ leaf, uint4 *__restrict__ cbox) {
     __shared__ int8_t s_start[256 / WAVE][WAVE];   // per wave: the row whose candidates start at a slot
     __shared__ float s_ring[FILL ? 256 / WAVE : 1][3][FILL ? RING : 1];
+    static_assert(LPW <= WAVE, "one lane sets up one leaf");
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t l = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (l >= A.N) return;
+    const int64_t lw = ((int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * LPW;   // first leaf
+    if (lw >= A.N) return;
     int8_t *S = s_start[threadIdx.x / WAVE];
     float *rx = s_ring[FILL ? threadIdx.x / WAVE : 0][0];
     float *ry = s_ring[FILL ? threadIdx.x / WAVE : 0][1];
     float *rz = s_ring[FILL ? threadIdx.x / WAVE : 0][2];
-    const uint32_t out0 = FILL ? pstart[l] : 0u;
-    // FILL: the set's box corner, the chunk boxes' base (scalars: a lane picks
-    // one by a lane-dependent choice, which must not become an indexed array)
-    float bx = 0.f, by = 0.f, bz = 0.f;
-    if (FILL) {
-        const Leaf L0 = leaf[l];
-        bx = L0.lo[0];
-        by = L0.lo[1];
-        bz = L0.lo[2];
-    }
-    uint32_t cnt = 0;
-    uint32_t done = 0;   // FILL: entries whose chunk boxes are written
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    // chunk boxes of set positions [first, first + 64) from the ring, up to
-    // `end` (later positions, padding, stay out of the boxes)
-    auto boxes = [&](uint32_t first, uint32_t end) {
-        static_assert(CHUNK == 16, "chunk boxes reduce over DPP rows of 16 lanes");
-        wave_lds_sync_b();
-        const uint32_t p = first + (uint32_t)lane;
-        const bool real = p < cnt;
-        const uint32_t q = p & (RING - 1);
-        const float x = real ? rx[q] : 0.f, y = real ? ry[q] : 0.f, z = real ? rz[q] : 0.f;
-        const int32_t kinf = ok_of(INFINITY), kninf = ok_of(-INFINITY);
-        const int32_t lx = row16_min_i(real ? ok_of(x) : kinf), ly = row16_min_i(real ? ok_of(y) : kinf),
-                      lz = row16_min_i(real ? ok_of(z) : kinf);
-        const int32_t hx = row16_max_i(real ? ok_of(x) : kninf), hy = row16_max_i(real ? ok_of(y) : kninf),
-                      hz = row16_max_i(real ? ok_of(z) : kninf);
-        // lanes 0..5 of a chunk's row encode lo x, y, z, hi x, y, z (the
-        // halves of hbox_encode, in its order), lanes 6 and 7 the zero pad
-        const int j = lane & (CHUNK - 1);
-        // (masks, not selects: the compiler turns a chain of lane-dependent
-        // selects into a table in scratch memory)
-        const int32_t m0 = -(int32_t)(j == 0), m1 = -(int32_t)(j == 1), m2 = -(int32_t)(j == 2);
-        const int32_t m3 = -(int32_t)(j == 3), m4 = -(int32_t)(j == 4), m5 = -(int32_t)(j == 5);
-        const int32_t kv = (lx & m0) | (ly & m1) | (lz & m2) | (hx & m3) | (hy & m4) | (hz & m5);
-        const float b = __int_as_float((__float_as_int(bx) & (m0 | m3)) | (__float_as_int(by) & (m1 | m4)) |
-                                       (__float_as_int(bz) & (m2 | m5)));
-        const float v = ok_float(kv);
-        const uint32_t h = j < 6 ? hbox_offset(b, v, j >= 3) : 0u;
-        const uint32_t k = p / CHUNK;   // chunk of the set
-        if (p - (uint32_t)j < end && j < 8)
-            reinterpret_cast<uint16_t *>(cbox + (int64_t)out0 / CHUNK + k)[j] = (uint16_t)h;
-        wave_lds_sync_b();   // the ring slots are free again
-    };
-    auto emit = [&](bool ok, float x, float y, float z, int32_t id) {
-        const uint64_t m = __ballot(ok);
-        if (ok) {
-            if (FILL) {
-                const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                const uint32_t pos = out0 + cnt + rank;
-                if (px) {   // not for indexed sets
-                    const int64_t o = set_off(pos);
-                    px[o] = x;
-                    py[o] = y;
-                    pz[o] = z;
+    const Grid g = *A.grid;
+    // Set-up, lane i for leaf lw + i: the set the leaf gets (1: its
+    // representative alone, a pruned leaf; 2: the grid gather; 0: none) and,
+    // for the gather, its cell and the bins of its reach on every axis.
+    int kind = 0;
+    int32_t pb0[3] = {0, 0, 0}, pb1[3] = {-1, -1, -1};
+    float pcl[3] = {0.f, 0.f, 0.f}, pch[3] = {0.f, 0.f, 0.f};
+    {
+        const int64_t lm = lw + lane;
+        if (lane < LPW && lm < A.N) {
+            if (A.pruned[lm]) {
+                kind = 1;
+            } else if (A.n > 0 && lm >= A.l0 && lm < A.l1) {
+                const float *c = A.cells + 6 * lm;
+                bool empty = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pcl[a] = c[a];
+                    pch[a] = c[3 + a];
+                    const double cl = (double)pcl[a], ch = (double)pch[a];
+                    // A point that passes the float64 test below lies within R
+                    // of the cell on every axis up to rounding (about 1e-16
+                    // relative); the slack covers that, and bin_of is
+                    // monotone, so the bins from bin_of(lo_b) to bin_of(hi_b)
+                    // hold every such point.  The range taken, bin_lo(lo_b) to
+                    // bin_hi(hi_b), may add a bin on a side: its points lie
+                    // outside [lo_b, hi_b] on that axis, fail the test and
+                    // leave the set and its order as they are.
+                    const double slack =
+                        1e-9 * (A.R + 1.0 + (isfinite(cl) ? fabs(cl) : 0.0) + (isfinite(ch) ? fabs(ch) : 0.0));
+                    const double lo_b = fmax(cl - A.R - slack, g.lo[a]);
+                    const double hi_b = fmin(ch + A.R + slack, g.hi[a]);
+                    if (!(lo_b <= hi_b)) {
+                        empty = true;
+                    } else {
+                        pb0[a] = bin_lo(lo_b, g.origin[a], g.inv, g.dims[a]);
+                        pb1[a] = bin_hi(hi_b, g.origin[a], g.inv, g.dims[a]);
+                    }
                 }
-                pidx[pos] = id;
-                const uint32_t q = (cnt + rank) & (RING - 1);
-                rx[q] = x;
-                ry[q] = y;
-                rz[q] = z;
-            } else {
-                lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
-                hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+                if (!empty) kind = 2;
             }
         }
-        cnt += (uint32_t)__popcll(m);
-    };
-    const int64_t rid = A.rep[l];
-    if (A.pruned[l]) {
-        const float x = A.xyz[3 * rid], y = A.xyz[3 * rid + 1], z = A.xyz[3 * rid + 2];
-        emit(lane == 0, x, y, z, (int32_t)rid);
-    } else if (A.n > 0 && l >= A.l0 && l < A.l1) {
-        const Grid g = *A.grid;
-        const float *c = A.cells + 6 * l;
-        double cl[3], ch[3];
-        const float clf[3] = {c[0], c[1], c[2]}, chf[3] = {c[3], c[4], c[5]};
-        int32_t b0[3], b1[3];
-        bool empty = false;
-        for (int a = 0; a < 3; ++a) {
-            cl[a] = (double)c[a];
-            ch[a] = (double)c[3 + a];
-            // A point that passes the float64 test below lies within R of the
-            // cell on every axis up to rounding (about 1e-16 relative); the
-            // slack covers that, and bin_of is monotone, so the bins from
-            // bin_of(lo_b) to bin_of(hi_b) hold every such point.
-            const double slack =
-                1e-9 * (A.R + 1.0 + (isfinite(cl[a]) ? fabs(cl[a]) : 0.0) + (isfinite(ch[a]) ? fabs(ch[a]) : 0.0));
-            const double lo_b = fmax(cl[a] - A.R - slack, g.lo[a]);
-            const double hi_b = fmin(ch[a] + A.R + slack, g.hi[a]);
-            if (!(lo_b <= hi_b)) {
-                empty = true;
-                b0[a] = 0;
-                b1[a] = -1;
-                continue;
-            }
-            b0[a] = bin_of(lo_b, g.origin[a], g.g, g.dims[a]);
-            b1[a] = bin_of(hi_b, g.origin[a], g.g, g.dims[a]);
+    }
+    for (int li = 0; li < LPW; ++li) {
+        const int64_t l = lw + li;
+        if (l >= A.N) break;
+        const uint32_t out0 = FILL ? pstart[l] : 0u;
+        // FILL: the set's box corner, the chunk boxes' base (scalars: a lane picks
+        // one by a lane-dependent choice, which must not become an indexed array)
+        float bx = 0.f, by = 0.f, bz = 0.f;
+        if (FILL) {
+            const Leaf L0 = leaf[l];
+            bx = L0.lo[0];
+            by = L0.lo[1];
+            bz = L0.lo[2];
         }
-        if (!empty) {
-            const int64_t ny = b1[1] - b0[1] + 1;
-            const int64_t nrows = ny * (int64_t)(b1[2] - b0[2] + 1);
+        uint32_t cnt = 0;
+        uint32_t done = 0;   // FILL: entries whose chunk boxes are written
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        // chunk boxes of set positions [first, first + 64) from the ring, up to
+        // `end` (later positions, padding, stay out of the boxes)
+        auto boxes = [&](uint32_t first, uint32_t end) {
+            static_assert(CHUNK == 16, "chunk boxes reduce over DPP rows of 16 lanes");
+            wave_lds_sync_b();
+            const uint32_t p = first + (uint32_t)lane;
+            const bool real = p < cnt;
+            const uint32_t q = p & (RING - 1);
+            const float x = real ? rx[q] : 0.f, y = real ? ry[q] : 0.f, z = real ? rz[q] : 0.f;
+            const int32_t kinf = ok_of(INFINITY), kninf = ok_of(-INFINITY);
+            const int32_t lx = row16_min_i(real ? ok_of(x) : kinf), ly = row16_min_i(real ? ok_of(y) : kinf),
+                          lz = row16_min_i(real ? ok_of(z) : kinf);
+            const int32_t hx = row16_max_i(real ? ok_of(x) : kninf), hy = row16_max_i(real ? ok_of(y) : kninf),
+                          hz = row16_max_i(real ? ok_of(z) : kninf);
+            // lanes 0..5 of a chunk's row encode lo x, y, z, hi x, y, z (the
+            // halves of hbox_encode, in its order), lanes 6 and 7 the zero pad
+            const int j = lane & (CHUNK - 1);
+            // (masks, not selects: the compiler turns a chain of lane-dependent
+            // selects into a table in scratch memory)
+            const int32_t m0 = -(int32_t)(j == 0), m1 = -(int32_t)(j == 1), m2 = -(int32_t)(j == 2);
+            const int32_t m3 = -(int32_t)(j == 3), m4 = -(int32_t)(j == 4), m5 = -(int32_t)(j == 5);
+            const int32_t kv = (lx & m0) | (ly & m1) | (lz & m2) | (hx & m3) | (hy & m4) | (hz & m5);
+            const float b = __int_as_float((__float_as_int(bx) & (m0 | m3)) | (__float_as_int(by) & (m1 | m4)) |
+                                           (__float_as_int(bz) & (m2 | m5)));
+            const float v = ok_float(kv);
+            const uint32_t h = j < 6 ? hbox_offset(b, v, j >= 3) : 0u;
+            const uint32_t k = p / CHUNK;   // chunk of the set
+            if (p - (uint32_t)j < end && j < 8)
+                reinterpret_cast<uint16_t *>(cbox + (int64_t)out0 / CHUNK + k)[j] = (uint16_t)h;
+            wave_lds_sync_b();   // the ring slots are free again
+        };
+        auto emit = [&](bool ok, float x, float y, float z, int32_t id) {
+            const uint64_t m = __ballot(ok);
+            if (ok) {
+                if (FILL) {
+                    const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                    const uint32_t pos = out0 + cnt + rank;
+                    if (px) {   // not for indexed sets
+                        const int64_t o = set_off(pos);
+                        px[o] = x;
+                        py[o] = y;
+                        pz[o] = z;
+                    }
+                    pidx[pos] = id;
+                    const uint32_t q = (cnt + rank) & (RING - 1);
+                    rx[q] = x;
+                    ry[q] = y;
+                    rz[q] = z;
+                } else {
+                    lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+                    hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+                }
+            }
+            cnt += (uint32_t)__popcll(m);
+        };
+        const int kd = __builtin_amdgcn_readlane(kind, li);
+        if (kd == 1) {
+            const int64_t rid = A.rep[l];
+            const float x = A.xyz[3 * rid], y = A.xyz[3 * rid + 1], z = A.xyz[3 * rid + 2];
+            emit(lane == 0, x, y, z, (int32_t)rid);
+        } else if (kd == 2) {
+            double cl[3], ch[3];
+            float clf[3], chf[3];
+            int32_t b0[3], b1[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                clf[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pcl[a]), li));
+                chf[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pch[a]), li));
+                cl[a] = (double)clf[a];
+                ch[a] = (double)chf[a];
+                b0[a] = __builtin_amdgcn_readlane(pb0[a], li);
+                b1[a] = __builtin_amdgcn_readlane(pb1[a], li);
+            }
+            // (rows number at most the grid's cells, fewer than 2^32: the
+            // row's place splits into y and z in 32-bit arithmetic)
+            const uint32_t ny = (uint32_t)(b1[1] - b0[1] + 1);
+            const int64_t nrows = (int64_t)ny * (int64_t)(b1[2] - b0[2] + 1);
             for (int64_t r0 = 0; r0 < nrows; r0 += WAVE) {
                 const int64_t r = r0 + lane;
                 uint32_t s = 0, e = 0;
                 if (r < nrows) {
-                    const int64_t y = b0[1] + r % ny, z = b0[2] + r / ny;
+                    const uint32_t zr = (uint32_t)r / ny;
+                    const int64_t y = b0[1] + (int64_t)((uint32_t)r - zr * ny), z = b0[2] + (int64_t)zr;
                     const int64_t row = (z * g.dims[1] + y) * g.dims[0];
                     s = A.cstart[row + b0[0]];
                     e = A.cstart[row + b1[0] + 1];
@@ -811,7 +865,8 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                             float gs[3];
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
-                                const float gg = fmaxf(fmaxf(__fsub_rn(clf[a], pf[a]), __fsub_rn(pf[a], chf[a])), 0.0f);
+                                const float gg =
+                                    fmaxf(fmaxf(__fsub_rn(clf[a], pf[a]), __fsub_rn(pf[a], chf[a])), 0.0f);
                                 gs[a] = __fmul_rn(gg, gg);
                             }
                             const float d2f = __fadd_rn(__fadd_rn(gs[0], gs[1]), gs[2]);
@@ -847,40 +902,40 @@ __global__ void __launch_bounds__(256) k_afford_grid(AffArgs A, uint32_t *__rest
                 }
             }
         }
-    }
-    if (!FILL) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = wave_min_f(lo[a]);
-            hi[a] = wave_max_f(hi[a]);
-        }
-        if (lane == 0) {
-            count[l] = cnt;
-            Leaf L;
+        if (!FILL) {
             for (int a = 0; a < 3; ++a) {
-                L.lo[a] = lo[a];
-                L.hi[a] = hi[a];
+                lo[a] = wave_min_f(lo[a]);
+                hi[a] = wave_max_f(hi[a]);
             }
-            L.start = 0;
-            L.count = cnt;
-            leaf[l] = L;
+            if (lane == 0) {
+                count[l] = cnt;
+                Leaf L;
+                for (int a = 0; a < 3; ++a) {
+                    L.lo[a] = lo[a];
+                    L.hi[a] = hi[a];
+                }
+                L.start = 0;
+                L.count = cnt;
+                leaf[l] = L;
+            }
+            continue;
         }
-        return;
-    }
-    // padding, the chunk boxes still to write, the leaf record's placement
-    const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
-    for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
-        if (px) {
-            const int64_t o = set_off(out0 + k);
-            px[o] = INFINITY;
-            py[o] = INFINITY;
-            pz[o] = INFINITY;
+        // padding, the chunk boxes still to write, the leaf record's placement
+        const uint32_t padded = cnt ? ((cnt + SET_ALIGN - 1) / SET_ALIGN) * SET_ALIGN : 0u;
+        for (uint32_t k = cnt + lane; k < padded; k += WAVE) {
+            if (px) {
+                const int64_t o = set_off(out0 + k);
+                px[o] = INFINITY;
+                py[o] = INFINITY;
+                pz[o] = INFINITY;
+            }
+            pidx[out0 + k] = -1;
         }
-        pidx[out0 + k] = -1;
-    }
-    for (uint32_t first = done; first < padded; first += WAVE) boxes(first, padded);
-    if (lane == 0) {
-        leaf[l].start = out0;
-        leaf[l].count = cnt;
+        for (uint32_t first = done; first < padded; first += WAVE) boxes(first, padded);
+        if (lane == 0) {
+            leaf[l].start = out0;
+            leaf[l].count = cnt;
+        }
     }
 }
 
@@ -1250,7 +1305,7 @@ capt_status build_phase1(const float *xyz, int64_t n, float r_min, float r_max, 
         A.R2hi = fhi;
         A.pre32 = (A.R2 >= 1e-30 && A.R2 <= 1e30) ? 1 : 0;
     }
-    hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
+    hipLaunchKernelGGL((k_afford_grid<false>), dim3(nblk(N, 4 * LPW)), dim3(256), 0, s, A, W.count, nullptr, nullptr,
                        nullptr, nullptr, nullptr, const_cast<Leaf *>(C.dev.leaf), nullptr);
     CAPT_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pad_counts, dim3(nblk(N)), dim3(TB), 0, s, W.count, N, W.pstart, pad_part);
@@ -1286,7 +1341,7 @@ capt_status build_phase2(hipStream_t s, CloudHost &C, CloudWork &W, const unsign
     C.dev.pz = pz;
     C.dev.pidx = pidx;
     C.dev.cbox = cbox;
-    hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
+    hipLaunchKernelGGL((k_afford_grid<true>), dim3(nblk(C.N, 4 * LPW)), dim3(256), 0, s, W.args, nullptr, W.pstart, px,
                        py, pz, pidx, const_cast<Leaf *>(C.dev.leaf), cbox);
     CAPT_LAUNCH_CHECK();
     return CAPT_OK;
