@@ -29,6 +29,7 @@
 #include <cmath>
 
 #include "capt_internal.h"
+#include "lookback.h"
 
 namespace capt {
 
@@ -467,32 +468,19 @@ __global__ void __launch_bounds__(CT) k_filter_chain(const float *__restrict__ x
     uint32_t kept;
     uint32_t off = block_excl_scan_c<CT>(cnt, lw, &kept);
     // 6. offset of the chunk's survivors: look back over earlier chunks
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < WAVE) {   // the first wavefront publishes and looks back
         uint32_t excl = 0;
         if (c == 0) {
-            st_agent(&kept_st[0], 0x80000000u | kept);
+            if (threadIdx.x == 0) st_agent(&kept_st[0], 0x80000000u | kept);
         } else {
-            st_agent(&kept_st[c], 0x40000000u | kept);
-            int64_t q = c - 1;
-            uint32_t spins = 0;
-            while (q >= 0) {
-                const uint32_t v = ld_agent(&kept_st[q]);
-                const uint32_t flag = v & 0xC0000000u;
-                if (flag == 0) {
-                    if (++spins > SPIN_LIMIT) {
-                        atomicOr(err, 4u);
-                        break;
-                    }
-                    continue;
-                }
-                excl += v & 0x3FFFFFFFu;
-                if (flag == 0x80000000u) break;
-                --q;
-            }
-            st_agent(&kept_st[c], 0x80000000u | (excl + kept));
+            if (threadIdx.x == 0) st_agent(&kept_st[c], 0x40000000u | kept);
+            excl = wave_lookback(kept_st, c, SPIN_LIMIT, err, 4u);
+            if (threadIdx.x == 0) st_agent(&kept_st[c], 0x80000000u | (excl + kept));
         }
-        s_prefix = excl;
-        if (ce == n) st->mm[0] = (int64_t)(excl + kept);
+        if (threadIdx.x == 0) {
+            s_prefix = excl;
+            if (ce == n) st->mm[0] = (int64_t)(excl + kept);
+        }
     }
     __syncthreads();
     off += s_prefix;

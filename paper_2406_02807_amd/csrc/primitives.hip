@@ -7,6 +7,7 @@
 // equal digits inside a tile comes from wave ballots (eight ballots match the
 // digit across the 64 lanes) and per-wave running offsets in LDS.
 #include "capt_internal.h"
+#include "lookback.h"
 
 namespace capt {
 
@@ -176,31 +177,16 @@ __global__ void __launch_bounds__(TB) k_scan_lb(const uint32_t *__restrict__ in,
     }
     uint32_t tot;
     uint32_t off = block_excl_scan(sum, lw, &tot);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < WAVE) {   // the first wavefront publishes and looks back
         uint32_t ex = 0;
         if (t == 0) {
-            store_agent(&status[0], ST_PRE | tot);
+            if (threadIdx.x == 0) store_agent(&status[0], ST_PRE | tot);
         } else {
-            store_agent(&status[t], ST_AGG | tot);
-            int64_t q = t - 1;
-            uint32_t spins = 0;
-            while (true) {
-                const uint32_t w = load_agent(&status[q]);
-                const uint32_t flag = w & ~ST_VAL;
-                if (flag == 0) {
-                    if (++spins > LOOKBACK_SPINS) {
-                        atomicOr(err, 16u);
-                        break;
-                    }
-                    continue;
-                }
-                ex += w & ST_VAL;
-                if (flag == ST_PRE) break;
-                --q;
-            }
-            store_agent(&status[t], ST_PRE | (ex + tot));
+            if (threadIdx.x == 0) store_agent(&status[t], ST_AGG | tot);
+            ex = wave_lookback(status, t, LOOKBACK_SPINS, err, 16u);
+            if (threadIdx.x == 0) store_agent(&status[t], ST_PRE | (ex + tot));
         }
-        s_excl = ex;
+        if (threadIdx.x == 0) s_excl = ex;
     }
     __syncthreads();
     off += s_excl;
