@@ -253,9 +253,11 @@ __global__ void __launch_bounds__(TB) k_os_hist_sum(const uint32_t *__restrict__
     ghist[((size_t)p * nseg + g) * 256 + d] = t;
 }
 
-// Items per thread of a sort tile (the scatter holds a tile in registers and LDS).
-constexpr int OS_IPT = 16;
-constexpr int OS_TILE = TB * OS_IPT;
+// Items per thread of a sort tile (the scatter holds a tile in registers and
+// LDS): 16 for sorts of at least OS_BIG items, where the passes are short of
+// neither tiles nor waves, else 8 (more, shorter tiles run at once).
+constexpr int64_t OS_BIG = (int64_t)1 << 20;
+inline int os_ipt(int nseg, int64_t len) { return (int64_t)nseg * len >= OS_BIG ? 16 : 8; }
 
 // One digit pass.  Wave w of a tile owns the tile's items [w * OS_IPT * 64,
 // (w + 1) * OS_IPT * 64) and walks them in OS_IPT rounds of 64; a lane's rank among the round's
@@ -264,13 +266,14 @@ constexpr int OS_TILE = TB * OS_IPT;
 // items are first placed in LDS in the tile's digit order, then written out
 // by consecutive threads, so each digit's run of the tile leaves as one
 // contiguous store sequence instead of scattered single items.
-template <class K>
+template <class K, int OS_IPT>
 __global__ void __launch_bounds__(TB) k_os_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                    K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t len,
                                                    int64_t tps, int shift, const uint32_t *__restrict__ ghist,
                                                    uint32_t *__restrict__ status, uint32_t *__restrict__ tile_ctr,
                                                    uint32_t *__restrict__ err) {
     constexpr int R = 256;
+    constexpr int OS_TILE = TB * OS_IPT;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t start[R];     // where the tile's run of each digit begins in the segment
     __shared__ uint32_t tstart[R];    // ... and in the tile's digit order
@@ -405,7 +408,9 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
         return CAPT_EUNSUPPORTED;
     }
     const int npass = (bits + 7) / 8;
-    const int64_t tps = (len + OS_TILE - 1) / OS_TILE;
+    const int ipt = os_ipt(nseg, len);
+    const int64_t tile = (int64_t)TB * ipt;
+    const int64_t tps = (len + tile - 1) / tile;
     const int64_t ntiles = tps * nseg;
     uint32_t *err = tmp;
     uint32_t *ghist = tmp + 64;
@@ -438,8 +443,12 @@ capt_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int nseg, int64
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int p = 0; p < npass; ++p) {
-        hipLaunchKernelGGL(k_os_scatter<K>, dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, len, tps, 8 * p,
-                           ghist + (size_t)p * nseg * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
+        if (ipt == 16)
+            hipLaunchKernelGGL((k_os_scatter<K, 16>), dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, len, tps,
+                               8 * p, ghist + (size_t)p * nseg * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
+        else
+            hipLaunchKernelGGL((k_os_scatter<K, 8>), dim3((unsigned)ntiles), dim3(TB), 0, s, ki, vi, ko, vo, len, tps,
+                               8 * p, ghist + (size_t)p * nseg * 256, status + (size_t)p * ntiles * 256, ctr + p, err);
         CAPT_LAUNCH_CHECK();
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
@@ -488,7 +497,8 @@ capt_status scan_exclusive_u32_lb(const uint32_t *in, uint32_t *out, int64_t n, 
 size_t radix_tmp_words(int64_t n) { return radix_tmp_words_seg(1, n); }
 
 size_t radix_tmp_words_seg(int nseg, int64_t len) {
-    const int64_t tps = (len + OS_TILE - 1) / OS_TILE;
+    const int64_t tile = (int64_t)TB * os_ipt(nseg, len);
+    const int64_t tps = (len + tile - 1) / tile;
     return (size_t)(64 + 8 * 256 * (int64_t)nseg + 64 + 8 * tps * nseg * 256 +
                     (int64_t)HIST_BLOCKS * nseg * 8 * 256 + 64);
 }
@@ -516,7 +526,8 @@ capt_status radix_sort_u32_seg(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_
 int64_t radix_clear_words(int nseg, int64_t len, int bits) {
     if (len <= 1 || bits <= 0 || nseg <= 0) return 0;
     const int64_t npass = (bits + 7) / 8;
-    const int64_t ntiles = ((len + OS_TILE - 1) / OS_TILE) * nseg;
+    const int64_t tile = (int64_t)TB * os_ipt(nseg, len);
+    const int64_t ntiles = ((len + tile - 1) / tile) * nseg;
     return npass * nseg * 256 + 64 + npass * ntiles * 256;
 }
 
