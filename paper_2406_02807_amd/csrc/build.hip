@@ -16,8 +16,8 @@
 //  3. leaf cells from the split values of each leaf's ancestors;
 //  4. affordance sets: instead of carrying z down the recursion, each leaf
 //     collects {p : dist(p, cell) <= R} directly from a uniform grid of the
-//     points (bins of side R / 2, points sorted by bin), scanning the exact
-//     bin range around its cell.  Both constructions give the same set
+//     points (bins of side R / 2, points sorted by bin), scanning the bin
+//     range around its cell.  Both constructions give the same set
 //     (Lemma 1, case 1); the float64 distance test is monotone under cell
 //     shrinking, so they agree exactly.  A count pass sizes the sets, a scan
 //     places them (each set starts at a multiple of SET_ALIGN entries), a fill
