@@ -1388,10 +1388,12 @@ capt_status build_forest(const float *xyz, const int64_t *cloud_off, int32_t ncl
         if (st) return st;
         ws[i] = fj[i].side;
     }
-    // Each stream's clouds are also issued by a host thread of their own (the
-    // launch chains of many small clouds are host-bound), unless the caller's
-    // allocator hooks are installed: those need not be thread-safe.
-    const int nth = default_allocator() ? nst : 1;
+    // The clouds are issued by two host threads (cloud c by thread c % 2; the
+    // launch chains of many small clouds are host-bound, and the runtime
+    // serialises launches across threads, so more threads only contend),
+    // unless the caller's allocator hooks are installed: those need not be
+    // thread-safe.
+    const int nth = default_allocator() ? std::min(nst, 2) : 1;
     std::vector<capt_status> th_st(nth, CAPT_OK);
     std::vector<std::string> th_msg(nth);
     int dev = 0;
