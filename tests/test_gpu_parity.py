@@ -536,6 +536,18 @@ def test_filter_matches_oracle(capt, orc, name, rf):
     assert np.array_equal(bits(out.cpu().numpy()), bits(pts[kept]))
 
 
+@pytest.mark.parametrize("n", [174_762, 174_763])
+def test_filter_sort_tile_boundary(capt, orc, n):
+    """The filter's six-key sort switches from 2,048- to 4,096-key tiles at
+    2^20 keys (6 n = 1,048,572 and 1,048,578): both sides against the oracle."""
+    pts = synth.room_cloud(n - n // 10, n // 10, 5003)
+    _say(f"case: filter of {n} room points at the sort's tile boundary")
+    kept, _ = orc.filter(pts, 0.005)
+    out, idx = capt.capt_filter(dev(pts), 0.005)
+    assert np.array_equal(idx.cpu().numpy(), kept)
+    assert np.array_equal(bits(out.cpu().numpy()), bits(pts[kept]))
+
+
 # ---------------------------------------------------------------------------
 # Batched ragged forests
 # ---------------------------------------------------------------------------
